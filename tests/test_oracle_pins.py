@@ -1,0 +1,323 @@
+"""Pins the CPU oracle to facts that do not come from the oracle itself:
+brute force on tiny graphs, closed forms, the paper's worked examples,
+identities, and planted mistakes the certificate must reject."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_2606_05081_amd import inputs
+from tests import helpers as H
+
+
+# ---------------------------------------------------------------- BFS levels
+
+@pytest.mark.parametrize("seed", range(12))
+def test_bfs_matches_floyd_warshall_and_dense_eq1(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 60))
+    p = float(rng.choice([0.02, 0.05, 0.1, 0.3]))
+    rp, col = H.gnp(n, p, seed)
+    fw = H.floyd_warshall(rp, col)
+    for src in range(n):
+        lev = oracle.bfs(rp, col, src)
+        assert np.array_equal(lev, fw[src]), (seed, src)
+    for src in rng.integers(0, n, 3):
+        assert np.array_equal(oracle.bfs(rp, col, int(src)), H.dense_eq1_levels(rp, col, int(src)))
+
+
+def test_bfs_rmat_tiny_matches_brute_force():
+    for scale, seed in [(6, 3), (7, 4), (8, 5)]:
+        rp, col = inputs.rmat_graph(scale, seed)
+        fw = H.floyd_warshall(rp, col)
+        for src in range(0, rp.size - 1, 7):
+            assert np.array_equal(oracle.bfs(rp, col, src), fw[src])
+
+
+def test_closed_forms_path_cycle_star_complete():
+    n = 37
+    rp, col = H.path(n)
+    for s in (0, 5, 36):
+        assert np.array_equal(oracle.bfs(rp, col, s), np.abs(np.arange(n) - s))
+    rp, col = H.cycle(n)
+    for s in (0, 11):
+        d = np.abs(np.arange(n) - s)
+        assert np.array_equal(oracle.bfs(rp, col, s), np.minimum(d, n - d))
+    rp, col = H.star(n)
+    lev = oracle.bfs(rp, col, 0)
+    assert lev[0] == 0 and (lev[1:] == 1).all()
+    lev = oracle.bfs(rp, col, 4)
+    exp = np.full(n, 2)
+    exp[4], exp[0] = 0, 1
+    assert np.array_equal(lev, exp)
+    rp, col = H.complete(12)
+    lev = oracle.bfs(rp, col, 3)
+    assert lev[3] == 0 and (np.delete(lev, 3) == 1).all()
+    a, b = 5, 7
+    rp, col = H.complete_bipartite(a, b)
+    lev = oracle.bfs(rp, col, 0)
+    assert lev[0] == 0 and (lev[1:a] == 2).all() and (lev[a:] == 1).all()
+
+
+def test_closed_form_hypercube_hamming():
+    d = 10
+    rp, col = H.hypercube(d)
+    v = np.arange(1 << d)
+    for s in (0, 5, 1023):
+        ham = np.array([bin(x).count("1") for x in (v ^ s)])
+        assert np.array_equal(oracle.bfs(rp, col, s), ham)
+
+
+def test_closed_form_full_grid_manhattan_under_permutation():
+    side = 40
+    rp, col = inputs.grid(side, 0.0, seed=7, permute=False)
+    rp2, col2, perm = inputs.permute(rp, col, seed=11)
+    x, y = np.arange(side * side) % side, np.arange(side * side) // side
+    for s in (0, 77, side * side - 1):
+        manh = np.abs(x - x[s]) + np.abs(y - y[s])
+        lev = oracle.bfs(rp2, col2, int(perm[s]))
+        assert np.array_equal(lev[perm], manh)
+
+
+def test_unreachable_is_minus_one_and_isolated_source():
+    rp, col = inputs.from_pairs(6, [0, 1, 3], [1, 2, 4])
+    assert oracle.bfs(rp, col, 0).tolist() == [0, 1, 2, -1, -1, -1]
+    assert oracle.bfs(rp, col, 5).tolist() == [-1, -1, -1, -1, -1, 0]
+
+
+# -------------------------------------------------------------- certificate
+
+def test_certificate_accepts_truth_and_rejects_planted_mistakes():
+    rp, col = inputs.rmat_graph(10, 21)
+    deg = np.diff(rp)
+    src = int(np.argmax(deg))
+    lev = oracle.bfs(rp, col, src)
+    assert oracle.certificate(rp, col, src, lev) == (0, -1)
+    reached = np.nonzero(lev > 0)[0]
+    v = int(reached[len(reached) // 2])
+    bad = lev.copy(); bad[v] += 1
+    assert oracle.certificate(rp, col, src, bad)[0] in (3, 4)
+    bad = lev.copy(); bad[v] -= 1
+    assert oracle.certificate(rp, col, src, bad)[0] in (3, 4)
+    bad = lev.copy(); bad[v] = -1
+    assert oracle.certificate(rp, col, src, bad)[0] == 2
+    bad = lev.copy(); bad[src] = 1
+    assert oracle.certificate(rp, col, src, bad)[0] == 1
+    # a whole level shifted by one breaks the one-level rule on its parent edges
+    bad = lev.copy(); bad[lev == lev.max()] += 1
+    assert oracle.certificate(rp, col, src, bad)[0] == 3
+    # every edge within one level, but vertex 2 has no parent: path 0-1-2 as [0,1,1]
+    rp3, col3 = H.path(3)
+    assert oracle.certificate(rp3, col3, 0, np.array([0, 1, 1]))[0] == 4
+    # an unreachable component given finite levels: caught by the parent rule
+    rp2, col2 = inputs.from_pairs(5, [0, 3], [1, 4])
+    assert oracle.certificate(rp2, col2, 0, np.array([0, 1, -1, 1, 2]))[0] == 4
+
+
+# ---------------------------------------------------- multi-source/closeness
+
+def test_msbfs_rows_equal_single_source():
+    rp, col = inputs.rmat_graph(9, 31)
+    srcs = inputs.sources(rp, 20, seed=5)
+    ms = oracle.msbfs16(rp, col, srcs)
+    for c, s in enumerate(srcs):
+        assert np.array_equal(ms[c].astype(np.int32), oracle.bfs(rp, col, int(s)))
+
+
+def test_msbfs_overflow_detected():
+    n = 33000
+    rp, col = H.path(n)
+    with pytest.raises(OverflowError):
+        oracle.msbfs16(rp, col, [0])
+    assert int(oracle.msbfs16(rp, col, [16000]).max()) == 16999
+
+
+def test_closeness_closed_forms():
+    n = 50
+    rp, col = H.path(n)
+    srcs = np.arange(n)
+    sums, reach, cc = oracle.closeness(rp, col, srcs)
+    i = np.arange(n)
+    assert np.array_equal(sums, i * (i + 1) // 2 + (n - 1 - i) * (n - i) // 2)
+    assert (reach == n).all()
+    assert np.array_equal(cc, (n - 1) / sums.astype(np.float64))
+    d = 9
+    rp, col = H.hypercube(d)
+    sums, reach, _ = oracle.closeness(rp, col, np.arange(1 << d))
+    assert (sums == d * 2 ** (d - 1)).all()
+    rp, col = H.star(n)
+    sums, _, _ = oracle.closeness(rp, col, np.arange(n))
+    assert sums[0] == n - 1 and (sums[1:] == 2 * n - 3).all()
+    side = 12
+    rp, col = inputs.grid(side, 0.0, seed=1, permute=False)
+    sums, _, _ = oracle.closeness(rp, col, np.arange(side * side))
+    x, y = np.arange(side * side) % side, np.arange(side * side) // side
+    exp = np.array([np.abs(x - x[s]).sum() + np.abs(y - y[s]).sum() for s in range(side * side)])
+    assert np.array_equal(sums, exp)
+
+
+def test_closeness_isolated_source_and_disconnected():
+    rp, col = inputs.from_pairs(5, [0, 1], [1, 2])
+    sums, reach, cc = oracle.closeness(rp, col, [0, 4, 1])
+    assert sums.tolist() == [3, 0, 2]
+    assert reach.tolist() == [3, 1, 3]
+    assert cc.tolist() == [2 / 3, 0.0, 1.0]
+
+
+def test_far_equals_sums_when_all_sources_and_total_identity():
+    rp, col = inputs.rmat_graph(9, 41)
+    n = rp.size - 1
+    allv = np.arange(n)
+    sums, _, _ = oracle.closeness(rp, col, allv)
+    assert np.array_equal(oracle.far(rp, col, allv), sums)
+    sub = inputs.sources(rp, 37, seed=3)
+    s2, _, _ = oracle.closeness(rp, col, sub)
+    assert oracle.far(rp, col, sub).sum() == s2.sum()
+
+
+# --------------------------------------------------------------------- BVSS
+
+def fig1_graph():
+    """A 24-vertex graph whose BVSS reproduces the BVSS figure (built here)."""
+    pairs = [(3, 17), (3, 19), (3, 22), (16, 0), (16, 1), (18, 2), (20, 4), (5, 6), (7, 21), (8, 23)]
+    u, v = zip(*pairs)
+    return inputs.from_pairs(24, u, v)
+
+
+def bits_lsb_first(s):
+    return sum(1 << i for i, ch in enumerate(s) if ch == "1")
+
+
+def test_bvss_fig1_worked_example(golden):
+    g = golden("fig1_bvss.txt")
+    rp, col = fig1_graph()
+    b = oracle.bvss(rp, col, sigma=int(g["sigma"][0]), tau=4)
+    assert b["real_ptrs"].tolist() == [int(x) for x in g["real_ptrs"]]
+    assert b["v2r"].tolist() == [int(x) for x in g["virtual_to_real"]]
+    assert [v for v in range(b["n_vss"]) if b["v2r"][v] == 2] == [int(x) for x in g["vss_of_set2"]]
+    lo, hi = b["slice_ptr"][2], b["slice_ptr"][3]
+    rows = b["slice_row"][lo:hi].tolist()
+    mask3 = int(b["slice_mask"][lo + rows.index(3)])
+    assert mask3 == bits_lsb_first(g["mask_row3_set2"][0])
+    alpha = bits_lsb_first(g["frontier_set2"][0])
+    hits = [r for r, m in zip(rows, b["slice_mask"][lo:hi].tolist()) if m & alpha]
+    assert int(g["hit_row"][0]) in hits
+    hit = int(g["hit_row"][0])
+    assert hit // 8 == int(g["next_set"][0]) and hit % 8 == int(g["next_bit"][0])
+    s = hit // 8
+    assert list(range(b["real_ptrs"][s], b["real_ptrs"][s + 1])) == [int(x) for x in g["next_vss"]]
+    # the BFS itself: from frontier {16, 17} vertex 3 is one hop away
+    assert oracle.bfs(rp, col, 17)[3] == 1
+
+
+@pytest.mark.parametrize("sigma,tau", [(8, 128), (8, 4), (16, 64), (32, 32), (1, 3)])
+def test_bvss_decodes_back_to_csr(sigma, tau):
+    rp, col = inputs.rmat_graph(9, 77)
+    n = rp.size - 1
+    b = oracle.bvss(rp, col, sigma, tau)
+    edges = set()
+    for s in range(b["n_slice_sets"]):
+        lo, hi = b["slice_ptr"][s], b["slice_ptr"][s + 1]
+        rows = b["slice_row"][lo:hi]
+        assert (np.diff(rows) > 0).all()  # ascending, one slice per row
+        nv = b["real_ptrs"][s + 1] - b["real_ptrs"][s]
+        assert nv == -(-(hi - lo) // tau)  # VSSs of at most tau slices
+        for r, m in zip(rows.tolist(), b["slice_mask"][lo:hi].tolist()):
+            assert m != 0
+            for bit in range(sigma):
+                if m >> bit & 1:
+                    edges.add((s * sigma + bit, r))
+    exp = {(u, int(v)) for u in range(n) for v in col[rp[u]:rp[u + 1]]}
+    assert edges == exp
+    assert b["v2r"].tolist() == [s for s in range(b["n_slice_sets"])
+                                 for _ in range(b["real_ptrs"][s + 1] - b["real_ptrs"][s])]
+
+
+def test_get_vi_worked_example(golden):
+    g = golden("getvi_n24.txt")
+    n, sigma, rho = int(g["n"][0]), int(g["sigma"][0]), int(g["rho"][0])
+    layout = [int(x) for x in g["layout"]]
+    vi = oracle.get_vi(np.arange(n), sigma, rho)
+    assert sorted(vi.tolist()) == list(range(n))  # bijective
+    assert [int(u) for u in np.argsort(vi)] == layout
+
+
+# ------------------------------------------------------------ Eq. 3 replay
+
+def test_switch_replay_star_by_hand():
+    rp, col = H.star(16)
+    b = oracle.bvss(rp, col, 8, 128)
+    lev = oracle.bfs(rp, col, 0)
+    rep = oracle.switch_replay(lev, rp, b["real_ptrs"], 8, eta=10)
+    # level 0: frontier {0}, one VSS, 15 unvisited -> 15 < 10 is false: top-down
+    assert rep[0] == {"level": 0, "frontier": 1, "queue": 1, "unvisited": 15, "bottom_up": False}
+    # level 1: leaves 1..15 cover slice sets 0 and 1 -> 2 VSSs, 0 unvisited -> bottom-up
+    assert rep[1] == {"level": 1, "frontier": 15, "queue": 2, "unvisited": 0, "bottom_up": True}
+
+
+def test_level_counts_sum_to_component():
+    rp, col = inputs.rmat_graph(10, 5)
+    lev = oracle.bfs(rp, col, int(np.argmax(np.diff(rp))))
+    cnt = oracle.level_counts(lev)
+    assert cnt[0] == 1 and cnt.sum() == (lev >= 0).sum() and (cnt > 0).all()
+
+
+# ---------------------------------------------------------------------- MLP
+
+def _rand_params(seed, scale=0.3):
+    return np.random.default_rng(seed).normal(0, scale, mlp.N_PARAMS)
+
+
+def test_mlp_zero_weights_loss_is_ln3_and_logit_grad():
+    x = np.random.default_rng(0).normal(size=(17, 12))
+    y = np.arange(17) % 3
+    loss, g = mlp.loss_and_grad(np.zeros(mlp.N_PARAMS), x, y)
+    assert loss == pytest.approx(math.log(3), abs=1e-15)
+    gb3 = mlp.unpack(g)["b3"]
+    exp = np.array([(1 / 3) - np.mean(y == k) for k in range(3)])
+    assert np.allclose(gb3, exp, atol=1e-15)
+
+
+def test_mlp_forward_hand_built_network():
+    # W1 copies the 12 inputs into the first 12 hidden units, W2 copies them
+    # again, W3 sums inputs 0..3 into logit 0, 4..7 into logit 1, 8..11 into 2.
+    p = {name: np.zeros(shp) for name, shp in mlp.SHAPES}
+    p["W1"][:12, :12] = np.eye(12)
+    p["W2"][:12, :12] = np.eye(12)
+    for k in range(3):
+        p["W3"][k, 4 * k:4 * k + 4] = 1.0
+    p["b3"] = np.array([0.5, -1.0, 2.0])
+    x = np.abs(np.random.default_rng(1).normal(size=(5, 12)))
+    z, _ = mlp.forward(mlp.pack(p), x)
+    exp = np.stack([x[:, 0:4].sum(1) + 0.5, x[:, 4:8].sum(1) - 1.0, x[:, 8:12].sum(1) + 2.0], 1)
+    assert np.allclose(z, exp, atol=1e-14)
+    z2, _ = mlp.forward(mlp.pack(p), -x)  # negative inputs die in the first ReLU
+    assert np.allclose(z2, np.broadcast_to(p["b3"], z2.shape))
+
+
+def test_mlp_gradient_central_differences():
+    rng = np.random.default_rng(2)
+    theta = _rand_params(3)
+    x = rng.normal(size=(9, 12))
+    y = rng.integers(0, 3, 9)
+    w = rng.uniform(0.5, 2.0, 9)
+    _, g = mlp.loss_and_grad(theta, x, y, w)
+    h = 1e-6
+    idx = rng.choice(mlp.N_PARAMS, 120, replace=False)
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        num = (mlp.loss_and_grad(tp, x, y, w)[0] - mlp.loss_and_grad(tm, x, y, w)[0]) / (2 * h)
+        assert abs(num - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-9, i
+
+
+def test_adam_first_step_closed_form():
+    theta = _rand_params(4)
+    g = np.random.default_rng(5).normal(size=mlp.N_PARAMS)
+    lr, eps = 1e-3, 1e-8
+    t1, m1, v1 = mlp.adam_step(theta, g, np.zeros_like(g), np.zeros_like(g), 1, lr=lr, eps=eps)
+    assert np.allclose(t1, theta - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-15)
+    assert np.allclose(m1, 0.1 * g) and np.allclose(v1, 0.001 * g * g)
