@@ -1,0 +1,243 @@
+/*
+ * blest.h -- C ABI of the MI355X (gfx950) BVSS breadth-first-search library.
+ *
+ * The library implements the data-parallel hot path of "Graph Traversal on
+ * Tensor Cores: A BFS Framework for Modern GPUs" (BLEST): level-synchronous
+ * BFS written as a Boolean-semiring sparse-matrix / sparse-frontier product
+ * (Background, Eq. 1 and Eq. 2) over Binarized Virtual Slice Sets (Section
+ * BVSS), with lazy visited marking (Section "Lazy Vertex Updates", Alg. 3),
+ * top-down / bottom-up switching (Section "Switching Mechanism", Eq. 3,
+ * Alg. 4), multi-source BFS (Section "Multi-Source BFS", Alg. 5) and
+ * closeness centrality (Section "Closeness Centrality", Eq. 4 and Eq. 5).
+ *
+ * Conventions for every entry point:
+ *  - Graphs are undirected and simple: the CSR must be symmetric, rows sorted
+ *    strictly ascending, no self loops. Vertex ids are int32.
+ *  - "host" pointers are ordinary CPU memory, borrowed for the call only.
+ *    "dev" pointers are device memory on the graph's device (e.g. torch
+ *    tensors), owned by the caller.
+ *  - `stream` is a hipStream_t (NULL = the null stream). Work is ordered on
+ *    it. Unless a graph is built with opts.async = 1, each call waits for
+ *    its stream before returning so that device-side errors are reported by
+ *    the call itself.
+ *  - Calls that use one graph must not overlap (the graph owns its working
+ *    buffers); serialise them on one stream.
+ *  - Every entry point returns a blest_status; on failure
+ *    blest_last_error() holds a thread-local message. Output buffers are
+ *    unspecified after a failure.
+ */
+#ifndef BLEST_H
+#define BLEST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t blest_status;
+#define BLEST_OK 0
+#define BLEST_ERR_INVALID_ARG (-1)   /* NULL/size/option errors */
+#define BLEST_ERR_INVALID_GRAPH (-2) /* CSR not symmetric/sorted/simple, n <= 0, m >= 2^31 */
+#define BLEST_ERR_OUT_OF_RANGE (-3)  /* a source vertex outside [0, n) */
+#define BLEST_ERR_OOM (-4)           /* host or device allocation failed */
+#define BLEST_ERR_HIP (-5)           /* a HIP runtime call failed */
+#define BLEST_ERR_OVERFLOW (-6)      /* an int16 level would exceed 32767 */
+#define BLEST_ERR_UNSUPPORTED (-7)   /* option not supported (e.g. sigma) */
+#define BLEST_ERR_TIMEOUT (-8)       /* a device-wide barrier exceeded its spin bound */
+#define BLEST_ERR_NO_DEVICE (-9)     /* no usable gfx950 device */
+
+/* Short name of a status code (static string). */
+const char* blest_status_str(blest_status s);
+/* Detail of the last failure on the calling thread (static per thread). */
+const char* blest_last_error(void);
+
+typedef struct blest_graph blest_graph;
+
+/* Host CSR of an undirected simple graph: row_ptr[n+1], col_idx[m]. */
+typedef struct {
+  int64_t n;
+  int64_t m;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+} blest_csr;
+
+/* Engine choice per BFS level (Section "Switching Mechanism"). */
+#define BLEST_POLICY_HEURISTIC 0  /* Eq. 3: bottom-up iff #unvisited < eta*|Q|, else BVSS top-down */
+#define BLEST_POLICY_BVSS 1       /* plain method: BVSS top-down every level */
+#define BLEST_POLICY_PUSH 2       /* scalar top-down (push over CSR) every level */
+#define BLEST_POLICY_BOTTOM_UP 3  /* bottom-up (Alg. 4) every level */
+#define BLEST_POLICY_LEARNED 4    /* switch MLP (blest_set_switch_model); Eq. 3 fallback */
+#define BLEST_POLICY_RANDOM 5     /* seeded random engine per level (engine-independence tests) */
+
+/* Engine ids reported in blest_level_stat.engine. */
+#define BLEST_ENGINE_BVSS 0
+#define BLEST_ENGINE_PUSH 1
+#define BLEST_ENGINE_BOTTOM_UP 2
+
+#define BLEST_REORDER_NONE 0
+#define BLEST_REORDER_RCM 1  /* Reverse Cuthill-McKee (Section "Boosting Cache Locality") */
+#define BLEST_REORDER_AUTO 2 /* RCM unless the degree distribution is scale-free-like (footnote of that section) */
+
+typedef struct {
+  int32_t sigma;        /* slice-set width in columns: 8 (default), 16 or 32 */
+  int32_t tau;          /* max slices per virtual slice set: 64, 128 (default) or 256 */
+  int32_t reorder;      /* BLEST_REORDER_* (default AUTO) */
+  int32_t policy;       /* BLEST_POLICY_* (default HEURISTIC) */
+  float eta;            /* Eq. 3 switching constant (default 10) */
+  int32_t block_size;   /* threads per workgroup of the persistent kernel (default 1024) */
+  int32_t blocks_per_cu;/* persistent workgroups per compute unit, 0 = as many as fit */
+  int32_t persistent;   /* 1 (default): one cooperative launch per BFS; 0: one launch per stage */
+  int32_t wide_slices;  /* 1: 64-bit slices (row | mask) even where 32-bit packing fits */
+  int32_t prefilter;    /* 1 (default): skip marking rows already visited */
+  int32_t async;        /* 1: calls return without waiting for the stream (see blest_sync) */
+  int32_t msbfs_width;  /* sources per multi-source batch: 64, 128, 256 or 512 (default 512) */
+  uint64_t random_seed; /* seed of BLEST_POLICY_RANDOM */
+  int32_t device;       /* HIP device ordinal, -1 = current device */
+  int32_t reserved[7];
+} blest_opts;
+
+/* Fills *opts with the defaults listed above. */
+void blest_default_opts(blest_opts* opts);
+
+/* Builds the BVSS of a CSR on the device (Section BVSS). The CSR is copied;
+ * *out is owned by the caller until blest_free. opts may be NULL.
+ * Errors: INVALID_GRAPH (not symmetric, unsorted, self loops, duplicates,
+ * n <= 0, m >= 2^31), UNSUPPORTED (sigma/tau), OOM, HIP, NO_DEVICE. */
+blest_status blest_build(const blest_csr* csr, const blest_opts* opts, blest_graph** out);
+
+/* Releases every host and device resource of g. NULL is a no-op. */
+void blest_free(blest_graph* g);
+
+/* Single-source BFS (Alg. 3 with the Eq. 3 switch and Alg. 4):
+ * levels_dev[v] = hop distance from src, -1 if unreachable, in input vertex
+ * ids. levels_dev: int32[n] device memory.
+ * Errors: OUT_OF_RANGE (src), INVALID_ARG (NULL), TIMEOUT, HIP. */
+blest_status blest_bfs(blest_graph* g, int32_t src, int32_t* levels_dev, void* stream);
+
+/* Same result as blest_bfs, but at every level all three engines run from the
+ * same state and are timed (device clock); the per-level log then holds the
+ * three times (probe mode, used to label switch training data). */
+blest_status blest_bfs_probe(blest_graph* g, int32_t src, int32_t* levels_dev, void* stream);
+
+/* Multi-source BFS (Alg. 5): levels_dev[c*n + v] = d(srcs_host[c], v) as int16,
+ * -1 if unreachable, source-major, input vertex ids. levels_dev: int16[k*n].
+ * Sources may repeat; k = 0 is a no-op. Batches of opts.msbfs_width sources.
+ * Errors: OUT_OF_RANGE, OVERFLOW (a distance > 32767; levels then unspecified),
+ * INVALID_ARG, TIMEOUT, HIP. */
+blest_status blest_msbfs(blest_graph* g, const int32_t* srcs_host, int32_t k, int16_t* levels_dev, void* stream);
+
+/* Closeness inputs per source (Eq. 4, Eq. 5, normalised per source):
+ * sums_dev[c] = sum of d(srcs[c], v) over reachable v (int64),
+ * reach_dev[c] = number of reachable vertices including srcs[c] (int64),
+ * cc_dev[c] = (reach-1)/sum in IEEE double, 0 when sum = 0.
+ * Any of the three output pointers may be NULL. */
+blest_status blest_closeness(blest_graph* g, const int32_t* srcs_host, int64_t k, int64_t* sums_dev,
+                             int64_t* reach_dev, double* cc_dev, void* stream);
+
+/* With opts.async = 1: waits for `stream` and reports device-side errors of the
+ * calls enqueued since the last sync (TIMEOUT, OVERFLOW). */
+blest_status blest_sync(blest_graph* g, void* stream);
+
+/* Changes the level-engine policy of an existing graph (BLEST_POLICY_*). */
+blest_status blest_set_policy(blest_graph* g, int32_t policy, float eta, uint64_t random_seed);
+
+typedef struct {
+  int64_t n, m;
+  int32_t sigma, tau;
+  int32_t slice_bytes;   /* 4 (packed row<<8 | mask) or 8 (row<<32 | mask) */
+  int32_t reordered;     /* 1 if RCM was applied */
+  int64_t n_slice_sets;  /* N_s = ceil(n / sigma) */
+  int64_t n_vss;         /* N_v */
+  int64_t n_slices;
+  int64_t bvss_bytes;    /* device bytes of slices + slice-set offsets */
+  int64_t csr_bytes;     /* device bytes of the CSR copy */
+  int64_t work_bytes;    /* device bytes of BFS working buffers */
+  int32_t grid_blocks;   /* persistent grid size */
+  int32_t block_size;
+  int32_t device;
+  int32_t reserved[5];
+} blest_graph_stats;
+
+/* Fills *out with structure sizes. Errors: INVALID_ARG. */
+blest_status blest_graph_info(const blest_graph* g, blest_graph_stats* out);
+
+/* Per-level record of the last single-source BFS (Alg. 3, Stage 2 statistics). */
+typedef struct {
+  int32_t level;        /* frontier level l; the record describes the step l -> l+1 */
+  int32_t engine;       /* BLEST_ENGINE_* that produced level l+1 (-1 for the last level) */
+  int64_t frontier;     /* |F_l| vertices */
+  int64_t queue;        /* |Q_l| virtual slice sets */
+  int64_t queue_slices; /* slices in Q_l */
+  int64_t frontier_edges;  /* m_f: sum of degrees of F_l */
+  int64_t unvisited;    /* n - #visited through level l */
+  int64_t unvisited_edges; /* m_u: sum of degrees of unvisited vertices */
+  int64_t deg_ge_32;    /* frontier vertices with degree >= 32 */
+  int64_t deg_ge_1024;  /* frontier vertices with degree >= 1024 */
+  double t_step_us;     /* device time of the chosen engine's step plus finalisation */
+  double t_stage1_us;   /* device time of the engine's step alone (Stage 1 and its barrier) */
+  double t_engine_us[3];/* probe mode: time of each engine from the same state; else -1 */
+  int32_t mlp_fallback; /* learned policy: 1 if Eq. 3 was used (input out of range) */
+  int32_t reserved;
+} blest_level_stat;
+
+/* Copies up to cap records of the last BFS to buf (host); *nlevels = number
+ * of frontier levels (max level + 1). Errors: INVALID_ARG. */
+blest_status blest_last_level_stats(const blest_graph* g, blest_level_stat* buf, int32_t cap, int32_t* nlevels);
+
+/* Copies the BVSS to host buffers (internal vertex ids; see perm):
+ * real_ptrs[N_s+1], v2r[N_v] (virtualToReal), slice_ptr[N_s+1],
+ * slice_row[n_slices], slice_mask[n_slices] (bit b = column s*sigma+b),
+ * perm[n] (input id -> internal id). Any pointer may be NULL. */
+blest_status blest_export_bvss(const blest_graph* g, int64_t* real_ptrs, int64_t* v2r, int64_t* slice_ptr,
+                               int32_t* slice_row, uint64_t* slice_mask, int32_t* perm);
+
+/* ---- learned switch (not in the paper; its Conclusion names a more robust
+ * switching criterion as future work) ------------------------------------ */
+
+#define BLEST_MLP_IN 12
+#define BLEST_MLP_HIDDEN 64
+#define BLEST_MLP_OUT 3
+/* Flat parameter count: W1[64][12], b1[64], W2[64][64], b2[64], W3[3][64], b3[3]. */
+#define BLEST_MLP_NPARAMS 5187
+
+/* Installs switch-network weights (host arrays) used by BLEST_POLICY_LEARNED:
+ * params[BLEST_MLP_NPARAMS]; mean[12], std[12] standardise the features.
+ * g = NULL sets the default for graphs built afterwards.
+ * Errors: INVALID_ARG (nparams mismatch, std <= 0). */
+blest_status blest_set_switch_model(blest_graph* g, const float* params, int32_t nparams, const float* mean,
+                                    const float* std);
+
+/* Per-level features (12 floats, the network's inputs before standardising)
+ * of the last BFS's levels, to host: feat[nlev][12]. */
+blest_status blest_last_level_features(const blest_graph* g, float* feat, int32_t cap, int32_t* nlevels);
+
+/* Forward pass on the device: logits_dev[b][3] for x_dev[b][12] (already
+ * standardised), params_dev[BLEST_MLP_NPARAMS]. fp32. */
+blest_status blest_mlp_forward(const float* params_dev, const float* x_dev, int32_t batch, float* logits_dev,
+                               void* stream);
+
+/* Weighted mean softmax cross-entropy and its gradient on the device:
+ * loss_dev[1], grad_dev[BLEST_MLP_NPARAMS]; y_dev int32 labels in {0,1,2};
+ * w_dev per-sample weights (NULL = 1). fp32. */
+blest_status blest_mlp_loss_grad(const float* params_dev, const float* x_dev, const int32_t* y_dev,
+                                 const float* w_dev, int32_t batch, float* loss_dev, float* grad_dev, void* stream);
+
+/* One bias-corrected Adam step (Kingma and Ba) at step t >= 1, in place on
+ * params_dev, m_dev, v_dev (n floats each). */
+blest_status blest_mlp_adam(float* params_dev, const float* grad_dev, float* m_dev, float* v_dev, int32_t n,
+                            int32_t t, float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Full training loop on the device: `steps` Adam steps on minibatches of
+ * `batch` samples drawn (counter-based, from `seed`) out of x_dev[nsamples][12],
+ * y_dev, w_dev (NULL = 1); loss_log_dev[steps] receives each step's loss (may be
+ * NULL). m_dev/v_dev are Adam state (zero them to start). */
+blest_status blest_mlp_train(float* params_dev, float* m_dev, float* v_dev, const float* x_dev,
+                             const int32_t* y_dev, const float* w_dev, int32_t nsamples, int32_t batch,
+                             int32_t steps, float lr, uint64_t seed, float* loss_log_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLEST_H */

@@ -1,0 +1,520 @@
+// C ABI of the BVSS BFS library: argument checking, graph construction and
+// ownership, error reporting, and dispatch to the device code.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "blest.h"
+#include "blest_internal.h"
+#include "host_build.h"
+#include "msbfs.h"
+
+struct blest_graph {
+  blest::DevGraph d;
+  blest_opts opts{};
+  std::vector<int32_t> perm;  // input id -> internal id; empty when not reordered
+  std::vector<int64_t> real_ptrs;
+  std::vector<uint32_t> slice_ptr;
+  int reordered = 0;
+  int64_t bvss_bytes = 0, csr_bytes = 0, work_bytes = 0;
+  int nlevels = 0;
+  blest::MsDev ms;  // multi-source buffers, allocated on first use
+  std::vector<void*> allocations;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+blest_status fail(blest_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+blest_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) return fail(BLEST_ERR_OOM, std::string(what) + ": out of device memory");
+  return fail(BLEST_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define CK(expr)                                  \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
+
+std::mutex g_model_mu;
+bool g_model_set = false;
+blest::MlpDev g_model{};
+
+hipError_t dalloc(blest_graph* g, void** p, size_t bytes) {
+  *p = nullptr;
+  hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
+  if (e == hipSuccess) g->allocations.push_back(*p);
+  return e;
+}
+
+template <class T>
+hipError_t dalloc_t(blest_graph* g, T** p, size_t count) {
+  void* q = nullptr;
+  hipError_t e = dalloc(g, &q, count * sizeof(T));
+  *p = static_cast<T*>(q);
+  return e;
+}
+
+void release(blest_graph* g) {
+  if (!g) return;
+  for (void* p : g->allocations) (void)hipFree(p);
+  g->allocations.clear();
+  if (g->d.host_flags) (void)hipHostFree(g->d.host_flags);
+  g->d.host_flags = nullptr;
+  blest::ms_release(&g->ms);
+}
+
+blest_status check_device(int want, int* dev, int* num_cu, double* tick_us) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(BLEST_ERR_NO_DEVICE, "no HIP device");
+  if (want >= 0) {
+    if (want >= count) return fail(BLEST_ERR_NO_DEVICE, "device ordinal out of range");
+    CK(hipSetDevice(want));
+  }
+  CK(hipGetDevice(dev));
+  hipDeviceProp_t prop;
+  CK(hipGetDeviceProperties(&prop, *dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(BLEST_ERR_NO_DEVICE, std::string("library is built for gfx950, device is ") + prop.gcnArchName);
+  int coop = 0;
+  CK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, *dev));
+  if (!coop) return fail(BLEST_ERR_NO_DEVICE, "device lacks cooperative launch");
+  *num_cu = prop.multiProcessorCount;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, *dev) != hipSuccess || khz <= 0) khz = 100000;
+  *tick_us = 1000.0 / khz;
+  return BLEST_OK;
+}
+
+blest_status wait_and_check(blest_graph* g, hipStream_t st) {
+  CK(hipStreamSynchronize(st));
+  int flags[2] = {0, 0};
+  CK(hipMemcpy(&flags[0], &g->d.ctl->error[0], sizeof(int), hipMemcpyDeviceToHost));
+  CK(hipMemcpy(&flags[1], &g->d.ctl->nlevels[0], sizeof(int), hipMemcpyDeviceToHost));
+  g->nlevels = flags[1];
+  if (flags[0] != 0) {
+    // Leave the working state clean for the next call.
+    CK(hipMemset(g->d.ctl, 0, sizeof(blest::Ctl)));
+    CK(hipMemset(g->d.mark, 0, static_cast<size_t>(g->d.nsets) * g->d.sigma));
+    blest::ms_reset(&g->ms);
+    if (flags[0] == BLEST_ERR_TIMEOUT) return fail(BLEST_ERR_TIMEOUT, "device-wide barrier timed out");
+    if (flags[0] == BLEST_ERR_OVERFLOW) return fail(BLEST_ERR_OVERFLOW, "a distance exceeds the int16 range");
+    return fail(flags[0], "device-side error");
+  }
+  return BLEST_OK;
+}
+
+blest_status bfs_common(blest_graph* g, int32_t src, int32_t* levels_dev, void* stream, int probe) {
+  if (!g || !levels_dev) return fail(BLEST_ERR_INVALID_ARG, "NULL graph or output");
+  if (src < 0 || src >= g->d.n) return fail(BLEST_ERR_OUT_OF_RANGE, "source vertex out of range");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  CK(hipSetDevice(g->d.device));
+  blest::BfsArgs a = blest::bfs_args(g->d);
+  a.levels = levels_dev;
+  a.src = g->perm.empty() ? src : g->perm[src];
+  a.policy = g->opts.policy;
+  a.eta = g->opts.eta;
+  a.seed = g->opts.random_seed;
+  a.probe = probe;
+  hipError_t e = blest::bfs_run(g->d, a, st);
+  if (e != hipSuccess) return hip_fail(e, "bfs launch");
+  if (g->opts.async && !probe) return BLEST_OK;
+  return wait_and_check(g, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* blest_status_str(blest_status s) {
+  switch (s) {
+    case BLEST_OK: return "OK";
+    case BLEST_ERR_INVALID_ARG: return "INVALID_ARG";
+    case BLEST_ERR_INVALID_GRAPH: return "INVALID_GRAPH";
+    case BLEST_ERR_OUT_OF_RANGE: return "OUT_OF_RANGE";
+    case BLEST_ERR_OOM: return "OOM";
+    case BLEST_ERR_HIP: return "HIP";
+    case BLEST_ERR_OVERFLOW: return "OVERFLOW";
+    case BLEST_ERR_UNSUPPORTED: return "UNSUPPORTED";
+    case BLEST_ERR_TIMEOUT: return "TIMEOUT";
+    case BLEST_ERR_NO_DEVICE: return "NO_DEVICE";
+    default: return "UNKNOWN";
+  }
+}
+
+const char* blest_last_error(void) { return g_err.c_str(); }
+
+void blest_default_opts(blest_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->sigma = 8;
+  o->tau = 128;
+  o->reorder = BLEST_REORDER_AUTO;
+  o->policy = BLEST_POLICY_HEURISTIC;
+  o->eta = 10.0f;
+  o->block_size = 1024;
+  o->blocks_per_cu = 0;
+  o->persistent = 1;
+  o->wide_slices = 0;
+  o->prefilter = 1;
+  o->async = 0;
+  o->msbfs_width = 512;
+  o->random_seed = 1;
+  o->device = -1;
+}
+
+blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_graph** out) {
+  if (!csr || !out) return fail(BLEST_ERR_INVALID_ARG, "NULL csr or out");
+  *out = nullptr;
+  blest_opts o;
+  blest_default_opts(&o);
+  if (opts_in) o = *opts_in;
+  if (o.sigma != 8 && o.sigma != 16 && o.sigma != 32) return fail(BLEST_ERR_UNSUPPORTED, "sigma must be 8, 16 or 32");
+  if (o.tau != 64 && o.tau != 128 && o.tau != 192 && o.tau != 256)
+    return fail(BLEST_ERR_UNSUPPORTED, "tau must be 64, 128, 192 or 256");
+  if (o.block_size != 256 && o.block_size != 512 && o.block_size != 1024)
+    return fail(BLEST_ERR_UNSUPPORTED, "block_size must be 256, 512 or 1024");
+  if (o.policy < BLEST_POLICY_HEURISTIC || o.policy > BLEST_POLICY_RANDOM)
+    return fail(BLEST_ERR_INVALID_ARG, "unknown policy");
+  if (o.reorder < BLEST_REORDER_NONE || o.reorder > BLEST_REORDER_AUTO)
+    return fail(BLEST_ERR_INVALID_ARG, "unknown reorder mode");
+  if (!(o.eta >= 0.0f)) return fail(BLEST_ERR_INVALID_ARG, "eta must be >= 0");
+  if (o.msbfs_width != 64 && o.msbfs_width != 128 && o.msbfs_width != 256 && o.msbfs_width != 512)
+    return fail(BLEST_ERR_UNSUPPORTED, "msbfs_width must be 64, 128, 256 or 512");
+  const int64_t n = csr->n, m = csr->m;
+  std::string why;
+  if (!blest::validate_csr(n, m, csr->row_ptr, csr->col_idx, &why)) return fail(BLEST_ERR_INVALID_GRAPH, why);
+  int dev = 0, num_cu = 0;
+  double tick_us = 0.01;
+  blest_status s = check_device(o.device, &dev, &num_cu, &tick_us);
+  if (s != BLEST_OK) return s;
+
+  blest_graph* g = new (std::nothrow) blest_graph;
+  if (!g) return fail(BLEST_ERR_OOM, "host allocation");
+  g->opts = o;
+  const int32_t* rp = csr->row_ptr;
+  const int32_t* col = csr->col_idx;
+  std::vector<int32_t> rp2, col2, orig;
+  bool reorder = o.reorder == BLEST_REORDER_RCM ||
+                 (o.reorder == BLEST_REORDER_AUTO && !blest::is_scale_free_like(n, rp));
+  if (reorder && n > 1) {
+    try {
+      orig = blest::rcm_order(n, rp, col);
+      blest::permute_csr(n, rp, col, orig, g->perm, rp2, col2);
+    } catch (...) {
+      delete g;
+      return fail(BLEST_ERR_OOM, "host allocation during reordering");
+    }
+    rp = rp2.data();
+    col = col2.data();
+    g->reordered = 1;
+  }
+  const bool wide = o.sigma != 8 || o.wide_slices || n > (int64_t(1) << 24);
+  blest::Bvss b;
+  try {
+    blest::build_bvss(n, rp, col, o.sigma, o.tau, wide, &b);
+  } catch (...) {
+    delete g;
+    return fail(BLEST_ERR_OOM, "host allocation during BVSS build");
+  }
+  blest::DevGraph& d = g->d;
+  d.device = dev;
+  d.sigma = o.sigma;
+  d.tau = o.tau;
+  d.wide = wide ? 1 : 0;
+  d.n = n;
+  d.m = m;
+  d.nsets = b.nsets;
+  d.nvss = b.nvss;
+  d.nslices = b.nslices;
+  d.block = o.block_size;
+  d.num_cu = num_cu;
+  d.persistent = o.persistent;
+  d.prefilter = o.prefilter;
+  d.tick_us = tick_us;
+  d.log_cap = 1 << 16;
+  int64_t nheavy = 0;
+  for (int64_t u = 0; u < n; ++u) {
+    int32_t dg = rp[u + 1] - rp[u];
+    if (dg > blest::kLightMax) nheavy += (dg + blest::kHeavyChunk - 1) / blest::kHeavyChunk;
+  }
+  d.nheavy_cap = std::max<int64_t>(nheavy, 1);
+  const size_t mb = static_cast<size_t>(o.sigma / 8);  // bytes per sigma-bit word
+  const size_t ns = static_cast<size_t>(b.nsets);
+  hipError_t e = hipSuccess;
+#define TRY(expr)                 \
+  do {                            \
+    e = (expr);                   \
+    if (e != hipSuccess) {        \
+      release(g);                 \
+      delete g;                   \
+      return hip_fail(e, #expr);  \
+    }                             \
+  } while (0)
+  TRY(dalloc_t(g, &d.rp, static_cast<size_t>(n + 1)));
+  TRY(dalloc_t(g, &d.col, static_cast<size_t>(std::max<int64_t>(m, 1))));
+  TRY(dalloc_t(g, &d.slice_ptr, ns + 1));
+  TRY(dalloc(g, &d.slices, static_cast<size_t>(std::max<int64_t>(b.nslices, 1)) * (wide ? 8 : 4)));
+  TRY(dalloc(g, &d.degmask, ns * mb));
+  TRY(dalloc(g, &d.vis, ns * mb));
+  TRY(dalloc(g, &d.front, ns * mb));
+  TRY(dalloc_t(g, &d.mark, ns * static_cast<size_t>(o.sigma)));
+  for (int i = 0; i < 2; ++i) {
+    TRY(dalloc_t(g, &d.queue[i], static_cast<size_t>(std::max<int64_t>(b.nvss, 1))));
+    TRY(dalloc_t(g, &d.flight[i], static_cast<size_t>(n)));
+    TRY(dalloc_t(g, &d.fheavy[i], static_cast<size_t>(d.nheavy_cap)));
+  }
+  TRY(dalloc_t(g, &d.ctl, 1));
+  TRY(dalloc_t(g, &d.log, static_cast<size_t>(d.log_cap)));
+  TRY(dalloc_t(g, &d.mlp, 1));
+  if (g->reordered) {
+    TRY(dalloc_t(g, &d.orig_id, static_cast<size_t>(n)));
+    TRY(hipMemcpy(d.orig_id, orig.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+  }
+  TRY(hipHostMalloc(reinterpret_cast<void**>(&d.host_flags), 64, hipHostMallocDefault));
+  TRY(hipMemcpy(d.rp, rp, sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
+  if (m > 0) TRY(hipMemcpy(d.col, col, sizeof(int32_t) * m, hipMemcpyHostToDevice));
+  TRY(hipMemcpy(d.slice_ptr, b.slice_ptr.data(), sizeof(uint32_t) * (ns + 1), hipMemcpyHostToDevice));
+  if (b.nslices > 0) {
+    if (wide)
+      TRY(hipMemcpy(d.slices, b.slices64.data(), 8 * b.nslices, hipMemcpyHostToDevice));
+    else
+      TRY(hipMemcpy(d.slices, b.slices32.data(), 4 * b.nslices, hipMemcpyHostToDevice));
+  }
+  {
+    std::vector<uint8_t> dm(ns * mb);
+    for (size_t s2 = 0; s2 < ns; ++s2) std::memcpy(&dm[s2 * mb], &b.degmask[s2], mb);  // little endian
+    TRY(hipMemcpy(d.degmask, dm.data(), dm.size(), hipMemcpyHostToDevice));
+  }
+  TRY(hipMemset(d.mark, 0, ns * o.sigma));
+  TRY(hipMemset(d.ctl, 0, sizeof(blest::Ctl)));
+  TRY(hipMemset(d.mlp, 0, sizeof(blest::MlpDev)));
+  {
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    if (g_model_set) TRY(hipMemcpy(d.mlp, &g_model, sizeof(g_model), hipMemcpyHostToDevice));
+  }
+  TRY(blest::bfs_grid_size(d, 1, o.blocks_per_cu, &d.grid));
+  TRY(hipDeviceSynchronize());
+#undef TRY
+  g->real_ptrs = std::move(b.real_ptrs);
+  g->slice_ptr = std::move(b.slice_ptr);
+  g->csr_bytes = 4 * (n + 1) + 4 * m;
+  g->bvss_bytes = 4 * static_cast<int64_t>(ns + 1) + (wide ? 8 : 4) * b.nslices;
+  g->work_bytes = static_cast<int64_t>(ns * mb * 3 + ns * o.sigma) + 2 * 16 * std::max<int64_t>(b.nvss, 1) +
+                  2 * 4 * n + 2 * 8 * d.nheavy_cap;
+  g->ms.device = dev;
+  *out = g;
+  return BLEST_OK;
+}
+
+void blest_free(blest_graph* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->d.device);
+  (void)hipDeviceSynchronize();
+  release(g);
+  delete g;
+}
+
+blest_status blest_bfs(blest_graph* g, int32_t src, int32_t* levels_dev, void* stream) {
+  return bfs_common(g, src, levels_dev, stream, 0);
+}
+
+blest_status blest_bfs_probe(blest_graph* g, int32_t src, int32_t* levels_dev, void* stream) {
+  return bfs_common(g, src, levels_dev, stream, 1);
+}
+
+blest_status blest_sync(blest_graph* g, void* stream) {
+  if (!g) return fail(BLEST_ERR_INVALID_ARG, "NULL graph");
+  CK(hipSetDevice(g->d.device));
+  return wait_and_check(g, static_cast<hipStream_t>(stream));
+}
+
+blest_status blest_set_policy(blest_graph* g, int32_t policy, float eta, uint64_t seed) {
+  if (!g) return fail(BLEST_ERR_INVALID_ARG, "NULL graph");
+  if (policy < BLEST_POLICY_HEURISTIC || policy > BLEST_POLICY_RANDOM) return fail(BLEST_ERR_INVALID_ARG, "unknown policy");
+  if (!(eta >= 0.0f)) return fail(BLEST_ERR_INVALID_ARG, "eta must be >= 0");
+  g->opts.policy = policy;
+  g->opts.eta = eta;
+  g->opts.random_seed = seed;
+  return BLEST_OK;
+}
+
+blest_status blest_graph_info(const blest_graph* g, blest_graph_stats* out) {
+  if (!g || !out) return fail(BLEST_ERR_INVALID_ARG, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  out->n = g->d.n;
+  out->m = g->d.m;
+  out->sigma = g->d.sigma;
+  out->tau = g->d.tau;
+  out->slice_bytes = g->d.wide ? 8 : 4;
+  out->reordered = g->reordered;
+  out->n_slice_sets = g->d.nsets;
+  out->n_vss = g->d.nvss;
+  out->n_slices = g->d.nslices;
+  out->bvss_bytes = g->bvss_bytes;
+  out->csr_bytes = g->csr_bytes;
+  out->work_bytes = g->work_bytes;
+  out->grid_blocks = g->d.grid;
+  out->block_size = g->d.block;
+  out->device = g->d.device;
+  return BLEST_OK;
+}
+
+blest_status blest_last_level_stats(const blest_graph* g, blest_level_stat* buf, int32_t cap, int32_t* nlevels) {
+  if (!g || !nlevels || (cap > 0 && !buf)) return fail(BLEST_ERR_INVALID_ARG, "NULL argument");
+  *nlevels = g->nlevels;
+  const int k = std::min({cap, g->nlevels, g->d.log_cap});
+  if (k <= 0) return BLEST_OK;
+  std::vector<blest::LevelRec> rec(static_cast<size_t>(k));
+  CK(hipSetDevice(g->d.device));
+  CK(hipMemcpy(rec.data(), g->d.log, sizeof(blest::LevelRec) * k, hipMemcpyDeviceToHost));
+  for (int i = 0; i < k; ++i) {
+    const blest::LevelRec& r = rec[i];
+    blest_level_stat& o = buf[i];
+    std::memset(&o, 0, sizeof(o));
+    o.level = i;
+    o.engine = (i == g->nlevels - 1) ? -1 : r.engine;
+    o.frontier = r.frontier;
+    o.queue = r.queue;
+    o.queue_slices = r.qslices;
+    o.frontier_edges = r.fedges;
+    o.unvisited = r.unvisited;
+    o.unvisited_edges = r.unvisited_edges;
+    o.deg_ge_32 = r.deg32;
+    o.deg_ge_1024 = r.deg1024;
+    o.t_step_us = r.t_end > r.t_begin ? (r.t_end - r.t_begin) * g->d.tick_us : 0.0;
+    o.t_stage1_us = r.t_mid > r.t_begin ? (r.t_mid - r.t_begin) * g->d.tick_us : 0.0;
+    for (int e = 0; e < 3; ++e) o.t_engine_us[e] = r.t_engine[e] ? r.t_engine[e] * g->d.tick_us : -1.0;
+    o.mlp_fallback = r.fallback;
+  }
+  return BLEST_OK;
+}
+
+blest_status blest_last_level_features(const blest_graph* g, float* feat, int32_t cap, int32_t* nlevels) {
+  if (!g || !nlevels || (cap > 0 && !feat)) return fail(BLEST_ERR_INVALID_ARG, "NULL argument");
+  *nlevels = g->nlevels;
+  const int k = std::min({cap, g->nlevels, g->d.log_cap});
+  if (k <= 0) return BLEST_OK;
+  std::vector<blest::LevelRec> rec(static_cast<size_t>(k));
+  CK(hipSetDevice(g->d.device));
+  CK(hipMemcpy(rec.data(), g->d.log, sizeof(blest::LevelRec) * k, hipMemcpyDeviceToHost));
+  for (int i = 0; i < k; ++i) std::memcpy(feat + i * BLEST_MLP_IN, rec[i].feat, sizeof(float) * BLEST_MLP_IN);
+  return BLEST_OK;
+}
+
+blest_status blest_export_bvss(const blest_graph* g, int64_t* real_ptrs, int64_t* v2r, int64_t* slice_ptr,
+                               int32_t* slice_row, uint64_t* slice_mask, int32_t* perm) {
+  if (!g) return fail(BLEST_ERR_INVALID_ARG, "NULL graph");
+  const int64_t ns = g->d.nsets;
+  if (real_ptrs) std::copy(g->real_ptrs.begin(), g->real_ptrs.end(), real_ptrs);
+  if (v2r)
+    for (int64_t s = 0; s < ns; ++s)
+      for (int64_t v = g->real_ptrs[s]; v < g->real_ptrs[s + 1]; ++v) v2r[v] = s;
+  if (slice_ptr)
+    for (int64_t s = 0; s <= ns; ++s) slice_ptr[s] = g->slice_ptr[s];
+  if ((slice_row || slice_mask) && g->d.nslices > 0) {
+    CK(hipSetDevice(g->d.device));
+    const int64_t k = g->d.nslices;
+    if (g->d.wide) {
+      std::vector<uint64_t> w(static_cast<size_t>(k));
+      CK(hipMemcpy(w.data(), g->d.slices, 8 * k, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < k; ++i) {
+        if (slice_row) slice_row[i] = static_cast<int32_t>(w[i] >> 32);
+        if (slice_mask) slice_mask[i] = w[i] & 0xffffffffULL;
+      }
+    } else {
+      std::vector<uint32_t> w(static_cast<size_t>(k));
+      CK(hipMemcpy(w.data(), g->d.slices, 4 * k, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < k; ++i) {
+        if (slice_row) slice_row[i] = static_cast<int32_t>(w[i] >> 8);
+        if (slice_mask) slice_mask[i] = w[i] & 0xffu;
+      }
+    }
+  }
+  if (perm) {
+    if (g->perm.empty())
+      for (int64_t i = 0; i < g->d.n; ++i) perm[i] = static_cast<int32_t>(i);
+    else
+      std::copy(g->perm.begin(), g->perm.end(), perm);
+  }
+  return BLEST_OK;
+}
+
+blest_status blest_set_switch_model(blest_graph* g, const float* params, int32_t nparams, const float* mean,
+                                    const float* std_) {
+  if (!params || !mean || !std_) return fail(BLEST_ERR_INVALID_ARG, "NULL argument");
+  if (nparams != BLEST_MLP_NPARAMS) return fail(BLEST_ERR_INVALID_ARG, "wrong parameter count");
+  blest::MlpDev m{};
+  std::memcpy(m.params, params, sizeof(m.params));
+  for (int i = 0; i < BLEST_MLP_IN; ++i) {
+    if (!(std_[i] > 0.0f) || !std::isfinite(std_[i]) || !std::isfinite(mean[i]))
+      return fail(BLEST_ERR_INVALID_ARG, "feature std must be positive and finite");
+    m.mean[i] = mean[i];
+    m.inv_std[i] = 1.0f / std_[i];
+  }
+  for (int i = 0; i < BLEST_MLP_NPARAMS; ++i)
+    if (!std::isfinite(params[i])) return fail(BLEST_ERR_INVALID_ARG, "non-finite parameter");
+  m.valid = 1;
+  if (!g) {
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    g_model = m;
+    g_model_set = true;
+    return BLEST_OK;
+  }
+  CK(hipSetDevice(g->d.device));
+  CK(hipMemcpy(g->d.mlp, &m, sizeof(m), hipMemcpyHostToDevice));
+  return BLEST_OK;
+}
+
+blest_status blest_msbfs(blest_graph* g, const int32_t* srcs, int32_t k, int16_t* levels_dev, void* stream) {
+  if (!g) return fail(BLEST_ERR_INVALID_ARG, "NULL graph");
+  if (k < 0) return fail(BLEST_ERR_INVALID_ARG, "negative source count");
+  if (k == 0) return BLEST_OK;
+  if (!srcs || !levels_dev) return fail(BLEST_ERR_INVALID_ARG, "NULL sources or output");
+  for (int32_t c = 0; c < k; ++c)
+    if (srcs[c] < 0 || srcs[c] >= g->d.n) return fail(BLEST_ERR_OUT_OF_RANGE, "source vertex out of range");
+  CK(hipSetDevice(g->d.device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<int32_t> internal(srcs, srcs + k);
+  if (!g->perm.empty())
+    for (auto& s : internal) s = g->perm[s];
+  hipError_t e = blest::ms_run(g->d, &g->ms, internal.data(), k, g->opts.msbfs_width, levels_dev, nullptr, nullptr,
+                               nullptr, st);
+  if (e != hipSuccess) return hip_fail(e, "msbfs");
+  if (g->opts.async) return BLEST_OK;
+  return wait_and_check(g, st);
+}
+
+blest_status blest_closeness(blest_graph* g, const int32_t* srcs, int64_t k, int64_t* sums_dev, int64_t* reach_dev,
+                             double* cc_dev, void* stream) {
+  if (!g) return fail(BLEST_ERR_INVALID_ARG, "NULL graph");
+  if (k < 0 || k > INT32_MAX) return fail(BLEST_ERR_INVALID_ARG, "bad source count");
+  if (k == 0) return BLEST_OK;
+  if (!srcs) return fail(BLEST_ERR_INVALID_ARG, "NULL sources");
+  for (int64_t c = 0; c < k; ++c)
+    if (srcs[c] < 0 || srcs[c] >= g->d.n) return fail(BLEST_ERR_OUT_OF_RANGE, "source vertex out of range");
+  CK(hipSetDevice(g->d.device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<int32_t> internal(srcs, srcs + k);
+  if (!g->perm.empty())
+    for (auto& s : internal) s = g->perm[s];
+  hipError_t e = blest::ms_run(g->d, &g->ms, internal.data(), static_cast<int32_t>(k), g->opts.msbfs_width, nullptr,
+                               sums_dev, reach_dev, cc_dev, st);
+  if (e != hipSuccess) return hip_fail(e, "closeness");
+  if (g->opts.async) return BLEST_OK;
+  return wait_and_check(g, st);
+}
+
+}  // extern "C"

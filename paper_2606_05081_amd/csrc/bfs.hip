@@ -1,0 +1,839 @@
+// Single-source BVSS breadth-first search for gfx950.
+//
+// One traversal step turns frontier level l into level l+1 in two stages
+// (Section "Lazy Vertex Updates", Alg. 3):
+//   Stage 1 marks every vertex that has a neighbour in the frontier, with a
+//           plain byte store of 1 into mark[] (idempotent, so no atomics).
+//           Three interchangeable engines do this:
+//             E0 BVSS top-down: one wave per queued virtual slice set; each
+//                lane tests (mask & alpha) != 0 for its slices, alpha being
+//                the frontier bits of the set (Eq. 1 / Eq. 2, popc(a&x) > 0
+//                written as a bitwise AND).
+//             E1 push: frontier vertices walk their CSR rows.
+//             E2 bottom-up (Alg. 4): each unvisited vertex scans its row and
+//                stops at the first frontier neighbour.
+//   Stage 2 sweeps the marks of every slice set, keeps the bits not yet
+//           visited (the XOR of V_next and V_curr), writes their level,
+//           updates visited/frontier words, enqueues every VSS of each set
+//           that gained a vertex and accumulates the per-level statistics.
+// The engine of each step is chosen on the device (Eq. 3 heuristic, learned
+// network, fixed or random) identically by every workgroup. All levels run in
+// one cooperative persistent launch separated by a device-wide barrier
+// (Section "Switching Mechanism", last paragraph); a per-stage launch mode is
+// kept for comparison.
+#include "device_common.h"
+
+namespace blest {
+
+// ------------------------------------------------------------- decisions
+
+struct LevelView {
+  long long frontier, queue, qslices, fedges, deg32, deg1024, light, heavy, cumv, cume;
+};
+
+__device__ __forceinline__ LevelView read_level(const Ctl* ctl, int slot) {
+  const unsigned long long* acc = &ctl->acc[slot][0][0];
+  LevelView v;
+  v.frontier = static_cast<long long>(acc[F_FRONTIER * kPad]);
+  v.queue = static_cast<long long>(acc[F_QUEUE * kPad]);
+  v.qslices = static_cast<long long>(acc[F_QSLICES * kPad]);
+  v.fedges = static_cast<long long>(acc[F_FEDGES * kPad]);
+  v.deg32 = static_cast<long long>(acc[F_DEG32 * kPad]);
+  v.deg1024 = static_cast<long long>(acc[F_DEG1024 * kPad]);
+  v.light = static_cast<long long>(acc[F_LIGHT * kPad]);
+  v.heavy = static_cast<long long>(acc[F_HEAVY * kPad]);
+  v.cumv = static_cast<long long>(acc[F_CUMV * kPad]);
+  v.cume = static_cast<long long>(acc[F_CUME * kPad]);
+  return v;
+}
+
+// The 12 switch features of a level (network inputs before standardising).
+__device__ __forceinline__ void level_features(float (&f)[kMaxSwitchFeatures], const LevelView& v, long long n,
+                                               long long m, int level, long long prev_frontier) {
+  const long long unv = n - v.cumv, unv_e = m - v.cume;
+  f[0] = log2f(1.0f + static_cast<float>(v.frontier));
+  f[1] = log2f(1.0f + static_cast<float>(v.queue));
+  f[2] = log2f(1.0f + static_cast<float>(v.qslices));
+  f[3] = log2f(1.0f + static_cast<float>(v.fedges));
+  f[4] = log2f(1.0f + static_cast<float>(unv));
+  f[5] = log2f(1.0f + static_cast<float>(unv_e));
+  f[6] = log2f(static_cast<float>(n));
+  f[7] = log2f(1.0f + static_cast<float>(m));
+  f[8] = log2f(1.0f + static_cast<float>(level));
+  f[9] = f[0] - log2f(1.0f + static_cast<float>(prev_frontier));
+  const float inv = v.frontier > 0 ? 1.0f / static_cast<float>(v.frontier) : 0.0f;
+  f[10] = static_cast<float>(v.deg32) * inv;
+  f[11] = static_cast<float>(v.deg1024) * inv;
+}
+
+// Eq. 3: bottom-up iff #unvisited < eta * |Q_curr| (|Q| counts VSSs).
+__device__ __forceinline__ int heuristic_engine(long long unvisited, long long queue, float eta) {
+  return (static_cast<double>(unvisited) < static_cast<double>(eta) * static_cast<double>(queue))
+             ? BLEST_ENGINE_BOTTOM_UP
+             : BLEST_ENGINE_BVSS;
+}
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// Switch network in LDS: W1T[12][64], b1[64], W2T[64][64], b2[64], W3[3][64],
+// b3[3], mean[12], inv_std[12] (W1 and W2 transposed for conflict-free reads).
+constexpr int kLdsW1T = 0, kLdsB1 = 768, kLdsW2T = 832, kLdsB2 = 4928, kLdsW3 = 4992, kLdsB3 = 5184,
+              kLdsMean = 5187, kLdsInvStd = 5199, kLdsMlpFloats = 5211;
+
+__device__ void mlp_to_lds(const MlpDev* mlp, float* s) {
+  const float* p = mlp->params;
+  for (int i = threadIdx.x; i < 768; i += blockDim.x) {
+    int j = i / 12, k = i % 12;  // W1[j][k]
+    s[kLdsW1T + k * 64 + j] = p[i];
+  }
+  for (int i = threadIdx.x; i < 4096; i += blockDim.x) {
+    int j = i / 64, k = i % 64;  // W2[j][k]
+    s[kLdsW2T + k * 64 + j] = p[832 + i];
+  }
+  for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+    s[kLdsB1 + i] = p[768 + i];
+    s[kLdsB2 + i] = p[4928 + i];
+  }
+  for (int i = threadIdx.x; i < 195; i += blockDim.x) s[kLdsW3 + i] = p[4992 + i];
+  for (int i = threadIdx.x; i < 12; i += blockDim.x) {
+    s[kLdsMean + i] = mlp->mean[i];
+    s[kLdsInvStd + i] = mlp->inv_std[i];
+  }
+}
+
+// Forward pass by one full wave; returns the argmax engine, or -1 when a
+// standardised input lies outside [-6, 6] (caller falls back to Eq. 3).
+__device__ int mlp_choose_wave(const float* s, const float (&feat)[kMaxSwitchFeatures]) {
+  float z[kMaxSwitchFeatures];
+  bool ood = false;
+#pragma unroll
+  for (int k = 0; k < kMaxSwitchFeatures; ++k) {
+    z[k] = (feat[k] - s[kLdsMean + k]) * s[kLdsInvStd + k];
+    ood |= !(fabsf(z[k]) <= 6.0f);
+  }
+  if (ood) return -1;
+  const int j = lane_id();
+  float h = s[kLdsB1 + j];
+#pragma unroll
+  for (int k = 0; k < kMaxSwitchFeatures; ++k) h = fmaf(s[kLdsW1T + k * 64 + j], z[k], h);
+  h = fmaxf(h, 0.0f);
+  float g = s[kLdsB2 + j];
+#pragma unroll 8
+  for (int k = 0; k < 64; ++k) {
+    float hk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h), k));
+    g = fmaf(s[kLdsW2T + k * 64 + j], hk, g);
+  }
+  g = fmaxf(g, 0.0f);
+  float l0 = wave_sum(s[kLdsW3 + j] * g) + s[kLdsB3 + 0];
+  float l1 = wave_sum(s[kLdsW3 + 64 + j] * g) + s[kLdsB3 + 1];
+  float l2 = wave_sum(s[kLdsW3 + 128 + j] * g) + s[kLdsB3 + 2];
+  int best = 0;
+  float bv = l0;
+  if (l1 > bv) { best = 1; bv = l1; }
+  if (l2 > bv) { best = 2; }
+  return best;
+}
+
+// Uniform engine choice for the step out of `level`. Contains __syncthreads().
+__device__ int choose_engine(const BfsArgs& a, const LevelView& v, const float (&feat)[kMaxSwitchFeatures],
+                             int level, const float* s_mlp, int* fallback) {
+  __shared__ int s_choice;
+  const long long unvisited = a.n - v.cumv;
+  *fallback = 0;
+  switch (a.policy) {
+    case BLEST_POLICY_BVSS:
+      return BLEST_ENGINE_BVSS;
+    case BLEST_POLICY_PUSH:
+      return BLEST_ENGINE_PUSH;
+    case BLEST_POLICY_BOTTOM_UP:
+      return BLEST_ENGINE_BOTTOM_UP;
+    case BLEST_POLICY_RANDOM:
+      return static_cast<int>(mix64(a.seed + 0x9E3779B97F4A7C15ULL * static_cast<unsigned long long>(level + 1)) % 3ULL);
+    case BLEST_POLICY_LEARNED:
+      if (s_mlp != nullptr) {
+        if (threadIdx.x < 64) {
+          int c = mlp_choose_wave(s_mlp, feat);
+          if (threadIdx.x == 0) s_choice = c;
+        }
+        __syncthreads();
+        int c = s_choice;
+        __syncthreads();
+        if (c >= 0) return c;
+      }
+      *fallback = 1;
+      return heuristic_engine(unvisited, v.queue, a.eta);
+    default:
+      return heuristic_engine(unvisited, v.queue, a.eta);
+  }
+}
+
+// ------------------------------------------------------------ Stage 1
+
+// E0: BVSS top-down with pull mechanics and lazy marking. A wave takes G
+// consecutive queue entries at a time and issues all their slice loads before
+// testing any, so each lane keeps G * K independent loads in flight
+// (K = tau / 64 slices per lane per VSS).
+template <int SIGMA, class SliceT, int K>
+__device__ void engine_bvss_k(const BfsArgs& a, const uint4* __restrict__ q, long long qlen, long long gwave,
+                              long long nwaves) {
+  using M = typename MaskOf<SIGMA>::T;
+  constexpr int G = 4;
+  const SliceT* __restrict__ sl = static_cast<const SliceT*>(a.slices);
+  const M* __restrict__ vis = static_cast<const M*>(a.vis);
+  uint8_t* __restrict__ mark = a.mark;
+  const uint32_t lane = static_cast<uint32_t>(lane_id());
+  const bool pre = a.prefilter != 0;
+  for (long long base = gwave * G; base < qlen; base += nwaves * G) {
+    uint4 dl = make_uint4(0u, 0u, 0u, 0u);
+    if (lane < G && base + lane < qlen) dl = q[base + lane];
+    uint32_t st[G], cn[G];
+    SliceT al[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      st[g] = __builtin_amdgcn_readlane(dl.x, g);
+      cn[g] = __builtin_amdgcn_readlane(dl.y, g);
+      al[g] = static_cast<SliceT>(static_cast<uint32_t>(__builtin_amdgcn_readlane(dl.z, g)));
+    }
+    SliceT w[G][K];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const uint32_t j = lane + 64u * k;
+        w[g][k] = (j < cn[g]) ? sl[st[g] + j] : SliceT(0);
+      }
+    if (pre) {
+      M vv[G][K];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const uint32_t row = static_cast<uint32_t>(w[g][k] >> SliceFmt<SliceT>::kRowShift);
+          vv[g][k] = (w[g][k] & al[g]) ? vis[row / SIGMA] : M(~M(0));
+        }
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const uint32_t row = static_cast<uint32_t>(w[g][k] >> SliceFmt<SliceT>::kRowShift);
+          if (!((vv[g][k] >> (row % SIGMA)) & 1u)) mark[row] = 1;
+        }
+    } else {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          if (w[g][k] & al[g]) mark[static_cast<uint32_t>(w[g][k] >> SliceFmt<SliceT>::kRowShift)] = 1;
+    }
+  }
+}
+
+template <int SIGMA, class SliceT>
+__device__ void engine_bvss(const BfsArgs& a, const uint4* __restrict__ q, long long qlen, long long gwave,
+                            long long nwaves) {
+  switch (a.tau) {
+    case 64:
+      engine_bvss_k<SIGMA, SliceT, 1>(a, q, qlen, gwave, nwaves);
+      break;
+    case 128:
+      engine_bvss_k<SIGMA, SliceT, 2>(a, q, qlen, gwave, nwaves);
+      break;
+    case 192:
+      engine_bvss_k<SIGMA, SliceT, 3>(a, q, qlen, gwave, nwaves);
+      break;
+    default:
+      engine_bvss_k<SIGMA, SliceT, 4>(a, q, qlen, gwave, nwaves);
+      break;
+  }
+}
+
+// E1: push over the CSR rows of the frontier vertices.
+template <int SIGMA>
+__device__ void engine_push(const BfsArgs& a, int sel, long long nlight, long long nheavy, long long gtid,
+                            long long nthreads, long long gwave, long long nwaves) {
+  using M = typename MaskOf<SIGMA>::T;
+  const M* __restrict__ vis = static_cast<const M*>(a.vis);
+  const int32_t* __restrict__ rp = a.rp;
+  const int32_t* __restrict__ col = a.col;
+  uint8_t* __restrict__ mark = a.mark;
+  const int lane = lane_id();
+  const unsigned long long* __restrict__ heavy = a.fheavy[sel];
+  for (long long i = gwave; i < nheavy; i += nwaves) {
+    const unsigned long long e = heavy[i];
+    const int u = static_cast<int>(e >> 32);
+    const int b = rp[u] + static_cast<int>(e & 0xffffffffULL);
+    const int end = min(rp[u + 1], b + kHeavyChunk);
+    for (int p = b + lane; p < end; p += 64) {
+      const int v = col[p];
+      if (!((vis[v / SIGMA] >> (v % SIGMA)) & 1u)) mark[v] = 1;
+    }
+  }
+  const int32_t* __restrict__ light = a.flight[sel];
+  for (long long i = gtid; i < nlight; i += nthreads) {
+    const int u = light[i];
+    const int e = rp[u + 1];
+    for (int p = rp[u]; p < e; ++p) {
+      const int v = col[p];
+      if (!((vis[v / SIGMA] >> (v % SIGMA)) & 1u)) mark[v] = 1;
+    }
+  }
+}
+
+// E2: bottom-up (Alg. 4). A lane owns one vertex; an unvisited vertex of
+// degree <= kPullLight scans its row alone and stops at the first frontier
+// neighbour. Longer rows are scanned by the whole wave, 64 neighbours per
+// step, stopping at the first step that finds one.
+constexpr int kPullLight = 32;
+
+template <int SIGMA>
+__device__ void engine_pull(const BfsArgs& a, long long gtid, long long nthreads) {
+  using M = typename MaskOf<SIGMA>::T;
+  const M* __restrict__ vis = static_cast<const M*>(a.vis);
+  const M* __restrict__ front = static_cast<const M*>(a.front);
+  const M* __restrict__ degm = static_cast<const M*>(a.degmask);
+  const int32_t* __restrict__ rp = a.rp;
+  const int32_t* __restrict__ col = a.col;
+  uint8_t* __restrict__ mark = a.mark;
+  const long long nv = a.nsets * SIGMA;
+  const int lane = lane_id();
+  for (long long ubase = gtid - lane; ubase < nv; ubase += nthreads) {
+    const long long u = ubase + lane;
+    bool cand = false;
+    int p = 0, e = 0;
+    if (u < nv) {
+      const long long s = u / SIGMA;
+      const M unv = static_cast<M>(~vis[s] & degm[s]);
+      cand = (unv >> (u % SIGMA)) & 1u;
+    }
+    if (cand) {
+      p = rp[u];
+      e = rp[u + 1];
+    }
+    const bool heavy = cand && (e - p > kPullLight);
+    if (cand && !heavy) {
+      for (; p < e; ++p) {
+        const int v = col[p];
+        if ((front[v / SIGMA] >> (v % SIGMA)) & 1u) {
+          mark[u] = 1;
+          break;
+        }
+      }
+    }
+    unsigned long long hb = __ballot(heavy);
+    while (hb) {
+      const int l = __builtin_ctzll(hb);
+      hb &= hb - 1;
+      const int hp = __builtin_amdgcn_readlane(p, l), he = __builtin_amdgcn_readlane(e, l);
+      for (int qq = hp; qq < he; qq += 64) {
+        const int i = qq + lane;
+        bool f = false;
+        if (i < he) {
+          const int v = col[i];
+          f = (front[v / SIGMA] >> (v % SIGMA)) & 1u;
+        }
+        if (__ballot(f)) {
+          if (lane == 0) mark[ubase + l] = 1;
+          break;
+        }
+      }
+    }
+  }
+}
+
+template <int SIGMA, class SliceT>
+__device__ __forceinline__ void run_engine(const BfsArgs& a, int engine, int sel, const LevelView& v, long long gtid,
+                                           long long nthreads, long long gwave, long long nwaves) {
+  if (engine == BLEST_ENGINE_BVSS)
+    engine_bvss<SIGMA, SliceT>(a, a.queue[sel], v.queue, gwave, nwaves);
+  else if (engine == BLEST_ENGINE_PUSH)
+    engine_push<SIGMA>(a, sel, v.light, v.heavy, gtid, nthreads, gwave, nwaves);
+  else
+    engine_pull<SIGMA>(a, gtid, nthreads);
+}
+
+// ------------------------------------------------------------ Stage 2
+
+// A run of queue descriptors (kind 0: first slice a, slice count b, frontier
+// bits c, set d) or heavy edge chunks (kind 1: vertex a) starting at `out`.
+struct ExpandRec {
+  unsigned long long out;
+  uint32_t n, kind, a, b, c, d;
+};
+constexpr int kExpandMin = 8;
+constexpr int kMaxExpand = 128;
+
+template <int SIGMA, int BLOCK>
+__device__ void finalize(const BfsArgs& a, int new_level, int slot_out, int sel_out, long long cumv_in,
+                         long long cume_in, unsigned nblocks) {
+  using M = typename MaskOf<SIGMA>::T;
+  constexpr int SPT = 2;
+  constexpr long long WIN = static_cast<long long>(BLOCK) * SPT;
+  __shared__ int lds32[3 * (BLOCK / 64)];
+  __shared__ long long lds64[5 * (BLOCK / 64)];
+  __shared__ unsigned long long bases[3];
+  __shared__ ExpandRec rec[kMaxExpand];
+  __shared__ int nrec;
+  if (threadIdx.x == 0) nrec = 0;
+  M* __restrict__ vis = static_cast<M*>(a.vis);
+  M* __restrict__ front = static_cast<M*>(a.front);
+  uint8_t* __restrict__ mark = a.mark;
+  const int32_t* __restrict__ rp = a.rp;
+  const uint32_t* __restrict__ sp = a.slice_ptr;
+  const uint32_t tau = static_cast<uint32_t>(a.tau);
+  unsigned long long* acc = &a.ctl->acc[slot_out][0][0];
+  int32_t* __restrict__ light = a.flight[sel_out];
+  unsigned long long* __restrict__ heavy = a.fheavy[sel_out];
+  uint4* __restrict__ queue = a.queue[sel_out];
+  long long st[5] = {0, 0, 0, 0, 0};  // frontier, queued slices, frontier edges, deg>=32, deg>=1024
+  const long long nwin = (a.nsets + WIN - 1) / WIN;
+  for (long long win = blockIdx.x; win < nwin; win += nblocks) {
+    const long long base = win * WIN;
+    M nw[SPT];
+    int cnt[3] = {0, 0, 0};  // light vertices, heavy chunks, VSSs
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+      const long long s = base + k * BLOCK + threadIdx.x;
+      nw[k] = 0;
+      if (s < a.nsets) {
+        const M bits = load_marks<SIGMA>(mark + s * SIGMA);
+        if (bits) {
+          clear_marks<SIGMA>(mark + s * SIGMA);
+          const M old = vis[s];
+          const M x = static_cast<M>(bits & ~old);
+          if (x) {
+            vis[s] = static_cast<M>(old | x);
+            front[s] = x;
+            nw[k] = x;
+            uint32_t t = x;
+            while (t) {
+              const int b = __builtin_ctz(t);
+              t &= t - 1;
+              const long long u = s * SIGMA + b;
+              const int d = rp[u + 1] - rp[u];
+              st[0] += 1;
+              st[2] += d;
+              st[3] += d >= 32;
+              st[4] += d >= 1024;
+              if (d > kLightMax)
+                cnt[1] += (d + kHeavyChunk - 1) / kHeavyChunk;
+              else
+                cnt[0] += 1;
+              a.levels[a.orig_id ? a.orig_id[u] : u] = new_level;
+            }
+            const uint32_t ns = sp[s + 1] - sp[s];
+            cnt[2] += static_cast<int>((ns + tau - 1) / tau);
+            st[1] += ns;
+          }
+        }
+      }
+    }
+    if (!__syncthreads_or(cnt[0] | cnt[1] | cnt[2])) continue;
+    int ex[3], tot[3];
+    block_exclusive_scan<BLOCK, 3>(cnt, ex, tot, lds32);
+    if (threadIdx.x == 0) {
+      bases[0] = tot[0] ? fetch_add_u64(acc + F_LIGHT * kPad, tot[0]) : 0ULL;
+      bases[1] = tot[1] ? fetch_add_u64(acc + F_HEAVY * kPad, tot[1]) : 0ULL;
+      bases[2] = tot[2] ? fetch_add_u64(acc + F_QUEUE * kPad, tot[2]) : 0ULL;
+    }
+    __syncthreads();
+    long long ol = static_cast<long long>(bases[0]) + ex[0];
+    long long oh = static_cast<long long>(bases[1]) + ex[1];
+    long long oq = static_cast<long long>(bases[2]) + ex[2];
+    // Runs longer than kExpandMin entries (hub slice sets, high-degree
+    // vertices) are recorded in LDS and written by the whole block below.
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+      if (!nw[k]) continue;
+      const long long s = base + k * BLOCK + threadIdx.x;
+      uint32_t t = nw[k];
+      while (t) {
+        const int b = __builtin_ctz(t);
+        t &= t - 1;
+        const long long u = s * SIGMA + b;
+        const int d = rp[u + 1] - rp[u];
+        if (d > kLightMax) {
+          const int nch = (d + kHeavyChunk - 1) / kHeavyChunk;
+          int r = nch > kExpandMin ? atomicAdd(&nrec, 1) : kMaxExpand;
+          if (r < kMaxExpand) {
+            rec[r] = ExpandRec{static_cast<unsigned long long>(oh), static_cast<uint32_t>(nch), 1u,
+                               static_cast<uint32_t>(u), 0u, 0u, 0u};
+            oh += nch;
+          } else {
+            for (int c = 0; c < d; c += kHeavyChunk)
+              heavy[oh++] = (static_cast<unsigned long long>(u) << 32) | static_cast<unsigned long long>(c);
+          }
+        } else {
+          light[ol++] = static_cast<int32_t>(u);
+        }
+      }
+      const uint32_t s0 = sp[s], ns = sp[s + 1] - s0;
+      const uint32_t nq = (ns + tau - 1) / tau;
+      int r = nq > static_cast<uint32_t>(kExpandMin) ? atomicAdd(&nrec, 1) : kMaxExpand;
+      if (r < kMaxExpand) {
+        rec[r] = ExpandRec{static_cast<unsigned long long>(oq), nq, 0u, s0, ns, static_cast<uint32_t>(nw[k]),
+                           static_cast<uint32_t>(s)};
+        oq += nq;
+      } else {
+        for (uint32_t off = 0; off < ns; off += tau)
+          queue[oq++] =
+              make_uint4(s0 + off, min(tau, ns - off), static_cast<uint32_t>(nw[k]), static_cast<uint32_t>(s));
+      }
+    }
+    __syncthreads();
+    const int nr = min(nrec, kMaxExpand);
+    for (int r = 0; r < nr; ++r) {
+      const ExpandRec e = rec[r];
+      if (e.kind == 0) {
+        for (uint32_t i = threadIdx.x; i < e.n; i += BLOCK) {
+          const uint32_t off = i * tau;
+          queue[e.out + i] = make_uint4(e.a + off, min(tau, e.b - off), e.c, e.d);
+        }
+      } else {
+        for (uint32_t i = threadIdx.x; i < e.n; i += BLOCK)
+          heavy[e.out + i] = (static_cast<unsigned long long>(e.a) << 32) |
+                             static_cast<unsigned long long>(i * static_cast<uint32_t>(kHeavyChunk));
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) nrec = 0;
+    __syncthreads();
+  }
+  block_sum64<BLOCK, 5>(st, lds64);
+  if (threadIdx.x == 0) {
+    if (st[0]) {
+      add_u64(acc + F_FRONTIER * kPad, st[0]);
+      add_u64(acc + F_CUMV * kPad, st[0]);
+    }
+    if (st[1]) add_u64(acc + F_QSLICES * kPad, st[1]);
+    if (st[2]) {
+      add_u64(acc + F_FEDGES * kPad, st[2]);
+      add_u64(acc + F_CUME * kPad, st[2]);
+    }
+    if (st[3]) add_u64(acc + F_DEG32 * kPad, st[3]);
+    if (st[4]) add_u64(acc + F_DEG1024 * kPad, st[4]);
+    if (blockIdx.x == 0) {
+      add_u64(acc + F_CUMV * kPad, cumv_in);
+      add_u64(acc + F_CUME * kPad, cume_in);
+    }
+  }
+}
+
+// ------------------------------------------------------- init and seeding
+
+template <int SIGMA>
+__device__ void clear_state(const BfsArgs& a, long long gtid, long long nthreads) {
+  using M = typename MaskOf<SIGMA>::T;
+  M* vis = static_cast<M*>(a.vis);
+  M* front = static_cast<M*>(a.front);
+  for (long long i = gtid; i < a.n; i += nthreads) a.levels[i] = -1;
+  for (long long s = gtid; s < a.nsets; s += nthreads) {
+    vis[s] = 0;
+    front[s] = 0;
+  }
+  if (blockIdx.x == 0)
+    for (int t = threadIdx.x; t < kStatSlots * kStatFields; t += blockDim.x)
+      a.ctl->acc[t / kStatFields][t % kStatFields][0] = 0ULL;
+}
+
+// Level 0: frontier = {src}, queue = the VSSs of src's slice set. One block.
+template <int SIGMA>
+__device__ void seed_source(const BfsArgs& a) {
+  using M = typename MaskOf<SIGMA>::T;
+  const long long src = a.src;
+  const long long s = src / SIGMA;
+  const M bit = static_cast<M>(M(1) << (src % SIGMA));
+  const uint32_t s0 = a.slice_ptr[s], ns = a.slice_ptr[s + 1] - s0;
+  const uint32_t tau = static_cast<uint32_t>(a.tau);
+  const uint32_t nq = (ns + tau - 1) / tau;
+  const int d = a.rp[src + 1] - a.rp[src];
+  for (uint32_t k = threadIdx.x; k < nq; k += blockDim.x)
+    a.queue[0][k] = make_uint4(s0 + k * tau, min(tau, ns - k * tau), static_cast<uint32_t>(bit), static_cast<uint32_t>(s));
+  const int nh = d > kLightMax ? (d + kHeavyChunk - 1) / kHeavyChunk : 0;
+  for (int c = threadIdx.x; c < nh; c += blockDim.x)
+    a.fheavy[0][c] = (static_cast<unsigned long long>(src) << 32) | static_cast<unsigned long long>(c * kHeavyChunk);
+  if (threadIdx.x == 0) {
+    static_cast<M*>(a.vis)[s] = bit;
+    static_cast<M*>(a.front)[s] = bit;
+    a.levels[a.orig_id ? a.orig_id[src] : src] = 0;
+    if (nh == 0) a.flight[0][0] = static_cast<int32_t>(src);
+    unsigned long long* acc = &a.ctl->acc[0][0][0];
+    acc[F_FRONTIER * kPad] = 1;
+    acc[F_QUEUE * kPad] = nq;
+    acc[F_QSLICES * kPad] = ns;
+    acc[F_FEDGES * kPad] = static_cast<unsigned long long>(d);
+    acc[F_DEG32 * kPad] = d >= 32;
+    acc[F_DEG1024 * kPad] = d >= 1024;
+    acc[F_LIGHT * kPad] = nh == 0 ? 1 : 0;
+    acc[F_HEAVY * kPad] = static_cast<unsigned long long>(nh);
+    acc[F_CUMV * kPad] = 1;
+    acc[F_CUME * kPad] = static_cast<unsigned long long>(d);
+  }
+}
+
+__device__ __forceinline__ void log_level(const BfsArgs& a, int level, const LevelView& v, int engine, int fallback,
+                                          const float (&feat)[kMaxSwitchFeatures]) {
+  if (level >= a.log_cap) return;
+  LevelRec& r = a.log[level];
+  r.frontier = v.frontier;
+  r.queue = v.queue;
+  r.qslices = v.qslices;
+  r.fedges = v.fedges;
+  r.unvisited = a.n - v.cumv;
+  r.unvisited_edges = a.m - v.cume;
+  r.deg32 = v.deg32;
+  r.deg1024 = v.deg1024;
+  r.engine = engine;
+  r.fallback = fallback;
+  r.t_begin = dev_ticks();
+  r.t_mid = 0;
+  r.t_end = 0;
+  r.t_engine[0] = r.t_engine[1] = r.t_engine[2] = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxSwitchFeatures; ++k) r.feat[k] = feat[k];
+}
+
+// ------------------------------------------------------ persistent kernel
+
+template <int SIGMA, class SliceT, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
+  extern __shared__ float s_mlp[];
+  const unsigned nblocks = gridDim.x;
+  const long long nthreads = static_cast<long long>(nblocks) * BLOCK;
+  const long long gtid = static_cast<long long>(blockIdx.x) * BLOCK + threadIdx.x;
+  const long long gwave = static_cast<long long>(blockIdx.x) * (BLOCK / 64) + wave_in_block();
+  const long long nwaves = static_cast<long long>(nblocks) * (BLOCK / 64);
+  const bool learned = a.policy == BLEST_POLICY_LEARNED && a.mlp != nullptr && a.mlp->valid;
+  if (learned) mlp_to_lds(a.mlp, s_mlp);
+  clear_state<SIGMA>(a, gtid, nthreads);
+  BarrierCtx bc;
+  if (!barrier_register(a.ctl, &bc, a.timeout_ticks)) return;
+  if (blockIdx.x == 0) seed_source<SIGMA>(a);
+  if (!grid_barrier(a.ctl, bc)) return;
+  long long prev_frontier = 0;
+  int level = 0;
+  for (;; ++level) {
+    const int slot = level % kStatSlots;
+    const LevelView v = read_level(a.ctl, slot);
+    if (v.frontier == 0) break;
+    float feat[kMaxSwitchFeatures];
+    level_features(feat, v, a.n, a.m, level, prev_frontier);
+    int fallback = 0;
+    const int engine = choose_engine(a, v, feat, level, learned ? s_mlp : nullptr, &fallback);
+    if (blockIdx.x == 0) {
+      if (threadIdx.x == 0) log_level(a, level, v, a.probe ? -1 : engine, fallback, feat);
+      const int nslot = (level + 1) % kStatSlots;
+      for (int t = threadIdx.x; t < kStatFields; t += BLOCK) a.ctl->acc[nslot][t][0] = 0ULL;
+    }
+    const int sel = level & 1;
+    if (a.probe) {
+      for (int e = 0; e < 3; ++e) {
+        const unsigned long long t0 = dev_ticks();
+        run_engine<SIGMA, SliceT>(a, e, sel, v, gtid, nthreads, gwave, nwaves);
+        if (!grid_barrier(a.ctl, bc)) return;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_engine[e] = dev_ticks() - t0;
+      }
+    } else {
+      run_engine<SIGMA, SliceT>(a, engine, sel, v, gtid, nthreads, gwave, nwaves);
+      if (!grid_barrier(a.ctl, bc)) return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_mid = dev_ticks();
+    finalize<SIGMA, BLOCK>(a, level + 1, (level + 1) % kStatSlots, sel ^ 1, v.cumv, v.cume, nblocks);
+    if (!grid_barrier(a.ctl, bc)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_end = dev_ticks();
+    prev_frontier = v.frontier;
+  }
+  if (blockIdx.x == 0) {
+    // Nothing reads the XCD registration after barrier_register; clear it
+    // for the next launch.
+    if (threadIdx.x < 8) a.ctl->xcd_blocks[threadIdx.x][0] = 0u;
+    if (threadIdx.x == 8) a.ctl->xcd_active[0] = 0u;
+    if (threadIdx.x == 0) a.ctl->nlevels[0] = level;
+  }
+}
+
+// ------------------------------------------------------ per-stage kernels
+
+template <int SIGMA, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_bfs_clear(BfsArgs a) {
+  const long long nthreads = static_cast<long long>(gridDim.x) * BLOCK;
+  clear_state<SIGMA>(a, static_cast<long long>(blockIdx.x) * BLOCK + threadIdx.x, nthreads);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->done[0] = 0;
+}
+
+template <int SIGMA, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_bfs_seed(BfsArgs a) {
+  seed_source<SIGMA>(a);
+}
+
+template <int SIGMA, class SliceT, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_bfs_stage1(BfsArgs a, int level, long long prev_slot_frontier_unused) {
+  extern __shared__ float s_mlp[];
+  if (a.ctl->done[0]) return;
+  const unsigned nblocks = gridDim.x;
+  const long long nthreads = static_cast<long long>(nblocks) * BLOCK;
+  const long long gtid = static_cast<long long>(blockIdx.x) * BLOCK + threadIdx.x;
+  const long long gwave = static_cast<long long>(blockIdx.x) * (BLOCK / 64) + wave_in_block();
+  const long long nwaves = static_cast<long long>(nblocks) * (BLOCK / 64);
+  const LevelView v = read_level(a.ctl, level % kStatSlots);
+  if (v.frontier == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.ctl->done[0] = 1;
+      a.ctl->nlevels[0] = level;
+    }
+    return;
+  }
+  const long long prev = level > 0 ? read_level(a.ctl, (level + kStatSlots - 1) % kStatSlots).frontier : 0;
+  const bool learned = a.policy == BLEST_POLICY_LEARNED && a.mlp != nullptr && a.mlp->valid;
+  if (learned) {
+    mlp_to_lds(a.mlp, s_mlp);
+    __syncthreads();
+  }
+  float feat[kMaxSwitchFeatures];
+  level_features(feat, v, a.n, a.m, level, prev);
+  int fallback = 0;
+  const int engine = choose_engine(a, v, feat, level, learned ? s_mlp : nullptr, &fallback);
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) log_level(a, level, v, engine, fallback, feat);
+    const int nslot = (level + 1) % kStatSlots;
+    for (int t = threadIdx.x; t < kStatFields; t += BLOCK) a.ctl->acc[nslot][t][0] = 0ULL;
+  }
+  run_engine<SIGMA, SliceT>(a, engine, level & 1, v, gtid, nthreads, gwave, nwaves);
+}
+
+template <int SIGMA, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_bfs_stage2(BfsArgs a, int level) {
+  if (a.ctl->done[0]) return;
+  const LevelView v = read_level(a.ctl, level % kStatSlots);
+  if (v.frontier == 0) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_mid = dev_ticks();
+  finalize<SIGMA, BLOCK>(a, level + 1, (level + 1) % kStatSlots, (level & 1) ^ 1, v.cumv, v.cume, gridDim.x);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_end = dev_ticks();
+}
+
+// ------------------------------------------------------------ host side
+
+namespace {
+
+template <int SIGMA, class SliceT, int BLOCK>
+const void* persistent_fn() {
+  return reinterpret_cast<const void*>(&k_bfs_persistent<SIGMA, SliceT, BLOCK>);
+}
+
+template <int SIGMA, class SliceT, int BLOCK>
+hipError_t run_t(const DevGraph& g, BfsArgs& a, hipStream_t st) {
+  const size_t shmem = (a.policy == BLEST_POLICY_LEARNED) ? kLdsMlpFloats * sizeof(float) : 0;
+  if (g.persistent || a.probe) {
+    void* args[] = {static_cast<void*>(&a)};
+    return hipLaunchCooperativeKernel(persistent_fn<SIGMA, SliceT, BLOCK>(), dim3(g.grid), dim3(BLOCK), args,
+                                      static_cast<unsigned>(shmem), st);
+  }
+  hipLaunchKernelGGL((k_bfs_clear<SIGMA, BLOCK>), dim3(g.grid), dim3(BLOCK), 0, st, a);
+  hipLaunchKernelGGL((k_bfs_seed<SIGMA, BLOCK>), dim3(1), dim3(BLOCK), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int level = 0;
+  int batch = 4;
+  for (;;) {
+    for (int i = 0; i < batch; ++i, ++level) {
+      hipLaunchKernelGGL((k_bfs_stage1<SIGMA, SliceT, BLOCK>), dim3(g.grid), dim3(BLOCK), shmem, st, a, level, 0LL);
+      hipLaunchKernelGGL((k_bfs_stage2<SIGMA, BLOCK>), dim3(g.grid), dim3(BLOCK), 0, st, a, level);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(g.host_flags, &g.ctl->done[0], sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    if (g.host_flags[0]) break;
+    if (level > g.n + 2) return hipErrorUnknown;
+    batch = batch < 64 ? batch * 2 : 64;
+  }
+  return hipSuccess;
+}
+
+template <int SIGMA, class SliceT>
+hipError_t run_block(const DevGraph& g, BfsArgs& a, hipStream_t st) {
+  switch (g.block) {
+    case 256:
+      return run_t<SIGMA, SliceT, 256>(g, a, st);
+    case 1024:
+      return run_t<SIGMA, SliceT, 1024>(g, a, st);
+    default:
+      return run_t<SIGMA, SliceT, 512>(g, a, st);
+  }
+}
+
+template <int SIGMA, class SliceT>
+hipError_t occupancy_block(const DevGraph& g, size_t shmem, int* nb) {
+  switch (g.block) {
+    case 256:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, persistent_fn<SIGMA, SliceT, 256>(), 256, shmem);
+    case 1024:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, persistent_fn<SIGMA, SliceT, 1024>(), 1024, shmem);
+    default:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, persistent_fn<SIGMA, SliceT, 512>(), 512, shmem);
+  }
+}
+
+}  // namespace
+
+BfsArgs bfs_args(const DevGraph& g) {
+  BfsArgs a{};
+  a.rp = g.rp;
+  a.col = g.col;
+  a.slice_ptr = g.slice_ptr;
+  a.slices = g.slices;
+  a.degmask = g.degmask;
+  a.orig_id = g.orig_id;
+  a.n = g.n;
+  a.m = g.m;
+  a.nsets = g.nsets;
+  a.tau = g.tau;
+  a.vis = g.vis;
+  a.front = g.front;
+  a.mark = g.mark;
+  for (int i = 0; i < 2; ++i) {
+    a.queue[i] = g.queue[i];
+    a.flight[i] = g.flight[i];
+    a.fheavy[i] = g.fheavy[i];
+  }
+  a.ctl = g.ctl;
+  a.log = g.log;
+  a.log_cap = g.log_cap;
+  a.mlp = g.mlp;
+  a.prefilter = g.prefilter;
+  a.timeout_ticks = 1000000000ULL;  // 10 s at the 100 MHz device clock
+  return a;
+}
+
+hipError_t bfs_run(const DevGraph& g, BfsArgs a, hipStream_t st) {
+  if (g.sigma == 8 && !g.wide) return run_block<8, uint32_t>(g, a, st);
+  if (g.sigma == 8) return run_block<8, uint64_t>(g, a, st);
+  if (g.sigma == 16) return run_block<16, uint64_t>(g, a, st);
+  return run_block<32, uint64_t>(g, a, st);
+}
+
+hipError_t bfs_grid_size(const DevGraph& g, int policy_learned, int blocks_per_cu, int* grid) {
+  const size_t shmem = policy_learned ? kLdsMlpFloats * sizeof(float) : 0;
+  int nb = 0;
+  hipError_t e;
+  if (g.sigma == 8 && !g.wide)
+    e = occupancy_block<8, uint32_t>(g, shmem, &nb);
+  else if (g.sigma == 8)
+    e = occupancy_block<8, uint64_t>(g, shmem, &nb);
+  else if (g.sigma == 16)
+    e = occupancy_block<16, uint64_t>(g, shmem, &nb);
+  else
+    e = occupancy_block<32, uint64_t>(g, shmem, &nb);
+  if (e != hipSuccess) return e;
+  if (nb < 1) return hipErrorInvalidConfiguration;
+  if (blocks_per_cu > 0 && blocks_per_cu < nb) nb = blocks_per_cu;
+  *grid = nb * g.num_cu;
+  return hipSuccess;
+}
+
+}  // namespace blest

@@ -1,0 +1,147 @@
+// Internal structures of the BVSS BFS library (host + device).
+//
+// Device data of one graph (internal vertex ids, after optional RCM):
+//   rp[n+1], col[m]          CSR copy (int32), used by the push and pull engines
+//   slice_ptr[N_s+1]         first slice of each slice set (uint32)
+//   slices[n_slices]         one word per slice, ascending row within a set:
+//                            32-bit  (row << 8)  | mask   when sigma = 8, n <= 2^24
+//                            64-bit  (row << 32) | mask   otherwise
+//   degmask[N_s]             sigma-bit mask of vertices with degree > 0
+//   orig_id[n]               internal id -> input id (NULL when not reordered)
+// A virtual slice set (VSS) is a run of at most tau consecutive slices of one
+// slice set, so VSS k of set s covers slices [slice_ptr[s] + k*tau, ...). The
+// queue holds one 16-byte descriptor per VSS (first slice, count, frontier
+// bits of its set, set id) instead of padding every VSS to tau slices.
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+#include "blest.h"
+
+namespace blest {
+
+constexpr int kStatFields = 12;     // accumulated by Stage 2, one 256-byte line each
+constexpr int kStatSlots = 3;       // rotating per-level slots
+constexpr int kPad = 32;            // 32 x 8 bytes = 256 bytes
+constexpr int kMaxSwitchFeatures = 12;
+
+enum StatField : int {
+  F_FRONTIER = 0,  // new frontier vertices (also the frontier-list append cursor)
+  F_QUEUE = 1,     // VSS descriptors enqueued (also the queue append cursor)
+  F_QSLICES = 2,   // slices covered by those descriptors
+  F_FEDGES = 3,    // sum of degrees of new frontier vertices
+  F_DEG32 = 4,     // new frontier vertices with degree >= 32
+  F_DEG1024 = 5,   // ... >= 1024
+  F_LIGHT = 6,     // light-vertex list append cursor (push engine)
+  F_HEAVY = 7,     // heavy-vertex edge-chunk list append cursor (push engine)
+  F_CUMV = 8,      // vertices visited through this level
+  F_CUME = 9,      // sum of degrees of those vertices
+};
+
+// Push-engine work split: vertices of degree <= kLightMax are walked by one
+// lane; larger ones are cut into chunks of kHeavyChunk edges walked by a wave.
+constexpr int kLightMax = 32;
+constexpr int kHeavyChunk = 256;
+
+// Device control block. Fields that many workgroups update sit on their own
+// 256-byte lines.
+struct alignas(256) Ctl {
+  unsigned long long acc[kStatSlots][kStatFields][kPad];
+  unsigned int bar_count[kPad * 2];      // top-level arrivals (one per XCD leader, or per block)
+  unsigned int bar_gen[kPad * 2];        // top-level generation
+  unsigned int xcd_count[8][kPad];       // per-XCD arrivals
+  unsigned int xcd_gen[8][kPad];         // per-XCD release flags
+  unsigned int xcd_blocks[8][kPad];      // blocks of this launch resident on each XCD
+  unsigned int xcd_active[kPad];         // number of XCDs with at least one block
+  int error[kPad * 2];   // first device-side error (BLEST_ERR_*), 0 if none
+  int done[kPad * 2];    // per-stage launch mode: 1 once the frontier is empty
+  int overflow[kPad * 2];
+  int nlevels[kPad * 2]; // frontier levels of the last traversal
+};
+
+// One record per frontier level, written by workgroup 0 of the persistent kernel.
+struct LevelRec {
+  long long frontier, queue, qslices, fedges, unvisited, unvisited_edges, deg32, deg1024;
+  unsigned long long t_begin;     // device clock (100 MHz) when the step started
+  unsigned long long t_mid;       // ... when Stage 1 ended (after its barrier)
+  unsigned long long t_end;       // ... when its finalisation ended
+  unsigned long long t_engine[3]; // probe mode: ticks of each engine
+  int engine;
+  int fallback;
+  float feat[kMaxSwitchFeatures];
+};
+
+struct MlpDev {
+  float params[BLEST_MLP_NPARAMS];
+  float mean[BLEST_MLP_IN];
+  float inv_std[BLEST_MLP_IN];
+  int valid;
+};
+
+// Kernel arguments of one single-source traversal (passed by value).
+struct BfsArgs {
+  const int32_t* rp;
+  const int32_t* col;
+  const uint32_t* slice_ptr;
+  const void* slices;
+  const void* degmask;
+  const int32_t* orig_id;
+  int64_t n, m, nsets;
+  int32_t tau;
+  // working state
+  void* vis;       // sigma-bit visited word per slice set (V_curr)
+  void* front;     // sigma-bit frontier word per slice set (F_curr)
+  uint8_t* mark;   // one byte per vertex: lazily marked in Stage 1 (V_next)
+  uint4* queue[2]; // VSS descriptors {first slice, count, frontier bits, set}
+  int32_t* flight[2];             // light frontier vertices
+  unsigned long long* fheavy[2];  // heavy frontier edge chunks: (vertex << 32) | first edge offset
+  Ctl* ctl;
+  LevelRec* log;
+  int32_t log_cap;
+  const MlpDev* mlp;
+  int32_t* levels; // output, input ids
+  int32_t src;     // internal id
+  int32_t policy;
+  float eta;
+  uint64_t seed;
+  int32_t probe;
+  int32_t prefilter;
+  unsigned long long timeout_ticks;
+};
+
+// Device-resident graph and working buffers (owned by one blest_graph).
+struct DevGraph {
+  int device = 0;
+  int sigma = 8, tau = 128, wide = 0;
+  int64_t n = 0, m = 0, nsets = 0, nvss = 0, nslices = 0, nheavy_cap = 0;
+  int32_t* rp = nullptr;
+  int32_t* col = nullptr;
+  uint32_t* slice_ptr = nullptr;
+  void* slices = nullptr;
+  void* degmask = nullptr;
+  int32_t* orig_id = nullptr;
+  void* vis = nullptr;
+  void* front = nullptr;
+  uint8_t* mark = nullptr;
+  uint4* queue[2] = {nullptr, nullptr};
+  int32_t* flight[2] = {nullptr, nullptr};
+  unsigned long long* fheavy[2] = {nullptr, nullptr};
+  Ctl* ctl = nullptr;
+  LevelRec* log = nullptr;
+  int log_cap = 0;
+  MlpDev* mlp = nullptr;
+  int* host_flags = nullptr;  // pinned: done flag readback of the per-stage mode
+  int block = 512, grid = 0, num_cu = 0, persistent = 1, prefilter = 1;
+  double tick_us = 0.01;      // device clock period in microseconds
+};
+
+// Single-source traversal on the device (bfs.hip). Returns a HIP error;
+// device-side errors are left in ctl->error.
+hipError_t bfs_run(const DevGraph& g, BfsArgs a, hipStream_t st);
+// Largest co-resident grid of the persistent kernel for this graph.
+hipError_t bfs_grid_size(const DevGraph& g, int policy_learned, int blocks_per_cu, int* grid);
+BfsArgs bfs_args(const DevGraph& g);
+
+}  // namespace blest

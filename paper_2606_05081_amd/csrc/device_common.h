@@ -1,0 +1,274 @@
+// Device-side helpers shared by the traversal kernels: wave/block scans and
+// reductions, the device-wide barrier, clocks and mask types.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "blest_internal.h"
+
+namespace blest {
+
+template <int SIGMA>
+struct MaskOf;
+template <>
+struct MaskOf<8> {
+  using T = uint8_t;
+};
+template <>
+struct MaskOf<16> {
+  using T = uint16_t;
+};
+template <>
+struct MaskOf<32> {
+  using T = uint32_t;
+};
+
+// Slice word layout: mask in the low bits, row above it.
+template <class SliceT>
+struct SliceFmt;
+template <>
+struct SliceFmt<uint32_t> {
+  static constexpr int kRowShift = 8;
+};
+template <>
+struct SliceFmt<uint64_t> {
+  static constexpr int kRowShift = 32;
+};
+
+__device__ __forceinline__ unsigned long long dev_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+__device__ __forceinline__ int lane_id() { return static_cast<int>(threadIdx.x & 63u); }
+
+// Wave index inside the block, known uniform to the compiler.
+__device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6)); }
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T x = __shfl_up(v, d, 64);
+    if (lane >= d) v += x;
+  }
+  return v;
+}
+
+// Exclusive block scan of N int counters; tot[] receives the block totals.
+// lds must hold N * (BLOCK / 64) ints. Contains two __syncthreads().
+template <int BLOCK, int N>
+__device__ __forceinline__ void block_exclusive_scan(const int (&v)[N], int (&excl)[N], int (&tot)[N], int* lds) {
+  constexpr int W = BLOCK / 64;
+  const int lane = lane_id(), w = static_cast<int>(threadIdx.x >> 6);
+  int inc[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    inc[k] = wave_inclusive_scan(v[k]);
+    if (lane == 63) lds[k * W + w] = inc[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    int before = 0, all = 0;
+    for (int i = 0; i < W; ++i) {
+      int x = lds[k * W + i];
+      before += (i < w) ? x : 0;
+      all += x;
+    }
+    excl[k] = before + inc[k] - v[k];
+    tot[k] = all;
+  }
+  __syncthreads();
+}
+
+// Block sum of N int64 values, result valid in thread 0. lds: N * (BLOCK/64) slots.
+template <int BLOCK, int N>
+__device__ __forceinline__ void block_sum64(long long (&v)[N], long long* lds) {
+  constexpr int W = BLOCK / 64;
+  const int lane = lane_id(), w = static_cast<int>(threadIdx.x >> 6);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    long long s = wave_sum(v[k]);
+    if (lane == 0) lds[k * W + w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      long long s = 0;
+      for (int i = 0; i < W; ++i) s += lds[k * W + i];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ unsigned long long ld_acquire_u64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_relaxed_u64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void add_u64(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long fetch_add_u64(unsigned long long* p, unsigned long long v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned xcc_id() {
+  unsigned v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return v & 7u;
+}
+
+// Device-wide barrier for a cooperative (co-resident) grid.
+//
+// The eight XCDs of MI355X each have a private L2 that is not coherent with
+// the others, so data written before the barrier must be written back to
+// memory (buffer_wbl2) and readers must invalidate (buffer_inv) after it.
+// Arrival is hierarchical: every wave waits for its own stores to be
+// acknowledged (s_waitcnt 0), the block's thread 0 arrives on its XCD's
+// counter, and the last block of each XCD -- whose L2 now holds every store
+// of that XCD -- performs one agent-scope release (one L2 write-back per XCD
+// instead of one per block) and arrives on the top-level counter. The last
+// XCD leader acquires, resets the counter and bumps the generation; each XCD
+// leader then forwards the release to its XCD's flag, which that XCD's blocks
+// poll with relaxed loads before a single acquire fence. Blocks per XCD are
+// counted at kernel start (barrier_register), so no dispatch order is
+// assumed. Every spin is bounded by `timeout` device-clock ticks and by the
+// error flag, so every wave leaves even if a block never arrives. Returns
+// false (uniformly in the block) when the traversal must stop.
+struct BarrierCtx {
+  unsigned xcc;        // this block's XCD
+  unsigned nlocal;     // blocks on this XCD
+  unsigned nxcd;       // XCDs with blocks
+  unsigned long long timeout;
+};
+
+__device__ __forceinline__ bool spin_until_changed(const unsigned* flag, unsigned old, Ctl* ctl,
+                                                   unsigned long long t0, unsigned long long timeout) {
+  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == old) {
+    if (__hip_atomic_load(&ctl->error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    if (dev_ticks() - t0 > timeout) {
+      __hip_atomic_store(&ctl->error[0], static_cast<int>(BLEST_ERR_TIMEOUT), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+__device__ __forceinline__ bool grid_barrier(Ctl* ctl, const BarrierCtx& bc) {
+  __shared__ int ok_flag;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned long long t0 = dev_ticks();
+    const unsigned x = bc.xcc;
+    const unsigned g = __hip_atomic_load(&ctl->xcd_gen[x][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned p = __hip_atomic_fetch_add(&ctl->xcd_count[x][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (p == bc.nlocal - 1) {
+      __hip_atomic_store(&ctl->xcd_count[x][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned gg = __hip_atomic_load(&ctl->bar_gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned q = __hip_atomic_fetch_add(&ctl->bar_count[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (q == bc.nxcd - 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __hip_atomic_store(&ctl->bar_count[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->bar_gen[0], gg + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        ok = spin_until_changed(&ctl->bar_gen[0], gg, ctl, t0, bc.timeout);
+      }
+      __hip_atomic_store(&ctl->xcd_gen[x][0], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      ok = spin_until_changed(&ctl->xcd_gen[x][0], g, ctl, t0, bc.timeout);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (__hip_atomic_load(&ctl->error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
+    ok_flag = ok;
+  }
+  __syncthreads();
+  return ok_flag != 0;
+}
+
+// Counts the blocks of this launch on each XCD. Must be the first grid-wide
+// step of a persistent kernel; it uses a flat barrier on bar_count/bar_gen
+// (one release RMW per block) because the per-XCD counts are not known yet.
+// The host zeroes xcd_blocks/xcd_active before every launch.
+__device__ __forceinline__ bool barrier_register(Ctl* ctl, BarrierCtx* bc, unsigned long long timeout) {
+  __shared__ unsigned s_xcc, s_nlocal, s_nxcd;
+  __shared__ int ok_flag;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned x = xcc_id();
+    const unsigned prevx = __hip_atomic_fetch_add(&ctl->xcd_blocks[x][0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (prevx == 0) __hip_atomic_fetch_add(&ctl->xcd_active[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    const unsigned long long t0 = dev_ticks();
+    const unsigned gg = __hip_atomic_load(&ctl->bar_gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned q = __hip_atomic_fetch_add(&ctl->bar_count[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (q == gridDim.x - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(&ctl->bar_count[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->bar_gen[0], gg + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      ok = spin_until_changed(&ctl->bar_gen[0], gg, ctl, t0, timeout);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_xcc = x;
+    s_nlocal = __hip_atomic_load(&ctl->xcd_blocks[x][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_nxcd = __hip_atomic_load(&ctl->xcd_active[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ok_flag = ok;
+  }
+  __syncthreads();
+  bc->xcc = s_xcc;
+  bc->nlocal = s_nlocal;
+  bc->nxcd = s_nxcd;
+  bc->timeout = timeout;
+  return ok_flag != 0;
+}
+
+// Number of sigma-byte marks of a slice set that are set, as a sigma-bit word.
+// Marks are 0 or 1 per byte; (x * 0x0102040810204080) >> 56 gathers the low
+// bit of each of the 8 bytes of x into one byte, byte i -> bit i.
+__device__ __forceinline__ uint32_t gather8(unsigned long long x) {
+  return static_cast<uint32_t>((x * 0x0102040810204080ULL) >> 56);
+}
+
+template <int SIGMA>
+__device__ __forceinline__ typename MaskOf<SIGMA>::T load_marks(const uint8_t* p) {
+  if constexpr (SIGMA == 8) {
+    return static_cast<uint8_t>(gather8(*reinterpret_cast<const unsigned long long*>(p)));
+  } else if constexpr (SIGMA == 16) {
+    ulonglong2 x = *reinterpret_cast<const ulonglong2*>(p);
+    return static_cast<uint16_t>(gather8(x.x) | (gather8(x.y) << 8));
+  } else {
+    ulonglong2 x = *reinterpret_cast<const ulonglong2*>(p);
+    ulonglong2 y = *reinterpret_cast<const ulonglong2*>(p + 16);
+    return gather8(x.x) | (gather8(x.y) << 8) | (gather8(y.x) << 16) | (gather8(y.y) << 24);
+  }
+}
+
+template <int SIGMA>
+__device__ __forceinline__ void clear_marks(uint8_t* p) {
+  if constexpr (SIGMA == 8) {
+    *reinterpret_cast<unsigned long long*>(p) = 0ULL;
+  } else if constexpr (SIGMA == 16) {
+    *reinterpret_cast<ulonglong2*>(p) = make_ulonglong2(0ULL, 0ULL);
+  } else {
+    *reinterpret_cast<ulonglong2*>(p) = make_ulonglong2(0ULL, 0ULL);
+    *reinterpret_cast<ulonglong2*>(p + 16) = make_ulonglong2(0ULL, 0ULL);
+  }
+}
+
+}  // namespace blest

@@ -1,0 +1,41 @@
+// Multi-source BFS and closeness (msbfs.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "blest_internal.h"
+
+namespace blest {
+
+// Device buffers of the multi-source traversal, sized for the widest batch
+// (kappa = 64 * wmax bits per vertex) on first use.
+struct MsDev {
+  int device = 0;
+  int wmax = 0;
+  int64_t nhat = 0;
+  unsigned long long* F = nullptr;   // frontier words, getVI-ordered, W per vertex
+  unsigned long long* V = nullptr;   // visited words
+  unsigned long long* N = nullptr;   // next marks (atomic OR targets)
+  unsigned long long* act = nullptr; // per slice set: sources active in it
+  uint8_t* dirty = nullptr;          // per slice set: marked in Stage 1
+  uint4* queue[2] = {nullptr, nullptr};
+  int32_t* srcs = nullptr;           // internal ids of all sources of a call
+  int64_t srcs_cap = 0;
+  long long* part = nullptr;         // per-block partial sums and reach
+  int part_blocks = 0;
+  void* batches = nullptr;           // batch descriptors
+  int batches_cap = 0;
+  int grid = 0, block = 512;
+};
+
+// Runs all sources in batches of `width` sources (64..512) in one persistent
+// launch. levels16 (k*n, source-major, input ids) and/or sums/reach/cc may be
+// NULL. Device-side errors (overflow, timeout) are left in g.ctl->error.
+hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs_internal, int32_t k, int width,
+                  int16_t* levels16, int64_t* sums, int64_t* reach, double* cc, hipStream_t st);
+void ms_release(MsDev* ms);
+void ms_reset(MsDev* ms);
+
+}  // namespace blest

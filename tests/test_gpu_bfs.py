@@ -1,0 +1,223 @@
+"""Single-source BFS on the GPU, through the C ABI, against the CPU oracle.
+
+Levels are integers with one correct value, so every comparison is exact
+(array equality). Sizes span many wavefront tiles and ragged tails; the
+full-size workloads (R-MAT scale 22, 2048x2048 grid) are checked exactly on
+sampled sources and by the O(m) distance certificate.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_05081_amd import inputs
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+POLICIES = ["HEURISTIC", "BVSS", "PUSH", "BOTTOM_UP", "RANDOM"]
+
+
+@pytest.fixture(scope="module")
+def blest():
+    import torch
+    from paper_2606_05081_amd import blest as b
+    assert torch.cuda.is_available()
+    b.lib()
+    return b
+
+
+def run_all_policies(blest, g, src, ref, seeds=(1, 2, 3)):
+    for pol in POLICIES:
+        for sd in (seeds if pol == "RANDOM" else (1,)):
+            g.set_policy(getattr(blest.Policy, pol), 10.0, sd)
+            lev = g.bfs(src).cpu().numpy()
+            assert np.array_equal(lev, ref), (pol, sd, src, np.nonzero(lev != ref)[0][:10])
+
+
+@pytest.mark.parametrize("name", ["path", "cycle", "star", "hypercube", "grid40perm", "bipartite", "gnp"])
+def test_closed_form_families(blest, name):
+    if name == "path":
+        rp, col = H.path(1000)
+    elif name == "cycle":
+        rp, col = H.cycle(777)
+    elif name == "star":
+        rp, col = H.star(3000)
+    elif name == "hypercube":
+        rp, col = H.hypercube(12)
+    elif name == "grid40perm":
+        rp0, col0 = inputs.grid(40, 0.0, seed=1, permute=False)
+        rp, col, _ = inputs.permute(rp0, col0, seed=3)
+    elif name == "bipartite":
+        rp, col = H.complete_bipartite(37, 91)
+    else:
+        rp, col = H.gnp(300, 0.02, 5)
+    g = blest.Graph(rp, col)
+    n = rp.size - 1
+    for src in {0, n // 3, n - 1}:
+        run_all_policies(blest, g, src, oracle.bfs(rp, col, src))
+    g.close()
+
+
+def test_rmat_s16_all_policies(blest):
+    """Scale-16 R-MAT (65,536 vertices, edge factor 16, a,b,c = .57,.19,.19)."""
+    rp, col = inputs.rmat_graph(16, 1010)
+    g = blest.Graph(rp, col)
+    srcs = inputs.sources(rp, 4, seed=1011)
+    for s in srcs:
+        run_all_policies(blest, g, int(s), oracle.bfs(rp, col, int(s)))
+    g.close()
+
+
+@pytest.mark.parametrize("opt", [
+    dict(sigma=16), dict(sigma=32), dict(tau=64), dict(tau=256), dict(tau=192), dict(wide_slices=1),
+    dict(block_size=256), dict(block_size=1024), dict(persistent=0), dict(prefilter=0), dict(reorder=1),
+    dict(reorder=0), dict(blocks_per_cu=1), dict(sigma=16, tau=64, block_size=256, persistent=0),
+])
+def test_option_matrix(blest, opt):
+    for rp, col in [inputs.rmat_graph(13, 77), inputs.grid_graph(70, 78)]:
+        g = blest.Graph(rp, col, **opt)
+        for s in inputs.sources(rp, 2, seed=79):
+            run_all_policies(blest, g, int(s), oracle.bfs(rp, col, int(s)), seeds=(4,))
+        g.close()
+
+
+def test_edge_cases(blest):
+    # ragged n (not a multiple of sigma), isolated source, unreachable parts
+    rp, col = inputs.from_pairs(13, [0, 1, 2, 5, 6], [1, 2, 3, 6, 7])
+    g = blest.Graph(rp, col)
+    for s in range(13):
+        run_all_policies(blest, g, s, oracle.bfs(rp, col, s))
+    g.close()
+    # no edges at all
+    rp, col = inputs.from_pairs(9, [], [])
+    g = blest.Graph(rp, col)
+    run_all_policies(blest, g, 4, oracle.bfs(rp, col, 4))
+    g.close()
+    # a single vertex
+    g = blest.Graph(np.array([0, 0], np.int32), np.zeros(0, np.int32))
+    assert g.bfs(0).cpu().tolist() == [0]
+    g.close()
+
+
+def test_errors(blest):
+    rp, col = H.path(10)
+    g = blest.Graph(rp, col)
+    for bad in (-1, 10, 1 << 30):
+        with pytest.raises(blest.BlestError) as ei:
+            g.bfs(bad)
+        assert ei.value.status == blest.Status.OUT_OF_RANGE
+    assert np.array_equal(g.bfs(3).cpu().numpy(), np.abs(np.arange(10) - 3))  # still usable
+    g.close()
+
+
+def test_bvss_export_matches_oracle_and_fig1(blest, golden):
+    from tests.test_oracle_pins import bits_lsb_first, fig1_graph
+    fig = golden("fig1_bvss.txt")
+    rp, col = fig1_graph()
+    g = blest.Graph(rp, col, tau=64, reorder=0)
+    b = g.export_bvss()
+    ob = oracle.bvss(rp, col, 8, 64)
+    for k in ("real_ptrs", "v2r", "slice_ptr", "slice_row", "slice_mask"):
+        assert np.array_equal(b[k].astype(np.int64), ob[k].astype(np.int64)), k
+    lo, hi = b["slice_ptr"][2], b["slice_ptr"][3]
+    rows = b["slice_row"][lo:hi].tolist()
+    assert int(b["slice_mask"][lo + rows.index(3)]) == bits_lsb_first(fig["mask_row3_set2"][0])
+    lev = g.bfs(17).cpu().numpy()
+    assert lev[3] == 1
+    g.close()
+    for sigma, tau, wide in [(8, 128, 0), (8, 256, 1), (16, 64, 1), (32, 192, 1)]:
+        rp, col = inputs.rmat_graph(11, 5)
+        g = blest.Graph(rp, col, sigma=sigma, tau=tau, wide_slices=wide, reorder=0)
+        b = g.export_bvss()
+        ob = oracle.bvss(rp, col, sigma, tau)
+        for k in ("real_ptrs", "v2r", "slice_ptr", "slice_row", "slice_mask"):
+            assert np.array_equal(b[k].astype(np.int64), ob[k].astype(np.int64)), (k, sigma, tau)
+        g.close()
+
+
+def test_rcm_export_is_bvss_of_permuted_graph(blest):
+    rp, col = inputs.grid_graph(50, 9)
+    g = blest.Graph(rp, col, reorder=1)
+    b = g.export_bvss()
+    assert g.info()["reordered"] == 1
+    perm = b["perm"]
+    assert sorted(perm.tolist()) == list(range(rp.size - 1))
+    # relabel the input by perm and rebuild the oracle BVSS
+    n = rp.size - 1
+    u = np.repeat(np.arange(n), np.diff(rp))
+    rp2, col2 = inputs.from_pairs(n, perm[u], perm[col])
+    ob = oracle.bvss(rp2, col2, 8, 128)
+    for k in ("real_ptrs", "slice_ptr", "slice_row", "slice_mask"):
+        assert np.array_equal(b[k].astype(np.int64), ob[k].astype(np.int64)), k
+    g.close()
+
+
+def test_level_log_matches_oracle_counts_and_eq3_replay(blest):
+    for rp, col in [inputs.rmat_graph(16, 1010), inputs.grid_graph(96, 4)]:
+        g = blest.Graph(rp, col, reorder=0)
+        b = g.export_bvss()
+        for s in inputs.sources(rp, 3, seed=12):
+            s = int(s)
+            g.set_policy(blest.Policy.HEURISTIC, 10.0)
+            g.bfs(s)
+            ref = oracle.bfs(rp, col, s)
+            stats = g.level_stats()
+            cnt = oracle.level_counts(ref)
+            assert [r["frontier"] for r in stats] == cnt.tolist()
+            rep = oracle.switch_replay(ref, rp, b["real_ptrs"], 8, eta=10.0)
+            assert [r["queue"] for r in stats] == [r["queue"] for r in rep]
+            assert [r["unvisited"] for r in stats] == [r["unvisited"] for r in rep]
+            dec = [r["engine"] == blest.Engine.BOTTOM_UP for r in stats[:-1]]
+            assert dec == [r["bottom_up"] for r in rep[:-1]]
+            deg = np.diff(rp)
+            for r in stats:
+                fr = ref == r["level"]
+                assert r["frontier_edges"] == int(deg[fr].sum())
+                assert r["deg_ge_32"] == int((deg[fr] >= 32).sum())
+        g.close()
+
+
+def test_relabelling_equivariance(blest):
+    rp, col = inputs.rmat_graph(14, 31)
+    rp2, col2, perm = inputs.permute(rp, col, seed=32)
+    g1, g2 = blest.Graph(rp, col), blest.Graph(rp2, col2)
+    for s in inputs.sources(rp, 3, seed=33):
+        a = g1.bfs(int(s)).cpu().numpy()
+        b = g2.bfs(int(perm[s])).cpu().numpy()
+        assert np.array_equal(b[perm], a)
+    g1.close()
+    g2.close()
+
+
+def test_probe_mode_same_levels_and_times(blest):
+    rp, col = inputs.rmat_graph(15, 41)
+    g = blest.Graph(rp, col)
+    s = int(inputs.sources(rp, 1, seed=42)[0])
+    lev = g.bfs_probe(s).cpu().numpy()
+    assert np.array_equal(lev, oracle.bfs(rp, col, s))
+    st = g.level_stats()
+    assert all(min(r["t_engine_us"]) > 0 for r in st[:-1])
+    g.close()
+
+
+@pytest.mark.parametrize("which", ["rmat22", "grid2048"])
+def test_full_size_sampled_sources(blest, which):
+    """The single-GPU workload at full size: 4,194,304-vertex R-MAT (scale 22,
+    edge factor 16) and 2048x2048 grid with 10% edge deletion (RCM-reordered)."""
+    if which == "rmat22":
+        rp, col = inputs.rmat_graph(22, 1020)
+        srcs = inputs.sources(rp, 64, seed=1021)
+    else:
+        rp, col = inputs.grid_graph(2048, 1022)
+        srcs = inputs.sources(rp, 64, seed=1023)
+    print(f"[{which}] n={rp.size - 1} m={col.size}", flush=True)
+    g = blest.Graph(rp, col)
+    for i, s in enumerate(srcs[:3]):
+        s = int(s)
+        for pol in ("HEURISTIC", "BVSS"):
+            g.set_policy(getattr(blest.Policy, pol), 10.0)
+            lev = g.bfs(s).cpu().numpy()
+            assert oracle.certificate(rp, col, s, lev) == (0, -1), pol
+            if i == 0:
+                assert np.array_equal(lev, oracle.bfs(rp, col, s)), pol
+    g.close()
