@@ -127,6 +127,13 @@ blest_status blest_bfs_probe(blest_graph* g, int32_t src, int32_t* levels_dev, v
  * INVALID_ARG, TIMEOUT, HIP. */
 blest_status blest_msbfs(blest_graph* g, const int32_t* srcs_host, int32_t k, int16_t* levels_dev, void* stream);
 
+/* Multi-source BFS with an explicit batch plan: the k sources are split, in
+ * order, into consecutive batches of widths[0], widths[1], ... sources (each
+ * 64, 128, 256 or 512; the last width repeats), all run in one persistent
+ * launch. Output and errors as blest_msbfs. */
+blest_status blest_msbfs_batched(blest_graph* g, const int32_t* srcs_host, int32_t k, const int32_t* widths_host,
+                                 int32_t nwidths, int16_t* levels_dev, void* stream);
+
 /* Closeness inputs per source (Eq. 4, Eq. 5, normalised per source):
  * sums_dev[c] = sum of d(srcs[c], v) over reachable v (int64),
  * reach_dev[c] = number of reachable vertices including srcs[c] (int64),
@@ -179,6 +186,8 @@ typedef struct {
   double t_engine_us[3];/* probe mode: time of each engine from the same state; else -1 */
   int32_t mlp_fallback; /* learned policy: 1 if Eq. 3 was used (input out of range) */
   int32_t reserved;
+  int64_t work;         /* adjacency entries read by the step's engine: slices (BVSS),
+                           CSR edges (push, bottom-up); probe mode: all three engines */
 } blest_level_stat;
 
 /* Copies up to cap records of the last BFS to buf (host); *nlevels = number

@@ -88,7 +88,7 @@ class LevelStat(ctypes.Structure):
                 ("unvisited", ctypes.c_int64), ("unvisited_edges", ctypes.c_int64), ("deg_ge_32", ctypes.c_int64),
                 ("deg_ge_1024", ctypes.c_int64), ("t_step_us", ctypes.c_double), ("t_stage1_us", ctypes.c_double),
                 ("t_engine_us", ctypes.c_double * 3),
-                ("mlp_fallback", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("mlp_fallback", ctypes.c_int32), ("reserved", ctypes.c_int32), ("work", ctypes.c_int64)]
 
 
 # Every exported symbol of the C ABI: name -> (restype, argtypes).
@@ -106,6 +106,7 @@ SIGNATURES = {
     "blest_bfs": (_i32, [_vp, _i32, _vp, _vp]),
     "blest_bfs_probe": (_i32, [_vp, _i32, _vp, _vp]),
     "blest_msbfs": (_i32, [_vp, _p32, _i32, _vp, _vp]),
+    "blest_msbfs_batched": (_i32, [_vp, _p32, _i32, _p32, _i32, _vp, _vp]),
     "blest_closeness": (_i32, [_vp, _p32, _i64, _vp, _vp, _vp, _vp]),
     "blest_sync": (_i32, [_vp, _vp]),
     "blest_set_policy": (_i32, [_vp, _i32, _f32, _u64]),
@@ -195,6 +196,13 @@ def blest_bfs_probe(h, src: int, levels: torch.Tensor, stream=None):
 def blest_msbfs(h, srcs, levels: torch.Tensor, stream=None):
     s = np.ascontiguousarray(srcs, dtype=np.int32)
     _check(lib().blest_msbfs(h, s.ctypes.data_as(_p32) if s.size else None, s.size, _ptr(levels), _stream(stream)))
+
+
+def blest_msbfs_batched(h, srcs, widths, levels: torch.Tensor, stream=None):
+    s = np.ascontiguousarray(srcs, dtype=np.int32)
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    _check(lib().blest_msbfs_batched(h, s.ctypes.data_as(_p32) if s.size else None, s.size, w.ctypes.data_as(_p32),
+                                     w.size, _ptr(levels), _stream(stream)))
 
 
 def blest_closeness(h, srcs, sums, reach, cc, stream=None):
@@ -293,6 +301,13 @@ class Graph:
         if out is None:
             out = torch.empty((k, self.n), dtype=torch.int16, device=self.device)
         blest_msbfs(self._h, srcs, out, stream)
+        return out
+
+    def msbfs_batched(self, srcs, widths, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        k = len(srcs)
+        if out is None:
+            out = torch.empty((k, self.n), dtype=torch.int16, device=self.device)
+        blest_msbfs_batched(self._h, srcs, widths, out, stream)
         return out
 
     def closeness(self, srcs, stream=None):

@@ -73,7 +73,7 @@ void release(blest_graph* g) {
   g->allocations.clear();
   if (g->d.host_flags) (void)hipHostFree(g->d.host_flags);
   g->d.host_flags = nullptr;
-  blest::ms_release(&g->ms);
+  blest::ms_free_all(&g->ms);
 }
 
 blest_status check_device(int want, int* dev, int* num_cu, double* tick_us) {
@@ -398,6 +398,7 @@ blest_status blest_last_level_stats(const blest_graph* g, blest_level_stat* buf,
     o.t_stage1_us = r.t_mid > r.t_begin ? (r.t_mid - r.t_begin) * g->d.tick_us : 0.0;
     for (int e = 0; e < 3; ++e) o.t_engine_us[e] = r.t_engine[e] ? r.t_engine[e] * g->d.tick_us : -1.0;
     o.mlp_fallback = r.fallback;
+    o.work = r.work;
   }
   return BLEST_OK;
 }
@@ -490,8 +491,32 @@ blest_status blest_msbfs(blest_graph* g, const int32_t* srcs, int32_t k, int16_t
   std::vector<int32_t> internal(srcs, srcs + k);
   if (!g->perm.empty())
     for (auto& s : internal) s = g->perm[s];
-  hipError_t e = blest::ms_run(g->d, &g->ms, internal.data(), k, g->opts.msbfs_width, levels_dev, nullptr, nullptr,
-                               nullptr, st);
+  const int32_t w = g->opts.msbfs_width;
+  hipError_t e = blest::ms_run(g->d, &g->ms, internal.data(), k, &w, 1, g->opts.policy, g->opts.eta,
+                               g->opts.random_seed, levels_dev, nullptr, nullptr, nullptr, st);
+  if (e != hipSuccess) return hip_fail(e, "msbfs");
+  if (g->opts.async) return BLEST_OK;
+  return wait_and_check(g, st);
+}
+
+blest_status blest_msbfs_batched(blest_graph* g, const int32_t* srcs, int32_t k, const int32_t* widths,
+                                 int32_t nwidths, int16_t* levels_dev, void* stream) {
+  if (!g) return fail(BLEST_ERR_INVALID_ARG, "NULL graph");
+  if (k < 0 || nwidths < 1 || !widths) return fail(BLEST_ERR_INVALID_ARG, "bad source count or widths");
+  for (int32_t i = 0; i < nwidths; ++i)
+    if (widths[i] != 64 && widths[i] != 128 && widths[i] != 256 && widths[i] != 512)
+      return fail(BLEST_ERR_UNSUPPORTED, "batch widths must be 64, 128, 256 or 512");
+  if (k == 0) return BLEST_OK;
+  if (!srcs || !levels_dev) return fail(BLEST_ERR_INVALID_ARG, "NULL sources or output");
+  for (int32_t c = 0; c < k; ++c)
+    if (srcs[c] < 0 || srcs[c] >= g->d.n) return fail(BLEST_ERR_OUT_OF_RANGE, "source vertex out of range");
+  CK(hipSetDevice(g->d.device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<int32_t> internal(srcs, srcs + k);
+  if (!g->perm.empty())
+    for (auto& s : internal) s = g->perm[s];
+  hipError_t e = blest::ms_run(g->d, &g->ms, internal.data(), k, widths, nwidths, g->opts.policy, g->opts.eta,
+                               g->opts.random_seed, levels_dev, nullptr, nullptr, nullptr, st);
   if (e != hipSuccess) return hip_fail(e, "msbfs");
   if (g->opts.async) return BLEST_OK;
   return wait_and_check(g, st);
@@ -510,8 +535,9 @@ blest_status blest_closeness(blest_graph* g, const int32_t* srcs, int64_t k, int
   std::vector<int32_t> internal(srcs, srcs + k);
   if (!g->perm.empty())
     for (auto& s : internal) s = g->perm[s];
-  hipError_t e = blest::ms_run(g->d, &g->ms, internal.data(), static_cast<int32_t>(k), g->opts.msbfs_width, nullptr,
-                               sums_dev, reach_dev, cc_dev, st);
+  const int32_t w = g->opts.msbfs_width;
+  hipError_t e = blest::ms_run(g->d, &g->ms, internal.data(), static_cast<int32_t>(k), &w, 1, g->opts.policy,
+                               g->opts.eta, g->opts.random_seed, nullptr, sums_dev, reach_dev, cc_dev, st);
   if (e != hipSuccess) return hip_fail(e, "closeness");
   if (g->opts.async) return BLEST_OK;
   return wait_and_check(g, st);

@@ -178,8 +178,9 @@ __device__ int choose_engine(const BfsArgs& a, const LevelView& v, const float (
 // testing any, so each lane keeps G * K independent loads in flight
 // (K = tau / 64 slices per lane per VSS).
 template <int SIGMA, class SliceT, int K>
-__device__ void engine_bvss_k(const BfsArgs& a, const uint4* __restrict__ q, long long qlen, long long gwave,
-                              long long nwaves) {
+__device__ long long engine_bvss_k(const BfsArgs& a, const uint4* __restrict__ q, long long qlen, long long gwave,
+                                   long long nwaves) {
+  long long work = 0;
   using M = typename MaskOf<SIGMA>::T;
   constexpr int G = 4;
   const SliceT* __restrict__ sl = static_cast<const SliceT*>(a.slices);
@@ -204,6 +205,7 @@ __device__ void engine_bvss_k(const BfsArgs& a, const uint4* __restrict__ q, lon
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const uint32_t j = lane + 64u * k;
+        work += j < cn[g];
         w[g][k] = (j < cn[g]) ? sl[st[g] + j] : SliceT(0);
       }
     if (pre) {
@@ -230,31 +232,29 @@ __device__ void engine_bvss_k(const BfsArgs& a, const uint4* __restrict__ q, lon
           if (w[g][k] & al[g]) mark[static_cast<uint32_t>(w[g][k] >> SliceFmt<SliceT>::kRowShift)] = 1;
     }
   }
+  return work;
 }
 
 template <int SIGMA, class SliceT>
-__device__ void engine_bvss(const BfsArgs& a, const uint4* __restrict__ q, long long qlen, long long gwave,
-                            long long nwaves) {
+__device__ long long engine_bvss(const BfsArgs& a, const uint4* __restrict__ q, long long qlen, long long gwave,
+                                 long long nwaves) {
   switch (a.tau) {
     case 64:
-      engine_bvss_k<SIGMA, SliceT, 1>(a, q, qlen, gwave, nwaves);
-      break;
+      return engine_bvss_k<SIGMA, SliceT, 1>(a, q, qlen, gwave, nwaves);
     case 128:
-      engine_bvss_k<SIGMA, SliceT, 2>(a, q, qlen, gwave, nwaves);
-      break;
+      return engine_bvss_k<SIGMA, SliceT, 2>(a, q, qlen, gwave, nwaves);
     case 192:
-      engine_bvss_k<SIGMA, SliceT, 3>(a, q, qlen, gwave, nwaves);
-      break;
+      return engine_bvss_k<SIGMA, SliceT, 3>(a, q, qlen, gwave, nwaves);
     default:
-      engine_bvss_k<SIGMA, SliceT, 4>(a, q, qlen, gwave, nwaves);
-      break;
+      return engine_bvss_k<SIGMA, SliceT, 4>(a, q, qlen, gwave, nwaves);
   }
 }
 
 // E1: push over the CSR rows of the frontier vertices.
 template <int SIGMA>
-__device__ void engine_push(const BfsArgs& a, int sel, long long nlight, long long nheavy, long long gtid,
-                            long long nthreads, long long gwave, long long nwaves) {
+__device__ long long engine_push(const BfsArgs& a, int sel, long long nlight, long long nheavy, long long gtid,
+                                 long long nthreads, long long gwave, long long nwaves) {
+  long long work = 0;
   using M = typename MaskOf<SIGMA>::T;
   const M* __restrict__ vis = static_cast<const M*>(a.vis);
   const int32_t* __restrict__ rp = a.rp;
@@ -269,6 +269,7 @@ __device__ void engine_push(const BfsArgs& a, int sel, long long nlight, long lo
     const int end = min(rp[u + 1], b + kHeavyChunk);
     for (int p = b + lane; p < end; p += 64) {
       const int v = col[p];
+      ++work;
       if (!((vis[v / SIGMA] >> (v % SIGMA)) & 1u)) mark[v] = 1;
     }
   }
@@ -276,11 +277,14 @@ __device__ void engine_push(const BfsArgs& a, int sel, long long nlight, long lo
   for (long long i = gtid; i < nlight; i += nthreads) {
     const int u = light[i];
     const int e = rp[u + 1];
-    for (int p = rp[u]; p < e; ++p) {
+    const int p0 = rp[u];
+    work += e - p0;
+    for (int p = p0; p < e; ++p) {
       const int v = col[p];
       if (!((vis[v / SIGMA] >> (v % SIGMA)) & 1u)) mark[v] = 1;
     }
   }
+  return work;
 }
 
 // E2: bottom-up (Alg. 4). A lane owns one vertex; an unvisited vertex of
@@ -290,7 +294,8 @@ __device__ void engine_push(const BfsArgs& a, int sel, long long nlight, long lo
 constexpr int kPullLight = 32;
 
 template <int SIGMA>
-__device__ void engine_pull(const BfsArgs& a, long long gtid, long long nthreads) {
+__device__ long long engine_pull(const BfsArgs& a, long long gtid, long long nthreads) {
+  long long work = 0;
   using M = typename MaskOf<SIGMA>::T;
   const M* __restrict__ vis = static_cast<const M*>(a.vis);
   const M* __restrict__ front = static_cast<const M*>(a.front);
@@ -315,13 +320,16 @@ __device__ void engine_pull(const BfsArgs& a, long long gtid, long long nthreads
     }
     const bool heavy = cand && (e - p > kPullLight);
     if (cand && !heavy) {
+      const int p0 = p;
       for (; p < e; ++p) {
         const int v = col[p];
         if ((front[v / SIGMA] >> (v % SIGMA)) & 1u) {
           mark[u] = 1;
+          ++p;
           break;
         }
       }
+      work += p - p0;
     }
     unsigned long long hb = __ballot(heavy);
     while (hb) {
@@ -334,6 +342,7 @@ __device__ void engine_pull(const BfsArgs& a, long long gtid, long long nthreads
         if (i < he) {
           const int v = col[i];
           f = (front[v / SIGMA] >> (v % SIGMA)) & 1u;
+          ++work;
         }
         if (__ballot(f)) {
           if (lane == 0) mark[ubase + l] = 1;
@@ -342,17 +351,24 @@ __device__ void engine_pull(const BfsArgs& a, long long gtid, long long nthreads
       }
     }
   }
+  return work;
 }
 
-template <int SIGMA, class SliceT>
-__device__ __forceinline__ void run_engine(const BfsArgs& a, int engine, int sel, const LevelView& v, long long gtid,
-                                           long long nthreads, long long gwave, long long nwaves) {
+// Runs one engine and adds the adjacency entries it read to the level's
+// F_WORK counter (one atomic per block).
+template <int SIGMA, class SliceT, int BLOCK>
+__device__ __forceinline__ void run_engine(const BfsArgs& a, int engine, int sel, int slot, const LevelView& v,
+                                           long long gtid, long long nthreads, long long gwave, long long nwaves) {
+  __shared__ long long lds_work[BLOCK / 64];
+  long long work[1];
   if (engine == BLEST_ENGINE_BVSS)
-    engine_bvss<SIGMA, SliceT>(a, a.queue[sel], v.queue, gwave, nwaves);
+    work[0] = engine_bvss<SIGMA, SliceT>(a, a.queue[sel], v.queue, gwave, nwaves);
   else if (engine == BLEST_ENGINE_PUSH)
-    engine_push<SIGMA>(a, sel, v.light, v.heavy, gtid, nthreads, gwave, nwaves);
+    work[0] = engine_push<SIGMA>(a, sel, v.light, v.heavy, gtid, nthreads, gwave, nwaves);
   else
-    engine_pull<SIGMA>(a, gtid, nthreads);
+    work[0] = engine_pull<SIGMA>(a, gtid, nthreads);
+  block_sum64<BLOCK, 1>(work, lds_work);
+  if (threadIdx.x == 0 && work[0]) add_u64(&a.ctl->acc[slot][F_WORK][0], static_cast<unsigned long long>(work[0]));
 }
 
 // ------------------------------------------------------------ Stage 2
@@ -592,6 +608,7 @@ __device__ __forceinline__ void log_level(const BfsArgs& a, int level, const Lev
   r.t_mid = 0;
   r.t_end = 0;
   r.t_engine[0] = r.t_engine[1] = r.t_engine[2] = 0;
+  r.work = 0;
 #pragma unroll
   for (int k = 0; k < kMaxSwitchFeatures; ++k) r.feat[k] = feat[k];
 }
@@ -632,18 +649,21 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
     if (a.probe) {
       for (int e = 0; e < 3; ++e) {
         const unsigned long long t0 = dev_ticks();
-        run_engine<SIGMA, SliceT>(a, e, sel, v, gtid, nthreads, gwave, nwaves);
+        run_engine<SIGMA, SliceT, BLOCK>(a, e, sel, slot, v, gtid, nthreads, gwave, nwaves);
         if (!grid_barrier(a.ctl, bc)) return;
         if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_engine[e] = dev_ticks() - t0;
       }
     } else {
-      run_engine<SIGMA, SliceT>(a, engine, sel, v, gtid, nthreads, gwave, nwaves);
+      run_engine<SIGMA, SliceT, BLOCK>(a, engine, sel, slot, v, gtid, nthreads, gwave, nwaves);
       if (!grid_barrier(a.ctl, bc)) return;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_mid = dev_ticks();
     finalize<SIGMA, BLOCK>(a, level + 1, (level + 1) % kStatSlots, sel ^ 1, v.cumv, v.cume, nblocks);
     if (!grid_barrier(a.ctl, bc)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_end = dev_ticks();
+    if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) {
+      a.log[level].t_end = dev_ticks();
+      a.log[level].work = static_cast<long long>(a.ctl->acc[slot][F_WORK][0]);
+    }
     prev_frontier = v.frontier;
   }
   if (blockIdx.x == 0) {
@@ -701,7 +721,7 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_stage1(BfsArgs a, int level, long
     const int nslot = (level + 1) % kStatSlots;
     for (int t = threadIdx.x; t < kStatFields; t += BLOCK) a.ctl->acc[nslot][t][0] = 0ULL;
   }
-  run_engine<SIGMA, SliceT>(a, engine, level & 1, v, gtid, nthreads, gwave, nwaves);
+  run_engine<SIGMA, SliceT, BLOCK>(a, engine, level & 1, level % kStatSlots, v, gtid, nthreads, gwave, nwaves);
 }
 
 template <int SIGMA, int BLOCK>
@@ -711,7 +731,10 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_stage2(BfsArgs a, int level) {
   if (v.frontier == 0) return;
   if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_mid = dev_ticks();
   finalize<SIGMA, BLOCK>(a, level + 1, (level + 1) % kStatSlots, (level & 1) ^ 1, v.cumv, v.cume, gridDim.x);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_end = dev_ticks();
+  if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) {
+    a.log[level].t_end = dev_ticks();
+    a.log[level].work = static_cast<long long>(a.ctl->acc[level % kStatSlots][F_WORK][0]);
+  }
 }
 
 // ------------------------------------------------------------ host side

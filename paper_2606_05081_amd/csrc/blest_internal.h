@@ -38,6 +38,7 @@ enum StatField : int {
   F_HEAVY = 7,     // heavy-vertex edge-chunk list append cursor (push engine)
   F_CUMV = 8,      // vertices visited through this level
   F_CUME = 9,      // sum of degrees of those vertices
+  F_WORK = 10,     // adjacency entries (slices or CSR edges) read by the engine that left this level
 };
 
 // Push-engine work split: vertices of degree <= kLightMax are walked by one
@@ -64,6 +65,7 @@ struct alignas(256) Ctl {
 // One record per frontier level, written by workgroup 0 of the persistent kernel.
 struct LevelRec {
   long long frontier, queue, qslices, fedges, unvisited, unvisited_edges, deg32, deg1024;
+  long long work;                 // adjacency entries read by the step's engine
   unsigned long long t_begin;     // device clock (100 MHz) when the step started
   unsigned long long t_mid;       // ... when Stage 1 ended (after its barrier)
   unsigned long long t_end;       // ... when its finalisation ended

@@ -15,6 +15,7 @@ struct MsDev {
   int device = 0;
   int wmax = 0;
   int64_t nhat = 0;
+  int64_t nsets = 0;
   unsigned long long* F = nullptr;   // frontier words, getVI-ordered, W per vertex
   unsigned long long* V = nullptr;   // visited words
   unsigned long long* N = nullptr;   // next marks (atomic OR targets)
@@ -30,12 +31,16 @@ struct MsDev {
   int grid = 0, block = 512;
 };
 
-// Runs all sources in batches of `width` sources (64..512) in one persistent
-// launch. levels16 (k*n, source-major, input ids) and/or sums/reach/cc may be
-// NULL. Device-side errors (overflow, timeout) are left in g.ctl->error.
-hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs_internal, int32_t k, int width,
-                  int16_t* levels16, int64_t* sums, int64_t* reach, double* cc, hipStream_t st);
-void ms_release(MsDev* ms);
-void ms_reset(MsDev* ms);
+// Runs all k sources in one persistent launch, in consecutive batches whose
+// widths (sources per batch: 64, 128, 256 or 512) are widths[0..nwidths-1],
+// the last width repeating. levels16 (k*n, source-major, input ids) and/or
+// sums/reach/cc may be NULL. Device-side errors (overflow, timeout) are left
+// in g.ctl->error. Returns after the launch is enqueued.
+hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs_internal, int32_t k, const int32_t* widths,
+                  int nwidths, int policy, float eta, uint64_t seed, int16_t* levels16, int64_t* sums,
+                  int64_t* reach, double* cc, hipStream_t st);
+void ms_release(MsDev* ms);   // frees the per-vertex arrays
+void ms_free_all(MsDev* ms);  // frees everything
+void ms_reset(MsDev* ms);     // clears marks after a device-side error
 
 }  // namespace blest

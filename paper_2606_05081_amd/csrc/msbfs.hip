@@ -1,13 +1,669 @@
-// Multi-source BFS and closeness centrality (placeholder until the kernels land).
+// Multi-source BFS (Section "Multi-Source BFS", Alg. 5) and closeness
+// centrality (Section "Closeness Centrality", Eq. 4 and Eq. 5) for gfx950.
+//
+// kappa = 64 * W concurrent traversals share one pass over the BVSS. Every
+// vertex u owns W 64-bit words in each of F (frontier), V (visited) and N
+// (marked during Stage 1), stored at getVI(u) = (u mod sigma) * rho +
+// floor(u / sigma), rho = number of slice sets, so that consecutive slice
+// sets touch consecutive words (the paper's coalescing remap).
+//
+// Stage 1, top-down over BVSS (E0): a wave takes one queued virtual slice set
+// of set s, stages the sigma * W frontier words of s's vertices in LDS, and
+// for each slice (row, mask) forms M = OR of the staged words selected by the
+// mask bits -- bit c of M is set iff the row has a neighbour in the frontier
+// of traversal c, which is what the paper's per-source ballot + binary MMA
+// loop computes. Words whose sources are inactive in s (activeSets) are
+// skipped; bits already visited are dropped; the rest is OR-ed into N with
+// one no-return 64-bit atomic per word, and the row's set is marked dirty.
+// Stage 1, bottom-up (E2): a lane owns a vertex with unvisited traversals and
+// ORs its neighbours' frontier words until every unvisited bit is covered;
+// it alone writes N[u], so no atomics.
+// Stage 2 visits dirty slice sets only: new = N & ~V, V |= new, F = new,
+// activeSets[s] = OR of the set's new words, the set's VSSs are enqueued when
+// nonzero, int16 levels are written, and per-source counts of newly reached
+// vertices feed the closeness sums.
+#include <algorithm>
+#include <vector>
+
+#include "device_common.h"
 #include "msbfs.h"
 
 namespace blest {
 
-hipError_t ms_run(const DevGraph&, MsDev*, const int32_t*, int32_t, int, int16_t*, int64_t*, int64_t*, double*,
-                  hipStream_t) {
-  return hipErrorNotSupported;
+namespace {
+
+constexpr int kWMax = 8;  // up to 512 sources per batch
+
+struct MsBatch {
+  int32_t offset;  // first source index of the batch in the call's source list
+  int32_t count;   // sources in the batch (<= 64 * W)
+  int32_t W;       // 64-bit words per vertex
+  int32_t pad;
+};
+
+struct MsArgs {
+  const int32_t* rp;
+  const int32_t* col;
+  const uint32_t* slice_ptr;
+  const void* slices;
+  const int32_t* orig_id;
+  int64_t n, m, nsets;
+  int32_t tau;
+  unsigned long long* F;
+  unsigned long long* V;
+  unsigned long long* N;
+  unsigned long long* act;
+  uint8_t* dirty;
+  uint4* queue[2];
+  const int32_t* srcs;
+  const MsBatch* batches;
+  int32_t nbatches;
+  int16_t* levels16;  // k * n or NULL
+  int64_t* sums;      // k or NULL
+  int64_t* reach;     // k or NULL
+  double* cc;         // k or NULL
+  long long* part;    // per block: kappa sums then kappa reach counts
+  Ctl* ctl;
+  int32_t policy;
+  float eta;
+  uint64_t seed;
+  unsigned long long timeout_ticks;
+};
+
+__device__ __forceinline__ long long get_vi(long long u, long long rho, int sigma) {
+  return (u % sigma) * rho + u / sigma;
 }
-void ms_release(MsDev*) {}
-void ms_reset(MsDev*) {}
+
+__device__ __forceinline__ unsigned long long batch_mask(int count, int w) {
+  const int lo = w * 64;
+  if (count >= lo + 64) return ~0ULL;
+  if (count <= lo) return 0ULL;
+  return (1ULL << (count - lo)) - 1ULL;
+}
+
+__device__ __forceinline__ unsigned long long mix64_ms(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// Sets count int16 values to -1: elementwise up to 16-byte alignment, then
+// 16-byte stores, then the tail.
+__device__ void fill_minus_one(int16_t* p, long long count, long long gtid, long long nthreads) {
+  const long long mis = (16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15;
+  const long long head = min(count, mis / 2);
+  for (long long i = gtid; i < head; i += nthreads) p[i] = -1;
+  const long long nvec = (count - head) / 8;
+  ulonglong2* v = reinterpret_cast<ulonglong2*>(p + head);
+  for (long long i = gtid; i < nvec; i += nthreads) v[i] = make_ulonglong2(~0ULL, ~0ULL);
+  for (long long i = head + nvec * 8 + gtid; i < count; i += nthreads) p[i] = -1;
+}
+
+// ---------------------------------------------------------------- Stage 1
+
+template <int SIGMA, class SliceT, int K>
+__device__ void ms_engine_bvss_k(const MsArgs& a, const uint4* __restrict__ q, long long qlen, int W,
+                                 long long gwave, long long nwaves, unsigned long long* lds_f) {
+  const SliceT* __restrict__ sl = static_cast<const SliceT*>(a.slices);
+  const long long rho = a.nsets;
+  const int lane = lane_id();
+  for (long long i = gwave; i < qlen; i += nwaves) {
+    const uint4 d = q[i];
+    const uint32_t start = d.x, cnt = d.y;
+    const long long s = d.w;
+    // Stage the frontier words of the set's sigma vertices (vertex s*SIGMA+b
+    // sits at b*rho + s in getVI order).
+    for (int j = lane; j < SIGMA * W; j += 64) {
+      const int b = j / W, w = j % W;
+      lds_f[j] = a.F[(b * rho + s) * W + w];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    SliceT sv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t j = static_cast<uint32_t>(lane) + 64u * k;
+      sv[k] = (j < cnt) ? sl[start + j] : SliceT(0);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t mask = static_cast<uint32_t>(sv[k] & ((SliceT(1) << SIGMA) - 1));
+      if (!mask) continue;
+      const long long row = static_cast<long long>(sv[k] >> SliceFmt<SliceT>::kRowShift);
+      const long long vi = get_vi(row, rho, SIGMA);
+      bool any = false;
+      for (int w = 0; w < W; ++w) {
+        if (!a.act[s * W + w]) continue;
+        unsigned long long mw = 0;
+        uint32_t t = mask;
+        while (t) {
+          const int b = __builtin_ctz(t);
+          t &= t - 1;
+          mw |= lds_f[b * W + w];
+        }
+        if (!mw) continue;
+        mw &= ~a.V[vi * W + w];
+        if (mw) {
+          __hip_atomic_fetch_or(&a.N[vi * W + w], mw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          any = true;
+        }
+      }
+      if (any) a.dirty[row / SIGMA] = 1;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+template <int SIGMA, class SliceT>
+__device__ void ms_engine_bvss(const MsArgs& a, const uint4* q, long long qlen, int W, long long gwave,
+                               long long nwaves, unsigned long long* lds_f) {
+  switch (a.tau) {
+    case 64:
+      ms_engine_bvss_k<SIGMA, SliceT, 1>(a, q, qlen, W, gwave, nwaves, lds_f);
+      break;
+    case 128:
+      ms_engine_bvss_k<SIGMA, SliceT, 2>(a, q, qlen, W, gwave, nwaves, lds_f);
+      break;
+    case 192:
+      ms_engine_bvss_k<SIGMA, SliceT, 3>(a, q, qlen, W, gwave, nwaves, lds_f);
+      break;
+    default:
+      ms_engine_bvss_k<SIGMA, SliceT, 4>(a, q, qlen, W, gwave, nwaves, lds_f);
+      break;
+  }
+}
+
+template <int SIGMA>
+__device__ void ms_engine_pull(const MsArgs& a, int W, int count, long long gtid, long long nthreads) {
+  const long long rho = a.nsets;
+  unsigned long long bm[kWMax];
+#pragma unroll
+  for (int w = 0; w < kWMax; ++w) bm[w] = (w < W) ? batch_mask(count, w) : 0ULL;
+  for (long long u = gtid; u < a.n; u += nthreads) {
+    const int p0 = a.rp[u], p1 = a.rp[u + 1];
+    if (p0 == p1) continue;
+    const long long vi = get_vi(u, rho, SIGMA);
+    unsigned long long unv[kWMax], acc[kWMax];
+    bool open = false;
+#pragma unroll
+    for (int w = 0; w < kWMax; ++w) {
+      unv[w] = (w < W) ? (~a.V[vi * W + w] & bm[w]) : 0ULL;
+      acc[w] = 0ULL;
+      open |= unv[w] != 0ULL;
+    }
+    if (!open) continue;
+    for (int p = p0; p < p1; ++p) {
+      const long long iv = get_vi(a.col[p], rho, SIGMA);
+      bool covered = true;
+#pragma unroll
+      for (int w = 0; w < kWMax; ++w) {
+        if (w < W && unv[w]) {
+          acc[w] |= a.F[iv * W + w];
+          covered &= (acc[w] & unv[w]) == unv[w];
+        }
+      }
+      if (covered) break;
+    }
+    bool any = false;
+#pragma unroll
+    for (int w = 0; w < kWMax; ++w) {
+      const unsigned long long x = acc[w] & unv[w];
+      if (w < W && x) {
+        a.N[vi * W + w] = x;
+        any = true;
+      }
+    }
+    if (any) a.dirty[u / SIGMA] = 1;
+  }
+}
+
+// ---------------------------------------------------------------- Stage 2
+
+struct MsExpandRec {
+  unsigned long long out;
+  uint32_t n, s0, ns, s;
+};
+constexpr int kMsExpandMin = 8;
+constexpr int kMsMaxExpand = 128;
+
+template <int SIGMA, int BLOCK>
+__device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, int slot_out, int sel_out,
+                            long long cum_in, int* lds_cnt, bool count_sources) {
+  __shared__ int lds32[BLOCK / 64];
+  __shared__ long long lds64[3 * (BLOCK / 64)];
+  __shared__ unsigned long long qbase;
+  __shared__ MsExpandRec rec[kMsMaxExpand];
+  __shared__ int nrec;
+  if (threadIdx.x == 0) nrec = 0;
+  const int W = bt.W;
+  const long long rho = a.nsets;
+  const uint32_t tau = static_cast<uint32_t>(a.tau);
+  unsigned long long* acc = &a.ctl->acc[slot_out][0][0];
+  uint4* __restrict__ queue = a.queue[sel_out];
+  const int lane = lane_id();
+  long long st[3] = {0, 0, 0};  // new pairs, queued slices, (unused)
+  const bool overflow = a.levels16 != nullptr && new_level > 32767;
+  for (long long base = static_cast<long long>(blockIdx.x) * BLOCK; base < a.nsets;
+       base += static_cast<long long>(gridDim.x) * BLOCK) {
+    const long long s = base + threadIdx.x;
+    const bool mine = s < a.nsets && a.dirty[s];
+    int nq = 0;
+    uint32_t s0 = 0, ns = 0;
+    if (__syncthreads_or(mine)) {
+      if (mine) a.dirty[s] = 0;
+      const bool wave_any = __ballot(mine) != 0ULL;
+      unsigned long long A_any = 0ULL;
+      if (wave_any) {
+        for (int w = 0; w < W; ++w) {
+          unsigned long long dw[SIGMA];
+          unsigned long long Aw = 0ULL;
+#pragma unroll
+          for (int b = 0; b < SIGMA; ++b) {
+            dw[b] = 0ULL;
+            if (mine) {
+              const long long idx = (b * rho + s) * W + w;
+              const unsigned long long nx = a.N[idx];
+              unsigned long long dd = 0ULL;
+              if (nx) {
+                a.N[idx] = 0ULL;
+                const unsigned long long old = a.V[idx];
+                dd = nx & ~old;
+                if (dd) a.V[idx] = old | dd;
+              }
+              a.F[idx] = dd;
+              dw[b] = dd;
+              Aw |= dd;
+            }
+          }
+          if (mine) a.act[s * W + w] = Aw;
+          A_any |= Aw;
+          // int16 levels: for each traversal c with new vertices in this set,
+          // write the set's vertices (8 contiguous int16 when not reordered).
+          if (a.levels16 && Aw && !overflow) {
+            unsigned long long t = Aw;
+            while (t) {
+              const int c = __builtin_ctzll(t);
+              t &= t - 1;
+              const long long row = static_cast<long long>(bt.offset) + w * 64 + c;
+              int16_t* out = a.levels16 + row * a.n;
+#pragma unroll
+              for (int b = 0; b < SIGMA; ++b)
+                if ((dw[b] >> c) & 1ULL) {
+                  const long long u = s * SIGMA + b;
+                  out[a.orig_id ? a.orig_id[u] : u] = static_cast<int16_t>(new_level);
+                }
+            }
+          }
+          if (Aw && overflow) __hip_atomic_store(&a.ctl->error[0], static_cast<int>(BLEST_ERR_OVERFLOW),
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          // Per-source counts of new vertices: lane c accumulates traversal
+          // w*64+c by a ballot over the wave's lanes (vertical popcount).
+          int cnt_c = 0;  // lane c: new vertices of traversal w*64+c in this wave
+#pragma unroll
+          for (int b = 0; b < SIGMA; ++b) {
+            st[0] += __popcll(dw[b]);
+            if (count_sources && __ballot(dw[b] != 0ULL)) {
+              for (int c = 0; c < 64; ++c) {
+                const int pc = __popcll(__ballot((dw[b] >> c) & 1ULL));
+                if (lane == c) cnt_c += pc;
+              }
+            }
+          }
+          if (cnt_c) atomicAdd(&lds_cnt[w * 64 + lane], cnt_c);
+        }
+      }
+      if (mine && A_any) {
+        s0 = a.slice_ptr[s];
+        ns = a.slice_ptr[s + 1] - s0;
+        nq = static_cast<int>((ns + tau - 1) / tau);
+        st[1] += ns;
+      }
+      // enqueue the VSSs of every set that gained a vertex in some traversal
+      int v1[1] = {nq}, ex1[1], tot1[1];
+      block_exclusive_scan<BLOCK, 1>(v1, ex1, tot1, lds32);
+      if (threadIdx.x == 0) qbase = tot1[0] ? fetch_add_u64(acc + F_QUEUE * kPad, tot1[0]) : 0ULL;
+      __syncthreads();
+      long long oq = static_cast<long long>(qbase) + ex1[0];
+      if (nq > kMsExpandMin) {
+        const int r = atomicAdd(&nrec, 1);
+        if (r < kMsMaxExpand) {
+          rec[r] = MsExpandRec{static_cast<unsigned long long>(oq), static_cast<uint32_t>(nq), s0, ns,
+                               static_cast<uint32_t>(s)};
+          nq = 0;
+        }
+      }
+      for (int k2 = 0; k2 < nq; ++k2) {
+        const uint32_t off = static_cast<uint32_t>(k2) * tau;
+        queue[oq + k2] = make_uint4(s0 + off, min(tau, ns - off), 0u, static_cast<uint32_t>(s));
+      }
+      __syncthreads();
+      const int nr = min(nrec, kMsMaxExpand);
+      for (int r = 0; r < nr; ++r) {
+        const MsExpandRec e = rec[r];
+        for (uint32_t i = threadIdx.x; i < e.n; i += BLOCK) {
+          const uint32_t off = i * tau;
+          queue[e.out + i] = make_uint4(e.s0 + off, min(tau, e.ns - off), 0u, e.s);
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) nrec = 0;
+      __syncthreads();
+    }
+  }
+  block_sum64<BLOCK, 3>(st, lds64);
+  if (threadIdx.x == 0) {
+    if (st[0]) {
+      add_u64(acc + F_FRONTIER * kPad, st[0]);
+      add_u64(acc + F_CUMV * kPad, st[0]);
+    }
+    if (st[1]) add_u64(acc + F_QSLICES * kPad, st[1]);
+    if (blockIdx.x == 0 && cum_in) add_u64(acc + F_CUMV * kPad, cum_in);
+  }
+  if (count_sources) {
+    __syncthreads();
+    // block-private partial sums across levels: sum += level * count, reach += count
+    long long* part = a.part + static_cast<long long>(blockIdx.x) * (2 * 64 * kWMax);
+    for (int c = threadIdx.x; c < 64 * W; c += BLOCK) {
+      const int x = lds_cnt[c];
+      if (x) {
+        part[c] += static_cast<long long>(new_level) * x;
+        part[64 * kWMax + c] += x;
+        lds_cnt[c] = 0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------- kernel
+
+template <int SIGMA, class SliceT, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
+  __shared__ unsigned long long lds_f[(BLOCK / 64) * SIGMA * kWMax];
+  __shared__ int lds_cnt[64 * kWMax];
+  const long long nthreads = static_cast<long long>(gridDim.x) * BLOCK;
+  const long long gtid = static_cast<long long>(blockIdx.x) * BLOCK + threadIdx.x;
+  const int wave = wave_in_block();
+  const long long gwave = static_cast<long long>(blockIdx.x) * (BLOCK / 64) + wave;
+  const long long nwaves = static_cast<long long>(gridDim.x) * (BLOCK / 64);
+  unsigned long long* my_f = lds_f + wave * SIGMA * kWMax;
+  const long long rho = a.nsets;
+  const long long nhat = a.nsets * SIGMA;
+  const bool count_sources = a.sums != nullptr || a.reach != nullptr || a.cc != nullptr;
+  for (int c = threadIdx.x; c < 64 * kWMax; c += BLOCK) lds_cnt[c] = 0;
+  BarrierCtx bc;
+  if (!barrier_register(a.ctl, &bc, a.timeout_ticks)) return;
+  int total_levels = 0;
+  for (int bi = 0; bi < a.nbatches; ++bi) {
+    const MsBatch bt = a.batches[bi];
+    const int W = bt.W;
+    // clear the batch's state and its level rows
+    for (long long i = gtid; i < nhat * W; i += nthreads) {
+      a.F[i] = 0ULL;
+      a.V[i] = 0ULL;
+    }
+    if (a.levels16) fill_minus_one(a.levels16 + static_cast<long long>(bt.offset) * a.n,
+                                   static_cast<long long>(bt.count) * a.n, gtid, nthreads);
+    if (count_sources) {
+      long long* part = a.part + static_cast<long long>(blockIdx.x) * (2 * 64 * kWMax);
+      for (int c = threadIdx.x; c < 2 * 64 * kWMax; c += BLOCK) part[c] = 0;
+    }
+    if (blockIdx.x == 0)
+      for (int t = threadIdx.x; t < kStatSlots * kStatFields; t += BLOCK)
+        a.ctl->acc[t / kStatFields][t % kStatFields][0] = 0ULL;
+    if (!grid_barrier(a.ctl, bc)) return;
+    // seed: mark each source in its own traversal's bit
+    for (long long c = gtid; c < bt.count; c += nthreads) {
+      const long long u = a.srcs[bt.offset + c];
+      const long long vi = get_vi(u, rho, SIGMA);
+      __hip_atomic_fetch_or(&a.N[vi * W + c / 64], 1ULL << (c % 64), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      a.dirty[u / SIGMA] = 1;
+    }
+    if (!grid_barrier(a.ctl, bc)) return;
+    ms_finalize<SIGMA, BLOCK>(a, bt, 0, 0, 0, 0, lds_cnt, count_sources);
+    if (!grid_barrier(a.ctl, bc)) return;
+    const long long pairs_total = static_cast<long long>(bt.count) * a.n;
+    for (int level = 0;; ++level) {
+      const int slot = level % kStatSlots;
+      const unsigned long long* accr = &a.ctl->acc[slot][0][0];
+      const long long fresh = static_cast<long long>(accr[F_FRONTIER * kPad]);
+      if (fresh == 0) break;
+      const long long qlen = static_cast<long long>(accr[F_QUEUE * kPad]);
+      const long long cumv = static_cast<long long>(accr[F_CUMV * kPad]);
+      int engine;
+      switch (a.policy) {
+        case BLEST_POLICY_BVSS:
+        case BLEST_POLICY_PUSH:
+          engine = BLEST_ENGINE_BVSS;
+          break;
+        case BLEST_POLICY_BOTTOM_UP:
+          engine = BLEST_ENGINE_BOTTOM_UP;
+          break;
+        case BLEST_POLICY_RANDOM:
+          engine = (mix64_ms(a.seed + 0x9E3779B97F4A7C15ULL * static_cast<unsigned long long>(level + 1 + 977 * bi)) & 1ULL)
+                       ? BLEST_ENGINE_BOTTOM_UP
+                       : BLEST_ENGINE_BVSS;
+          break;
+        default:
+          // Eq. 3 counted in (vertex, traversal) pairs: the bottom-up engine
+          // reads W frontier words per scanned edge and rarely stops early
+          // while many traversals are open, so it is chosen only once fewer
+          // than eta * |Q| pairs remain unvisited.
+          engine = (static_cast<double>(pairs_total - cumv) < static_cast<double>(a.eta) * static_cast<double>(qlen))
+                       ? BLEST_ENGINE_BOTTOM_UP
+                       : BLEST_ENGINE_BVSS;
+          break;
+      }
+      if (blockIdx.x == 0) {
+        const int nslot = (level + 1) % kStatSlots;
+        for (int t = threadIdx.x; t < kStatFields; t += BLOCK) a.ctl->acc[nslot][t][0] = 0ULL;
+      }
+      if (engine == BLEST_ENGINE_BVSS)
+        ms_engine_bvss<SIGMA, SliceT>(a, a.queue[level & 1], qlen, W, gwave, nwaves, my_f);
+      else
+        ms_engine_pull<SIGMA>(a, W, bt.count, gtid, nthreads);
+      if (!grid_barrier(a.ctl, bc)) return;
+      ms_finalize<SIGMA, BLOCK>(a, bt, level + 1, (level + 1) % kStatSlots, (level & 1) ^ 1, cumv, lds_cnt,
+                                count_sources);
+      if (!grid_barrier(a.ctl, bc)) return;
+      total_levels = max(total_levels, level + 1);
+    }
+    if (count_sources) {
+      // reduce the block partials of this batch
+      for (long long c = gtid; c < bt.count; c += nthreads) {
+        long long su = 0, re = 0;
+        for (unsigned blk = 0; blk < gridDim.x; ++blk) {
+          const long long* part = a.part + static_cast<long long>(blk) * (2 * 64 * kWMax);
+          su += part[c];
+          re += part[64 * kWMax + c];
+        }
+        const long long row = bt.offset + c;
+        if (a.sums) a.sums[row] = su;
+        if (a.reach) a.reach[row] = re;
+        if (a.cc) a.cc[row] = su ? static_cast<double>(re - 1) / static_cast<double>(su) : 0.0;
+      }
+    }
+    if (!grid_barrier(a.ctl, bc)) return;
+  }
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < 8) a.ctl->xcd_blocks[threadIdx.x][0] = 0u;
+    if (threadIdx.x == 8) a.ctl->xcd_active[0] = 0u;
+    if (threadIdx.x == 0) a.ctl->nlevels[0] = total_levels;
+  }
+}
+
+template <int SIGMA, class SliceT, int BLOCK>
+const void* ms_fn() {
+  return reinterpret_cast<const void*>(&k_ms_persistent<SIGMA, SliceT, BLOCK>);
+}
+
+template <int SIGMA, class SliceT>
+const void* ms_fn_block(int block) {
+  switch (block) {
+    case 256:
+      return ms_fn<SIGMA, SliceT, 256>();
+    case 1024:
+      return ms_fn<SIGMA, SliceT, 1024>();
+    default:
+      return ms_fn<SIGMA, SliceT, 512>();
+  }
+}
+
+// The multi-source kernel keeps sigma words per slice set live in Stage 2;
+// 512-thread blocks leave it enough registers to avoid spilling at sigma 8.
+constexpr int kMsBlock = 512;
+
+const void* ms_kernel(const DevGraph& g) {
+  if (g.sigma == 8 && !g.wide) return ms_fn_block<8, uint32_t>(kMsBlock);
+  if (g.sigma == 8) return ms_fn_block<8, uint64_t>(kMsBlock);
+  if (g.sigma == 16) return ms_fn_block<16, uint64_t>(kMsBlock);
+  return ms_fn_block<32, uint64_t>(kMsBlock);
+}
+
+hipError_t ensure(const DevGraph& g, MsDev* ms, int wmax, int32_t k, int nbatches) {
+  const int64_t nhat = g.nsets * g.sigma;
+  if (ms->wmax < wmax || ms->nhat != nhat) {
+    ms_release(ms);
+    const size_t words = static_cast<size_t>(nhat) * wmax;
+    hipError_t e;
+    if ((e = hipMalloc(&ms->F, words * 8)) != hipSuccess) return e;
+    if ((e = hipMalloc(&ms->V, words * 8)) != hipSuccess) return e;
+    if ((e = hipMalloc(&ms->N, words * 8)) != hipSuccess) return e;
+    if ((e = hipMalloc(&ms->act, static_cast<size_t>(g.nsets) * wmax * 8)) != hipSuccess) return e;
+    if ((e = hipMalloc(&ms->dirty, static_cast<size_t>(g.nsets))) != hipSuccess) return e;
+    for (int i = 0; i < 2; ++i)
+      if ((e = hipMalloc(&ms->queue[i], sizeof(uint4) * static_cast<size_t>(std::max<int64_t>(g.nvss, 1)))) !=
+          hipSuccess)
+        return e;
+    if ((e = hipMemset(ms->N, 0, words * 8)) != hipSuccess) return e;
+    if ((e = hipMemset(ms->dirty, 0, static_cast<size_t>(g.nsets))) != hipSuccess) return e;
+    ms->wmax = wmax;
+    ms->nhat = nhat;
+    ms->nsets = g.nsets;
+  }
+  if (ms->srcs_cap < k) {
+    if (ms->srcs) (void)hipFree(ms->srcs);
+    ms->srcs = nullptr;
+    hipError_t e = hipMalloc(&ms->srcs, sizeof(int32_t) * static_cast<size_t>(k));
+    if (e != hipSuccess) return e;
+    ms->srcs_cap = k;
+  }
+  if (ms->batches_cap < nbatches) {
+    if (ms->batches) (void)hipFree(ms->batches);
+    ms->batches = nullptr;
+    hipError_t e = hipMalloc(&ms->batches, sizeof(MsBatch) * static_cast<size_t>(nbatches));
+    if (e != hipSuccess) return e;
+    ms->batches_cap = nbatches;
+  }
+  if (ms->grid == 0) {
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ms_kernel(g), kMsBlock, 0);
+    if (e != hipSuccess) return e;
+    if (nb < 1) return hipErrorInvalidConfiguration;
+    nb = std::min(nb, 2);
+    ms->grid = nb * g.num_cu;
+    ms->block = kMsBlock;
+  }
+  if (ms->part_blocks < ms->grid) {
+    if (ms->part) (void)hipFree(ms->part);
+    ms->part = nullptr;
+    hipError_t e = hipMalloc(&ms->part, sizeof(long long) * 2 * 64 * kWMax * static_cast<size_t>(ms->grid));
+    if (e != hipSuccess) return e;
+    ms->part_blocks = ms->grid;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, const int32_t* widths, int nwidths,
+                  int policy, float eta, uint64_t seed, int16_t* levels16, int64_t* sums, int64_t* reach, double* cc,
+                  hipStream_t st) {
+  if (k <= 0) return hipSuccess;
+  std::vector<MsBatch> plan;
+  int32_t off = 0;
+  for (int i = 0; off < k; ++i) {
+    const int width = widths[nwidths > 0 ? std::min(i, nwidths - 1) : 0];
+    const int W = width / 64;
+    plan.push_back(MsBatch{off, std::min(64 * W, k - off), W, 0});
+    off += 64 * W;
+  }
+  const int nplan = static_cast<int>(plan.size());
+  int wmax = 1;
+  for (int i = 0; i < nplan; ++i) wmax = std::max(wmax, plan[i].W);
+  hipError_t e = ensure(g, ms, wmax, k, nplan);
+  if (e != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(ms->srcs, srcs, sizeof(int32_t) * k, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(ms->batches, plan.data(), sizeof(MsBatch) * nplan, hipMemcpyHostToDevice, st)) !=
+      hipSuccess)
+    return e;
+  // the copies read pageable host memory; wait so `plan` may go out of scope
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  MsArgs a{};
+  a.rp = g.rp;
+  a.col = g.col;
+  a.slice_ptr = g.slice_ptr;
+  a.slices = g.slices;
+  a.orig_id = g.orig_id;
+  a.n = g.n;
+  a.m = g.m;
+  a.nsets = g.nsets;
+  a.tau = g.tau;
+  a.F = ms->F;
+  a.V = ms->V;
+  a.N = ms->N;
+  a.act = ms->act;
+  a.dirty = ms->dirty;
+  a.queue[0] = ms->queue[0];
+  a.queue[1] = ms->queue[1];
+  a.srcs = ms->srcs;
+  a.batches = static_cast<const MsBatch*>(ms->batches);
+  a.nbatches = nplan;
+  a.levels16 = levels16;
+  a.sums = sums;
+  a.reach = reach;
+  a.cc = cc;
+  a.part = ms->part;
+  a.ctl = g.ctl;
+  a.policy = policy;
+  a.eta = eta;
+  a.seed = seed;
+  a.timeout_ticks = 3000000000ULL;  // 30 s
+  void* args[] = {static_cast<void*>(&a)};
+  return hipLaunchCooperativeKernel(ms_kernel(g), dim3(ms->grid), dim3(ms->block), args, 0, st);
+}
+
+void ms_release(MsDev* ms) {
+  for (void* p : {static_cast<void*>(ms->F), static_cast<void*>(ms->V), static_cast<void*>(ms->N),
+                  static_cast<void*>(ms->act), static_cast<void*>(ms->dirty), static_cast<void*>(ms->queue[0]),
+                  static_cast<void*>(ms->queue[1])})
+    if (p) (void)hipFree(p);
+  ms->F = ms->V = ms->N = ms->act = nullptr;
+  ms->dirty = nullptr;
+  ms->queue[0] = ms->queue[1] = nullptr;
+  ms->wmax = 0;
+  ms->nhat = 0;
+}
+
+void ms_free_all(MsDev* ms) {
+  ms_release(ms);
+  if (ms->srcs) (void)hipFree(ms->srcs);
+  if (ms->part) (void)hipFree(ms->part);
+  if (ms->batches) (void)hipFree(ms->batches);
+  ms->srcs = nullptr;
+  ms->part = nullptr;
+  ms->batches = nullptr;
+  ms->srcs_cap = 0;
+  ms->part_blocks = 0;
+  ms->batches_cap = 0;
+  ms->grid = 0;
+}
+
+void ms_reset(MsDev* ms) {
+  // After a device-side error N and dirty may hold stale marks.
+  if (ms->N && ms->nhat) (void)hipMemset(ms->N, 0, static_cast<size_t>(ms->nhat) * ms->wmax * 8);
+  if (ms->dirty && ms->nsets) (void)hipMemset(ms->dirty, 0, static_cast<size_t>(ms->nsets));
+}
 
 }  // namespace blest

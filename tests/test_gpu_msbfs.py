@@ -1,0 +1,143 @@
+"""Multi-source BFS and closeness on the GPU against the CPU oracle.
+
+int16 levels and int64 sums/reach are exact integers (array equality); the
+FP64 closeness is one IEEE division of exact integers on both sides, so it is
+compared bit for bit (relative error 0 <= 1e-12)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_05081_amd import inputs
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def blest():
+    import torch
+    from paper_2606_05081_amd import blest as b
+    assert torch.cuda.is_available()
+    b.lib()
+    return b
+
+
+POLICIES = ["HEURISTIC", "BVSS", "BOTTOM_UP", "RANDOM"]
+
+
+@pytest.mark.parametrize("width", [64, 128, 256, 512])
+def test_msbfs_rmat_all_widths_and_policies(blest, width):
+    rp, col = inputs.rmat_graph(12, 51)
+    srcs = inputs.sources(rp, 300, seed=52, distinct=False)  # ragged last batch, repeated sources
+    ref = oracle.msbfs16(rp, col, srcs)
+    g = blest.Graph(rp, col, msbfs_width=width)
+    for pol in POLICIES:
+        g.set_policy(getattr(blest.Policy, pol), 10.0, 7)
+        got = g.msbfs(srcs).cpu().numpy()
+        assert np.array_equal(got, ref), (pol, width, np.argwhere(got != ref)[:5])
+    g.close()
+
+
+def test_msbfs_uneven_batches_one_launch(blest):
+    rp, col = inputs.rmat_graph(13, 61)
+    srcs = inputs.sources(rp, 960, seed=62)
+    ref = oracle.msbfs16(rp, col, srcs)
+    g = blest.Graph(rp, col)
+    got = g.msbfs_batched(srcs, [64, 128, 256, 512]).cpu().numpy()
+    assert np.array_equal(got, ref)
+    got = g.msbfs_batched(srcs[:100], [64]).cpu().numpy()
+    assert np.array_equal(got, ref[:100])
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["grid", "path", "hypercube", "disconnected", "tiny"])
+def test_msbfs_structured(blest, name):
+    if name == "grid":
+        rp, col = inputs.grid_graph(60, 3)
+    elif name == "path":
+        rp, col = H.path(2000)
+    elif name == "hypercube":
+        rp, col = H.hypercube(10)
+    elif name == "disconnected":
+        rp, col = inputs.from_pairs(29, [0, 1, 2, 10, 11, 20], [1, 2, 3, 11, 12, 21])
+    else:
+        rp, col = inputs.from_pairs(3, [0], [1])
+    n = rp.size - 1
+    srcs = np.arange(n, dtype=np.int32) if n <= 300 else inputs.sources(rp, 200, seed=4)
+    ref = oracle.msbfs16(rp, col, srcs)
+    for opts in ({}, {"reorder": 1}, {"sigma": 16}, {"tau": 64}):
+        g = blest.Graph(rp, col, **opts)
+        for pol in POLICIES:
+            g.set_policy(getattr(blest.Policy, pol), 10.0, 3)
+            assert np.array_equal(g.msbfs(srcs).cpu().numpy(), ref), (name, opts, pol)
+        g.close()
+
+
+def test_msbfs_overflow_and_errors(blest):
+    rp, col = H.path(33000)
+    g = blest.Graph(rp, col)
+    with pytest.raises(blest.BlestError) as ei:
+        g.msbfs([0, 5])
+    assert ei.value.status == blest.Status.OVERFLOW
+    ok = g.msbfs([16000]).cpu().numpy()  # still usable after the error
+    assert np.array_equal(ok, oracle.msbfs16(rp, col, [16000]))
+    with pytest.raises(blest.BlestError) as ei:
+        g.msbfs([0, 33000])
+    assert ei.value.status == blest.Status.OUT_OF_RANGE
+    assert g.msbfs([]).shape == (0, 33000)
+    g.close()
+
+
+def test_closeness_matches_oracle(blest):
+    for rp, col, k in [(*inputs.rmat_graph(12, 71), 700), (*inputs.grid_graph(40, 72), 300),
+                       (*inputs.from_pairs(9, [0, 1, 4], [1, 2, 5]), 9)]:
+        n = rp.size - 1
+        srcs = np.arange(n, dtype=np.int32) if k >= n else inputs.sources(rp, k, seed=73, nonzero_degree=False)
+        osum, oreach, occ = oracle.closeness(rp, col, srcs)
+        g = blest.Graph(rp, col)
+        for pol in POLICIES:
+            g.set_policy(getattr(blest.Policy, pol), 10.0, 5)
+            s, r, c = g.closeness(srcs)
+            assert np.array_equal(s.cpu().numpy(), osum), pol
+            assert np.array_equal(r.cpu().numpy(), oreach), pol
+            assert np.array_equal(c.cpu().numpy(), occ), pol  # bit-identical doubles
+        g.close()
+
+
+def test_closeness_all_sources_equals_per_target_far(blest):
+    rp, col = inputs.rmat_graph(11, 81)
+    n = rp.size - 1
+    allv = np.arange(n, dtype=np.int32)
+    g = blest.Graph(rp, col)
+    s, _, _ = g.closeness(allv)
+    assert np.array_equal(s.cpu().numpy(), oracle.far(rp, col, allv))
+    g.close()
+
+
+def test_msbfs_full_size_rmat20_sampled_rows(blest):
+    """Scale-20 R-MAT, 960 sources in batches of 64/128/256/512 (one launch)."""
+    rp, col = inputs.rmat_graph(20, 1040)
+    srcs = inputs.sources(rp, 960, seed=1041)
+    g = blest.Graph(rp, col)
+    got = g.msbfs_batched(srcs, [64, 128, 256, 512])
+    rows = [0, 63, 64, 191, 192, 447, 448, 959]
+    for r in rows:
+        lev = got[r].cpu().numpy().astype(np.int32)
+        assert np.array_equal(lev, oracle.bfs(rp, col, int(srcs[r]))), r
+    for r in (5, 300, 700):
+        lev = got[r].cpu().numpy().astype(np.int32)
+        assert oracle.certificate(rp, col, int(srcs[r]), lev) == (0, -1), r
+    g.close()
+
+
+def test_closeness_rmat18_subset(blest):
+    """Scale-18 R-MAT closeness on a 512-source subset of all vertices."""
+    rp, col = inputs.rmat_graph(18, 1050)
+    srcs = np.arange(0, rp.size - 1, 512, dtype=np.int32)
+    osum, oreach, occ = oracle.closeness(rp, col, srcs)
+    g = blest.Graph(rp, col)
+    s, r, c = g.closeness(srcs)
+    assert np.array_equal(s.cpu().numpy(), osum)
+    assert np.array_equal(r.cpu().numpy(), oreach)
+    assert np.array_equal(c.cpu().numpy(), occ)
+    g.close()
