@@ -1,0 +1,173 @@
+"""Autotuner for the BVSS traversal's structural and launch parameters.
+
+Searches, by coordinate descent from the defaults, over slice-set width sigma,
+slices per virtual slice set tau, 64-bit slice words, threads per workgroup,
+workgroups per compute unit, the visited pre-filter, and the multi-source batch
+width (kappa). Each candidate is timed on the device (HIP events on the launch
+stream) on a seeded graph of the requested family, and the winner is cached in
+JSON keyed by (device, family, log2 n, mean degree). The paper fixes sigma = 8,
+theta = 4, tau = 128 for 32-wide warps (BVSS subsection) and notes that its
+switching constant is GPU-specific (Fig. 5 discussion); on 64-wide wavefronts
+these choices are re-measured rather than assumed.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import numpy as np
+
+CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+
+SPACE = {
+    "sigma": [8, 16, 32],
+    "tau": [64, 128, 192, 256],
+    "wide_slices": [0, 1],
+    "block_size": [256, 512, 1024],
+    "blocks_per_cu": [0, 1, 2],
+    "prefilter": [1, 0],
+}
+MS_WIDTHS = [64, 128, 256, 512]
+DEFAULTS = {"sigma": 8, "tau": 128, "wide_slices": 0, "block_size": 1024, "blocks_per_cu": 0, "prefilter": 1}
+
+
+def cache_key(device_name: str, family: str, n: int, m: int) -> str:
+    return f"{device_name}|{family}|log2n={int(np.log2(max(n, 1)))}|deg={int(round(m / max(n, 1)))}"
+
+
+def load_cache(path=CACHE_PATH) -> dict:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def save_cache(cache: dict, path=CACHE_PATH):
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+
+
+def lookup(family: str, n: int, m: int, device_name: str | None = None, path=CACHE_PATH) -> dict:
+    """Tuned options for a graph of this family and size, or the defaults."""
+    if device_name is None:
+        import torch
+        device_name = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    ent = load_cache(path).get(cache_key(device_name, family, n, m))
+    return dict(ent["bfs"]) if ent else dict(DEFAULTS)
+
+
+def _valid(opts):
+    return not (opts["sigma"] != 8 and opts["wide_slices"] == 0)
+
+
+def time_bfs(rp, col, srcs, opts, policy="HEURISTIC", reps=2):
+    """Mean device time per source (ms) for one option set."""
+    import torch
+    from . import blest
+    o = dict(opts)
+    if o["sigma"] != 8:
+        o["wide_slices"] = 1
+    g = blest.Graph(rp, col, **{**o, "async": 1})
+    g.set_policy(getattr(blest.Policy, policy))
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for s in srcs[:2]:
+        g.bfs(int(s), out)
+    g.sync()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for s in srcs:
+            g.bfs(int(s), out)
+        e1.record()
+        g.sync()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / len(srcs))
+    g.close()
+    return best
+
+
+def time_msbfs(rp, col, srcs, width, opts):
+    import torch
+    from . import blest
+    o = dict(opts)
+    if o["sigma"] != 8:
+        o["wide_slices"] = 1
+    g = blest.Graph(rp, col, **{**o, "async": 1})
+    out = torch.empty((len(srcs), g.n), dtype=torch.int16, device="cuda")
+    g.msbfs_batched(srcs, [width], out)
+    g.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.msbfs_batched(srcs, [width], out)
+    e1.record()
+    g.sync()
+    torch.cuda.synchronize()
+    g.close()
+    return e0.elapsed_time(e1)
+
+
+def tune(rp, col, family, n_sources=16, seed=7, passes=1, tune_ms=True, log=print):
+    """Coordinate descent from DEFAULTS; returns the cache entry."""
+    from . import inputs
+    srcs = inputs.sources(rp, n_sources, seed=seed)
+    best = dict(DEFAULTS)
+    best_t = time_bfs(rp, col, srcs, best)
+    trials = [(dict(best), best_t)]
+    log(f"[autotune] {family}: defaults {best_t:.4f} ms/source")
+    for _ in range(passes):
+        for key, values in SPACE.items():
+            for v in values:
+                if v == best[key]:
+                    continue
+                cand = {**best, key: v}
+                if not _valid(cand):
+                    continue
+                try:
+                    t = time_bfs(rp, col, srcs, cand)
+                except Exception as e:  # an option the device cannot launch (e.g. occupancy)
+                    log(f"[autotune] {cand} failed: {e}")
+                    continue
+                trials.append((cand, t))
+                if t < best_t * 0.98:
+                    best, best_t = cand, t
+                    log(f"[autotune] {family}: {key}={v} -> {t:.4f} ms/source")
+    ent = {"bfs": best, "bfs_ms_per_source": best_t, "bfs_default_ms_per_source": trials[0][1],
+           "trials": len(trials), "tuned_at": time.strftime("%Y-%m-%d %H:%M:%S")}
+    if tune_ms:
+        k = 512
+        msrcs = inputs.sources(rp, k, seed=seed + 1)
+        times = {w: time_msbfs(rp, col, msrcs, w, best) for w in MS_WIDTHS}
+        wbest = min(times, key=times.get)
+        ent["msbfs_width"] = wbest
+        ent["msbfs_sources_per_s"] = {str(w): k / t * 1e3 for w, t in times.items()}
+        log(f"[autotune] {family}: msbfs widths {ent['msbfs_sources_per_s']} -> {wbest}")
+    return ent
+
+
+def main(argv=None):
+    import argparse
+    import torch
+    from . import inputs
+    ap = argparse.ArgumentParser(description="tune BVSS traversal parameters on this GPU")
+    ap.add_argument("--families", default="rmat,grid,er")
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--out", default=CACHE_PATH)
+    args = ap.parse_args(argv)
+    dev_name = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cache = load_cache(args.out)
+    for fam in args.families.split(","):
+        if fam == "rmat":
+            rp, col = inputs.rmat_graph(args.scale, 3000 + args.scale)
+        elif fam == "grid":
+            rp, col = inputs.grid_graph(int(2 ** (args.scale / 2)), 3100 + args.scale)
+        else:
+            rp, col = inputs.er_graph(args.scale, 3200 + args.scale)
+        ent = tune(rp, col, fam)
+        cache[cache_key(dev_name, fam, rp.size - 1, col.size)] = ent
+        save_cache(cache, args.out)
+
+
+if __name__ == "__main__":
+    main()

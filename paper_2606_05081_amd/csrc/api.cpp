@@ -543,4 +543,43 @@ blest_status blest_closeness(blest_graph* g, const int32_t* srcs, int64_t k, int
   return wait_and_check(g, st);
 }
 
+blest_status blest_mlp_forward(const float* params, const float* x, int32_t batch, float* logits, void* stream) {
+  if (batch < 0) return fail(BLEST_ERR_INVALID_ARG, "negative batch");
+  if (batch == 0) return BLEST_OK;
+  if (!params || !x || !logits) return fail(BLEST_ERR_INVALID_ARG, "NULL argument");
+  CK(blest::mlp_forward_launch(params, x, batch, logits, static_cast<hipStream_t>(stream)));
+  return BLEST_OK;
+}
+
+blest_status blest_mlp_loss_grad(const float* params, const float* x, const int32_t* y, const float* w, int32_t batch,
+                                 float* loss, float* grad, void* stream) {
+  if (!params || !x || !y || !grad) return fail(BLEST_ERR_INVALID_ARG, "NULL argument");
+  if (batch <= 0) return fail(BLEST_ERR_INVALID_ARG, "batch must be positive");
+  CK(blest::mlp_loss_grad_launch(params, x, y, w, batch, loss, grad, static_cast<hipStream_t>(stream)));
+  return BLEST_OK;
+}
+
+blest_status blest_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t n, int32_t t, float lr,
+                            float beta1, float beta2, float eps, void* stream) {
+  if (!params || !grad || !m || !v) return fail(BLEST_ERR_INVALID_ARG, "NULL argument");
+  if (n <= 0 || t < 1) return fail(BLEST_ERR_INVALID_ARG, "n must be positive and t >= 1");
+  CK(blest::mlp_adam_launch(params, grad, m, v, n, t, lr, beta1, beta2, eps, static_cast<hipStream_t>(stream)));
+  return BLEST_OK;
+}
+
+blest_status blest_mlp_train(float* params, float* m, float* v, const float* x, const int32_t* y, const float* w,
+                             int32_t nsamples, int32_t batch, int32_t steps, float lr, uint64_t seed, float* loss_log,
+                             void* stream) {
+  if (!params || !m || !v || !x || !y) return fail(BLEST_ERR_INVALID_ARG, "NULL argument");
+  if (nsamples <= 0 || batch <= 0 || steps < 0) return fail(BLEST_ERR_INVALID_ARG, "bad sizes");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* grad = nullptr;
+  CK(hipMallocAsync(reinterpret_cast<void**>(&grad), sizeof(float) * BLEST_MLP_NPARAMS, st));
+  hipError_t e = blest::mlp_train_launch(params, m, v, x, y, w, nsamples, batch, steps, lr, seed, loss_log, grad, st);
+  hipError_t e2 = hipFreeAsync(grad, st);
+  if (e != hipSuccess) return hip_fail(e, "mlp training");
+  if (e2 != hipSuccess) return hip_fail(e2, "hipFreeAsync");
+  return BLEST_OK;
+}
+
 }  // extern "C"

@@ -146,4 +146,14 @@ hipError_t bfs_run(const DevGraph& g, BfsArgs a, hipStream_t st);
 hipError_t bfs_grid_size(const DevGraph& g, int policy_learned, int blocks_per_cu, int* grid);
 BfsArgs bfs_args(const DevGraph& g);
 
+// Switch-network kernels (mlp.hip).
+hipError_t mlp_forward_launch(const float* params, const float* x, int32_t batch, float* logits, hipStream_t st);
+hipError_t mlp_loss_grad_launch(const float* params, const float* x, const int32_t* y, const float* w, int32_t batch,
+                                float* loss, float* grad, hipStream_t st);
+hipError_t mlp_adam_launch(float* params, const float* grad, float* m, float* v, int32_t n, int32_t t, float lr,
+                           float beta1, float beta2, float eps, hipStream_t st);
+hipError_t mlp_train_launch(float* params, float* m, float* v, const float* x, const int32_t* y, const float* w,
+                            int32_t nsamples, int32_t batch, int32_t steps, float lr, uint64_t seed, float* loss_log,
+                            float* grad, hipStream_t st);
+
 }  // namespace blest

@@ -1,0 +1,255 @@
+"""Learned per-level engine switch: dataset, training on the GPU, evaluation.
+
+The paper switches between its BVSS top-down kernel and a bottom-up kernel by
+Eq. 3 (bottom-up iff #unvisited < eta * |Q|, eta = 10) and names a more
+robust, graph-adaptive criterion as future work (Conclusion); it also shows
+that the rule misclassifies some levels (Fig. 5 discussion). This module
+builds that criterion:
+
+1. Dataset: probe-mode traversals (every level runs all three engines from
+   the same state and times each on the device clock) over R-MAT graphs of
+   scale 18-22 and 4-neighbour grids; each level yields the 12 features the
+   kernel computes and the three measured times. Label = the fastest engine
+   (ties go to Eq. 3's choice).
+2. Training: the 12 -> 64 -> 64 -> 3 network is trained by the library's own
+   HIP kernels (blest_mlp_train: minibatch softmax cross-entropy, Adam), with
+   class- and family-balanced sample weights.
+3. Evaluation: on held-out graphs, per-level regret against the per-level
+   optimum, Sum(t_chosen - t_min) / Sum(t_min), as in Fig. 5, for the learned
+   choices and for Eq. 3, plus end-to-end GTEPS of both policies.
+
+Every traversal here runs on the GPU; this module only marshals data.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import numpy as np
+
+FEATURES = ["log2(1+|F|)", "log2(1+|Q|)", "log2(1+queued slices)", "log2(1+m_f)", "log2(1+#unvisited)",
+            "log2(1+m_u)", "log2 n", "log2(1+m)", "log2(1+level)", "log2 |F_l|/|F_l-1|", "frac deg>=32",
+            "frac deg>=1024"]
+ENGINES = ["bvss", "push", "bottom_up"]
+MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "switch_model.json")
+
+# Training workload: graph families of the paper's classes (Kronecker-like and
+# road-like), disjoint seeds from every evaluation graph.
+TRAIN_SPECS = ([("rmat", s, 2000 + s) for s in (18, 19, 20, 21, 22)] +
+               [("grid", side, 2100 + i) for i, side in enumerate((512, 768, 1024, 1536, 2048))])
+EVAL_SPECS = [("rmat", 24, 1030), ("er", 24, 1032)]
+
+
+def make_graph(kind, size, seed):
+    from . import inputs
+    if kind == "rmat":
+        return inputs.rmat_graph(size, seed)
+    if kind == "grid":
+        return inputs.grid_graph(size, seed)
+    if kind == "er":
+        return inputs.er_graph(size, seed)
+    raise ValueError(kind)
+
+
+def heuristic_choice(stat, eta=10.0):
+    return 2 if stat["unvisited"] < eta * stat["queue"] else 0
+
+
+def probe_graph(g, srcs, max_levels_per_run=None, rng=None):
+    """Probe-mode rows for each source: (features[12], times[3], eq3 choice)."""
+    feats, times, heur, run_ids = [], [], [], []
+    for r, s in enumerate(srcs):
+        g.bfs_probe(int(s))
+        st = g.level_stats()
+        f = g.level_features()
+        idx = np.arange(len(st) - 1)
+        if max_levels_per_run is not None and idx.size > max_levels_per_run:
+            idx = np.sort((rng or np.random.default_rng(r)).choice(idx, max_levels_per_run, replace=False))
+        for i in idx:
+            t = st[i]["t_engine_us"]
+            if min(t) <= 0:
+                continue
+            feats.append(f[i])
+            times.append(t)
+            heur.append(heuristic_choice(st[i]))
+            run_ids.append(r)
+    return (np.array(feats, np.float32).reshape(-1, 12), np.array(times, np.float32).reshape(-1, 3),
+            np.array(heur, np.int32), np.array(run_ids, np.int32))
+
+
+def labels_from_times(times, heur):
+    y = np.argmin(times, axis=1).astype(np.int32)
+    best = times[np.arange(len(y)), y]
+    tie = times[np.arange(len(y)), heur] <= best * 1.0 + 1e-9
+    y[tie] = heur[tie]
+    return y
+
+
+def balanced_weights(y, family):
+    """Each (family, class) cell gets equal total weight."""
+    w = np.zeros(len(y), np.float32)
+    cells = {}
+    for i, key in enumerate(zip(family, y)):
+        cells.setdefault(key, []).append(i)
+    for idx in cells.values():
+        w[idx] = 1.0 / len(idx)
+    return w * (len(y) / w.sum())
+
+
+def regret(times, choice):
+    t_min = times.min(axis=1)
+    t_ch = times[np.arange(len(choice)), choice]
+    return float((t_ch - t_min).sum() / t_min.sum())
+
+
+def init_params(seed=1):
+    """He-uniform weights, zero biases, in the flat parameter order."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((12, 64), (64, 64), (64, 3)):
+        lim = np.sqrt(6.0 / fan_in)
+        parts.append(rng.uniform(-lim, lim, (fan_out, fan_in)).ravel())
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def train(X, y, w, steps=4000, batch=256, lr=1e-3, seed=1):
+    """Trains on the GPU with the library's kernels. Returns (params, mean, std, losses)."""
+    import torch
+    from . import blest
+    mean = X.mean(axis=0)
+    std = X.std(axis=0)
+    std = np.where(std < 1e-3, 1.0, std).astype(np.float32)
+    Z = ((X - mean) / std).astype(np.float32)
+    dev = torch.device("cuda", 0)
+    p = torch.tensor(init_params(seed), device=dev)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    xs = torch.tensor(Z, device=dev)
+    ys = torch.tensor(y.astype(np.int32), device=dev)
+    ws = torch.tensor(w.astype(np.float32), device=dev)
+    losses = torch.zeros(steps, dtype=torch.float32, device=dev)
+    blest.blest_mlp_train(p, m, v, xs, ys, ws, batch, steps, lr, seed, losses)
+    torch.cuda.synchronize()
+    return p.cpu().numpy(), mean.astype(np.float32), std, losses.cpu().numpy()
+
+
+def predict(params, mean, std, X):
+    """Engine choices of the network on the GPU (blest_mlp_forward); -1 = out of range (Eq. 3 fallback)."""
+    import torch
+    from . import blest
+    Z = ((X - mean) / std).astype(np.float32)
+    dev = torch.device("cuda", 0)
+    logits = torch.empty((len(Z), 3), dtype=torch.float32, device=dev)
+    blest.blest_mlp_forward(torch.tensor(params, device=dev), torch.tensor(Z, device=dev), logits)
+    ch = logits.cpu().numpy().argmax(axis=1).astype(np.int32)
+    ch[(np.abs(Z) > 6).any(axis=1)] = -1
+    return ch
+
+
+def save_model(params, mean, std, meta, path=MODEL_PATH):
+    with open(path, "w") as f:
+        json.dump({"params": [float(x) for x in params], "mean": [float(x) for x in mean],
+                   "std": [float(x) for x in std], "features": FEATURES, "engines": ENGINES, "meta": meta}, f)
+
+
+def load_model(path=MODEL_PATH):
+    with open(path) as f:
+        d = json.load(f)
+    return np.array(d["params"], np.float32), np.array(d["mean"], np.float32), np.array(d["std"], np.float32), d
+
+
+def build_dataset(specs=TRAIN_SPECS, runs_per_graph=20, grid_levels_per_run=96, log=print):
+    from . import blest, inputs
+    Xs, Ts, Hs, fam = [], [], [], []
+    for kind, size, seed in specs:
+        t0 = time.time()
+        rp, col = make_graph(kind, size, seed)
+        g = blest.Graph(rp, col)
+        srcs = inputs.sources(rp, runs_per_graph, seed=seed + 500)
+        X, T, Hc, _ = probe_graph(g, srcs, grid_levels_per_run if kind == "grid" else None,
+                                  np.random.default_rng(seed))
+        g.close()
+        Xs.append(X)
+        Ts.append(T)
+        Hs.append(Hc)
+        fam += [kind] * len(X)
+        log(f"[dataset] {kind} {size} seed {seed}: {len(X)} levels in {time.time() - t0:.1f}s")
+    return np.concatenate(Xs), np.concatenate(Ts), np.concatenate(Hs), np.array(fam)
+
+
+def evaluate_graph(kind, size, seed, params, mean, std, n_sources=16, log=print):
+    """Regret of both policies on probe timings and end-to-end GTEPS of both."""
+    import torch
+    from . import blest, inputs
+    rp, col = make_graph(kind, size, seed)
+    g = blest.Graph(rp, col, **{"async": 1})
+    g.set_switch_model(params, mean, std)
+    srcs = inputs.sources(rp, n_sources, seed=seed + 1)
+    X, T, Hc, _ = probe_graph(g, srcs[: max(4, n_sources // 4)])
+    ch = predict(params, mean, std, X)
+    ch = np.where(ch < 0, Hc, ch)
+    res = {"graph": f"{kind}{size}", "levels": int(len(X)), "regret_learned": regret(T, ch),
+           "regret_heuristic": regret(T, Hc), "misclassified_learned": float((ch != T.argmin(1)).mean()),
+           "misclassified_heuristic": float((Hc != T.argmin(1)).mean())}
+    deg = np.diff(rp).astype(np.int64)
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    edges = []
+    g.set_policy(blest.Policy.HEURISTIC)
+    for s in srcs:
+        g.bfs(int(s), out)
+        g.sync()
+        edges.append(int(deg[out.cpu().numpy() >= 0].sum() // 2))
+    for name, pol in (("heuristic", blest.Policy.HEURISTIC), ("learned", blest.Policy.LEARNED)):
+        g.set_policy(pol)
+        for s in srcs[:2]:
+            g.bfs(int(s), out)
+        g.sync()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(srcs) + 1)]
+        evs[0].record()
+        for i, s in enumerate(srcs):
+            g.bfs(int(s), out)
+            evs[i + 1].record()
+        g.sync()
+        torch.cuda.synchronize()
+        t = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(len(srcs))])
+        res[f"gteps_{name}"] = float(len(t) / np.sum(t * 1e-3 / np.array(edges) * 1e9))
+    res["learned_over_heuristic"] = res["gteps_learned"] / res["gteps_heuristic"]
+    g.close()
+    log(f"[eval] {res}")
+    return res
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="train and evaluate the learned engine switch (GPU)")
+    ap.add_argument("--runs-per-graph", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--out", default=MODEL_PATH)
+    ap.add_argument("--dataset-out", default=None)
+    ap.add_argument("--eval", action="store_true")
+    args = ap.parse_args(argv)
+    X, T, Hc, fam = build_dataset(runs_per_graph=args.runs_per_graph)
+    y = labels_from_times(T, Hc)
+    w = balanced_weights(y, fam)
+    print(f"[train] {len(y)} levels, label counts {np.bincount(y, minlength=3).tolist()}", flush=True)
+    t0 = time.time()
+    params, mean, std, losses = train(X, y, w, steps=args.steps)
+    ch = predict(params, mean, std, X)
+    ch = np.where(ch < 0, Hc, ch)
+    meta = {"levels": int(len(y)), "label_counts": np.bincount(y, minlength=3).tolist(),
+            "train_loss_first": float(losses[:50].mean()), "train_loss_last": float(losses[-50:].mean()),
+            "train_regret_learned": regret(T, ch), "train_regret_heuristic": regret(T, Hc),
+            "steps": args.steps, "specs": TRAIN_SPECS}
+    print(f"[train] {time.time() - t0:.1f}s {meta}", flush=True)
+    save_model(params, mean, std, meta, args.out)
+    if args.dataset_out:
+        np.savez(args.dataset_out, X=X, T=T, H=Hc, fam=fam)
+    if args.eval:
+        for kind, size, seed in EVAL_SPECS:
+            evaluate_graph(kind, size, seed, params, mean, std)
+
+
+if __name__ == "__main__":
+    main()

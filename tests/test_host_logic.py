@@ -1,0 +1,48 @@
+"""Host-side logic of the learned switch and autotuner (no GPU)."""
+import json
+
+import numpy as np
+
+from paper_2606_05081_amd import autotune, switch
+
+
+def test_labels_prefer_fastest_and_break_ties_to_eq3():
+    T = np.array([[3.0, 1.0, 2.0], [1.0, 1.0, 5.0], [2.0, 2.0, 2.0]], np.float32)
+    H = np.array([0, 1, 2], np.int32)
+    assert switch.labels_from_times(T, H).tolist() == [1, 1, 2]
+
+
+def test_regret_definition():
+    T = np.array([[1.0, 2.0, 4.0], [3.0, 1.0, 1.0]])
+    assert switch.regret(T, np.array([0, 1])) == 0.0
+    assert switch.regret(T, np.array([2, 0])) == (3.0 + 2.0) / 2.0
+
+
+def test_balanced_weights_equalise_cells():
+    y = np.array([0, 0, 0, 1, 2, 2])
+    fam = np.array(["a", "a", "b", "a", "b", "b"])
+    w = switch.balanced_weights(y, fam)
+    cells = {}
+    for wi, key in zip(w, zip(fam, y)):
+        cells[key] = cells.get(key, 0) + wi
+    assert np.allclose(list(cells.values()), list(cells.values())[0])
+    assert np.isclose(w.sum(), len(y))
+
+
+def test_init_params_layout_and_heuristic_choice():
+    p = switch.init_params(3)
+    assert p.shape == (5187,) and p.dtype == np.float32
+    assert np.all(p[768:832] == 0) and np.all(p[-3:] == 0)
+    assert switch.heuristic_choice({"unvisited": 9, "queue": 1}) == 2
+    assert switch.heuristic_choice({"unvisited": 10, "queue": 1}) == 0
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    path = str(tmp_path / "c.json")
+    key = autotune.cache_key("gfx950", "rmat", 1 << 20, 31 * (1 << 20))
+    assert key == "gfx950|rmat|log2n=20|deg=31"
+    assert autotune.lookup("rmat", 1 << 20, 31 << 20, device_name="gfx950", path=path) == autotune.DEFAULTS
+    autotune.save_cache({key: {"bfs": {**autotune.DEFAULTS, "tau": 64}}}, path)
+    assert autotune.lookup("rmat", 1 << 20, 31 << 20, device_name="gfx950", path=path)["tau"] == 64
+    assert json.load(open(path))[key]["bfs"]["tau"] == 64
+    assert not autotune._valid({**autotune.DEFAULTS, "sigma": 16, "wide_slices": 0})
