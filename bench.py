@@ -108,6 +108,59 @@ def cpu_baseline(rp, col, srcs, budget_s=20.0):
             "sample": f"{len(times)} of the {len(srcs)} R-MAT scale-22 sources, FIFO-queue BFS on one host thread"}
 
 
+KERNEL_SOURCES = ["paper_2606_05081_amd/csrc/bfs.hip", "paper_2606_05081_amd/csrc/device_common.h",
+                  "paper_2606_05081_amd/csrc/blest_internal.h"]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_bfs_persistent_rmat22_bvss_traffic.txt")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile():
+    """HBM bytes per launch of the plain-method persistent kernel from the committed
+    rocprofv3 summary, or None if it is missing or was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    vals = {}
+    with open(TRAFFIC_SUMMARY) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return int(float(vals["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def profile_leg(policy_name, n_sources=8):
+    """A short run for rocprofv3: a 512 MiB device copy (counter calibration),
+    then n_sources traversals of the scale-22 workload with one policy."""
+    import torch
+    from paper_2606_05081_amd import blest, inputs
+    rp, col = inputs.rmat_graph(22, 1020)
+    srcs = inputs.sources(rp, n_sources, seed=1021)
+    g = blest.Graph(rp, col, device=0, **{"async": 1})
+    a = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    c.copy_(a)
+    torch.cuda.synchronize()
+    g.set_policy(getattr(blest.Policy, policy_name.upper()))
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    ts = timed_sources(g, srcs, out, torch)
+    print(json.dumps({"profile_leg": policy_name, "sources": n_sources, "ms_per_source": float(np.mean(ts)),
+                      "calibration_copy_bytes": 2 * a.numel() * 4, "kernel_source_sha256_16": kernel_source_hash()}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,11 +168,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sources", type=int, default=64)
     ap.add_argument("--no-extras", action="store_true", help="skip grid, msBFS and CPU legs")
+    ap.add_argument("--profile-leg", choices=["heuristic", "bvss"], default=None,
+                    help="only a short run of one policy plus a calibration copy, for rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is not built "
                                    "(see DESIGN.md, 'How the path would shard')", "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.profile_leg:
+        profile_leg(args.profile_leg)
+        return
 
     import torch
     from paper_2606_05081_amd import blest, inputs
@@ -147,7 +206,7 @@ def main():
     policy = "heuristic"
     if model is not None:
         g.set_switch_model(np.array(model["params"], np.float32), np.array(model["mean"], np.float32),
-                           np.array(model["std"], np.float32))
+                           np.array(model["std"], np.float32), model.get("min_confidence", 0.5))
 
     def run_policy(pol, steps, warmup):
         g.set_policy(pol, 10.0)
@@ -175,6 +234,7 @@ def main():
 
     # plain method (BVSS top-down every level): roofline of the persistent kernel
     td_gteps, _, td_t = run_policy(blest.Policy.BVSS, 1, 1)
+    g.set_log_work(True)  # per-level adjacency counts for the byte accounting (not timed)
     nb = []
     deg = np.diff(rp).astype(np.int64)
     for s in srcs[:8]:
@@ -187,7 +247,7 @@ def main():
     launch_ms = float(np.mean(td_t[:8]))
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(),
                 "kernel": "k_bfs_persistent (plain method: BVSS top-down every level)",
                 "bytes_per_launch": int(bytes_per_launch), "launch_ms": round(launch_ms, 4)}
     # same for the switched run
@@ -200,6 +260,7 @@ def main():
         nb2.append(algorithmic_bytes(g.level_stats(), info["n"], info["n_slice_sets"], info["sigma"],
                                      info["slice_bytes"], deg, lev))
     sw_ach = float(np.mean(nb2)) / (float(np.mean(heur_t[:8])) * 1e-3) / 1e9
+    g.set_log_work(False)
 
     extras = {"heuristic_gteps": round(heur_gteps, 3), "learned_gteps": None if learned_gteps is None else
               round(learned_gteps, 3), "learned_over_heuristic": None if learned_gteps is None else

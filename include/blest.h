@@ -94,7 +94,9 @@ typedef struct {
   int32_t msbfs_width;  /* sources per multi-source batch: 64, 128, 256 or 512 (default 512) */
   uint64_t random_seed; /* seed of BLEST_POLICY_RANDOM */
   int32_t device;       /* HIP device ordinal, -1 = current device */
-  int32_t reserved[7];
+  int32_t single_block; /* 1 (default): levels whose Stage 1 can mark at most 4096 rows run on one
+                           workgroup with workgroup barriers instead of device-wide ones */
+  int32_t reserved[6];
 } blest_opts;
 
 /* Fills *opts with the defaults listed above. */
@@ -145,6 +147,11 @@ blest_status blest_closeness(blest_graph* g, const int32_t* srcs_host, int64_t k
 /* With opts.async = 1: waits for `stream` and reports device-side errors of the
  * calls enqueued since the last sync (TIMEOUT, OVERFLOW). */
 blest_status blest_sync(blest_graph* g, void* stream);
+
+/* Enables (on != 0) counting of the adjacency entries each level's engine
+ * reads (blest_level_stat.work). Off by default: the count costs one device
+ * atomic per workgroup before every Stage 1 barrier. Probe mode always counts. */
+blest_status blest_set_log_work(blest_graph* g, int32_t on);
 
 /* Changes the level-engine policy of an existing graph (BLEST_POLICY_*). */
 blest_status blest_set_policy(blest_graph* g, int32_t policy, float eta, uint64_t random_seed);
@@ -216,6 +223,12 @@ blest_status blest_export_bvss(const blest_graph* g, int64_t* real_ptrs, int64_t
  * Errors: INVALID_ARG (nparams mismatch, std <= 0). */
 blest_status blest_set_switch_model(blest_graph* g, const float* params, int32_t nparams, const float* mean,
                                     const float* std);
+
+/* Minimum softmax probability of the network's choice for BLEST_POLICY_LEARNED
+ * (default 0.5); below it, and for standardised inputs outside [-6, 6], the
+ * level falls back to Eq. 3. g = NULL sets the default for later models.
+ * Errors: INVALID_ARG (min_prob outside (0, 1]). */
+blest_status blest_set_switch_confidence(blest_graph* g, float min_prob);
 
 /* Per-level features (12 floats, the network's inputs before standardising)
  * of the last BFS's levels, to host: feat[nlev][12]. */

@@ -71,7 +71,8 @@ class Opts(ctypes.Structure):
                 ("policy", ctypes.c_int32), ("eta", ctypes.c_float), ("block_size", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("persistent", ctypes.c_int32), ("wide_slices", ctypes.c_int32),
                 ("prefilter", ctypes.c_int32), ("async_", ctypes.c_int32), ("msbfs_width", ctypes.c_int32),
-                ("random_seed", ctypes.c_uint64), ("device", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("random_seed", ctypes.c_uint64), ("device", ctypes.c_int32), ("single_block", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class GraphStats(ctypes.Structure):
@@ -115,6 +116,8 @@ SIGNATURES = {
     "blest_last_level_features": (_i32, [_vp, _pf32, _i32, _p32]),
     "blest_export_bvss": (_i32, [_vp, _p64, _p64, _p64, _p32, _pu64, _p32]),
     "blest_set_switch_model": (_i32, [_vp, _pf32, _i32, _pf32, _pf32]),
+    "blest_set_switch_confidence": (_i32, [_vp, _f32]),
+    "blest_set_log_work": (_i32, [_vp, _i32]),
     "blest_mlp_forward": (_i32, [_vp, _vp, _i32, _vp, _vp]),
     "blest_mlp_loss_grad": (_i32, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp]),
     "blest_mlp_adam": (_i32, [_vp, _vp, _vp, _vp, _i32, _i32, _f32, _f32, _f32, _f32, _vp]),
@@ -225,6 +228,14 @@ def blest_set_switch_model(h, params, mean, std):
     sd = np.ascontiguousarray(std, dtype=np.float32)
     _check(lib().blest_set_switch_model(h, p.ctypes.data_as(_pf32), p.size, mu.ctypes.data_as(_pf32),
                                         sd.ctypes.data_as(_pf32)))
+
+
+def blest_set_switch_confidence(h, min_prob: float):
+    _check(lib().blest_set_switch_confidence(h, float(min_prob)))
+
+
+def blest_set_log_work(h, on: bool):
+    _check(lib().blest_set_log_work(h, int(bool(on))))
 
 
 def blest_mlp_forward(params, x, logits, stream=None):
@@ -356,8 +367,13 @@ class Graph:
         return {"real_ptrs": real_ptrs, "v2r": v2r[:nv], "slice_ptr": slice_ptr, "slice_row": rows[:nsl],
                 "slice_mask": masks[:nsl], "perm": perm}
 
-    def set_switch_model(self, params, mean, std):
+    def set_switch_model(self, params, mean, std, min_confidence: float | None = None):
         blest_set_switch_model(self._h, params, mean, std)
+        if min_confidence is not None:
+            blest_set_switch_confidence(self._h, min_confidence)
+
+    def set_log_work(self, on: bool = True):
+        blest_set_log_work(self._h, on)
 
 
 def set_default_switch_model(params, mean, std):

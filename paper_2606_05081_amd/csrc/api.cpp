@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -50,6 +51,7 @@ blest_status hip_fail(hipError_t e, const char* what) {
 
 std::mutex g_model_mu;
 bool g_model_set = false;
+float g_min_conf = 0.5f;
 blest::MlpDev g_model{};
 
 hipError_t dalloc(blest_graph* g, void** p, size_t bytes) {
@@ -173,6 +175,7 @@ void blest_default_opts(blest_opts* o) {
   o->msbfs_width = 512;
   o->random_seed = 1;
   o->device = -1;
+  o->single_block = 1;
 }
 
 blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_graph** out) {
@@ -243,6 +246,7 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   d.num_cu = num_cu;
   d.persistent = o.persistent;
   d.prefilter = o.prefilter;
+  d.single_block = o.single_block;
   d.tick_us = tick_us;
   d.log_cap = 1 << 16;
   int64_t nheavy = 0;
@@ -263,7 +267,10 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
       return hip_fail(e, #expr);  \
     }                             \
   } while (0)
-  TRY(dalloc_t(g, &d.rp, static_cast<size_t>(n + 1)));
+  // rp is padded to N_s*sigma + 1 entries (tail = m) so a slice set's row
+  // pointers can be read with aligned 16-byte loads.
+  const size_t rp_len = static_cast<size_t>(b.nsets) * o.sigma + 1;
+  TRY(dalloc_t(g, &d.rp, rp_len + 4));
   TRY(dalloc_t(g, &d.col, static_cast<size_t>(std::max<int64_t>(m, 1))));
   TRY(dalloc_t(g, &d.slice_ptr, ns + 1));
   TRY(dalloc(g, &d.slices, static_cast<size_t>(std::max<int64_t>(b.nslices, 1)) * (wide ? 8 : 4)));
@@ -284,7 +291,11 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
     TRY(hipMemcpy(d.orig_id, orig.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
   }
   TRY(hipHostMalloc(reinterpret_cast<void**>(&d.host_flags), 64, hipHostMallocDefault));
-  TRY(hipMemcpy(d.rp, rp, sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
+  {
+    std::vector<int32_t> rpp(rp_len + 4, static_cast<int32_t>(m));
+    std::copy(rp, rp + n + 1, rpp.begin());
+    TRY(hipMemcpy(d.rp, rpp.data(), sizeof(int32_t) * rpp.size(), hipMemcpyHostToDevice));
+  }
   if (m > 0) TRY(hipMemcpy(d.col, col, sizeof(int32_t) * m, hipMemcpyHostToDevice));
   TRY(hipMemcpy(d.slice_ptr, b.slice_ptr.data(), sizeof(uint32_t) * (ns + 1), hipMemcpyHostToDevice));
   if (b.nslices > 0) {
@@ -467,6 +478,10 @@ blest_status blest_set_switch_model(blest_graph* g, const float* params, int32_t
   }
   for (int i = 0; i < BLEST_MLP_NPARAMS; ++i)
     if (!std::isfinite(params[i])) return fail(BLEST_ERR_INVALID_ARG, "non-finite parameter");
+  {
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    m.max_ratio = 1.0f / g_min_conf;
+  }
   m.valid = 1;
   if (!g) {
     std::lock_guard<std::mutex> lk(g_model_mu);
@@ -476,6 +491,27 @@ blest_status blest_set_switch_model(blest_graph* g, const float* params, int32_t
   }
   CK(hipSetDevice(g->d.device));
   CK(hipMemcpy(g->d.mlp, &m, sizeof(m), hipMemcpyHostToDevice));
+  return BLEST_OK;
+}
+
+blest_status blest_set_switch_confidence(blest_graph* g, float min_prob) {
+  if (!(min_prob > 0.0f && min_prob <= 1.0f)) return fail(BLEST_ERR_INVALID_ARG, "min_prob must be in (0, 1]");
+  const float r = 1.0f / min_prob;
+  if (!g) {
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    g_min_conf = min_prob;
+    g_model.max_ratio = r;
+    return BLEST_OK;
+  }
+  CK(hipSetDevice(g->d.device));
+  CK(hipMemcpy(reinterpret_cast<char*>(g->d.mlp) + offsetof(blest::MlpDev, max_ratio), &r, sizeof(float),
+               hipMemcpyHostToDevice));
+  return BLEST_OK;
+}
+
+blest_status blest_set_log_work(blest_graph* g, int32_t on) {
+  if (!g) return fail(BLEST_ERR_INVALID_ARG, "NULL graph");
+  g->d.count_work = on ? 1 : 0;
   return BLEST_OK;
 }
 

@@ -47,6 +47,24 @@ __device__ __forceinline__ LevelView read_level(const Ctl* ctl, int slot) {
   return v;
 }
 
+// Same, with agent-scope loads (used inside a single-workgroup episode, where
+// the counters were just updated by device atomics without a barrier).
+__device__ __forceinline__ LevelView read_level_atomic(const Ctl* ctl, int slot) {
+  const unsigned long long* acc = &ctl->acc[slot][0][0];
+  LevelView v;
+  v.frontier = static_cast<long long>(ld_relaxed_u64(acc + F_FRONTIER * kPad));
+  v.queue = static_cast<long long>(ld_relaxed_u64(acc + F_QUEUE * kPad));
+  v.qslices = static_cast<long long>(ld_relaxed_u64(acc + F_QSLICES * kPad));
+  v.fedges = static_cast<long long>(ld_relaxed_u64(acc + F_FEDGES * kPad));
+  v.deg32 = static_cast<long long>(ld_relaxed_u64(acc + F_DEG32 * kPad));
+  v.deg1024 = static_cast<long long>(ld_relaxed_u64(acc + F_DEG1024 * kPad));
+  v.light = static_cast<long long>(ld_relaxed_u64(acc + F_LIGHT * kPad));
+  v.heavy = static_cast<long long>(ld_relaxed_u64(acc + F_HEAVY * kPad));
+  v.cumv = static_cast<long long>(ld_relaxed_u64(acc + F_CUMV * kPad));
+  v.cume = static_cast<long long>(ld_relaxed_u64(acc + F_CUME * kPad));
+  return v;
+}
+
 // The 12 switch features of a level (network inputs before standardising).
 __device__ __forceinline__ void level_features(float (&f)[kMaxSwitchFeatures], const LevelView& v, long long n,
                                                long long m, int level, long long prev_frontier) {
@@ -82,7 +100,7 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
 // Switch network in LDS: W1T[12][64], b1[64], W2T[64][64], b2[64], W3[3][64],
 // b3[3], mean[12], inv_std[12] (W1 and W2 transposed for conflict-free reads).
 constexpr int kLdsW1T = 0, kLdsB1 = 768, kLdsW2T = 832, kLdsB2 = 4928, kLdsW3 = 4992, kLdsB3 = 5184,
-              kLdsMean = 5187, kLdsInvStd = 5199, kLdsMlpFloats = 5211;
+              kLdsMean = 5187, kLdsInvStd = 5199, kLdsMaxRatio = 5211, kLdsMlpFloats = 5212;
 
 __device__ void mlp_to_lds(const MlpDev* mlp, float* s) {
   const float* p = mlp->params;
@@ -103,10 +121,12 @@ __device__ void mlp_to_lds(const MlpDev* mlp, float* s) {
     s[kLdsMean + i] = mlp->mean[i];
     s[kLdsInvStd + i] = mlp->inv_std[i];
   }
+  if (threadIdx.x == 0) s[kLdsMaxRatio] = mlp->max_ratio;
 }
 
 // Forward pass by one full wave; returns the argmax engine, or -1 when a
-// standardised input lies outside [-6, 6] (caller falls back to Eq. 3).
+// standardised input lies outside [-6, 6] or the softmax probability of the
+// argmax is below the model's confidence floor (caller falls back to Eq. 3).
 __device__ int mlp_choose_wave(const float* s, const float (&feat)[kMaxSwitchFeatures]) {
   float z[kMaxSwitchFeatures];
   bool ood = false;
@@ -134,7 +154,9 @@ __device__ int mlp_choose_wave(const float* s, const float (&feat)[kMaxSwitchFea
   int best = 0;
   float bv = l0;
   if (l1 > bv) { best = 1; bv = l1; }
-  if (l2 > bv) { best = 2; }
+  if (l2 > bv) { best = 2; bv = l2; }
+  const float ratio = expf(l0 - bv) + expf(l1 - bv) + expf(l2 - bv);  // = 1 / p(best)
+  if (!(ratio <= s[kLdsMaxRatio])) return -1;
   return best;
 }
 
@@ -173,13 +195,37 @@ __device__ int choose_engine(const BfsArgs& a, const LevelView& v, const float (
 
 // ------------------------------------------------------------ Stage 1
 
+constexpr int kSingleHash = 8192;              // LDS hash-set slots (power of two)
+constexpr long long kSingleMaxMarks = 4096;    // keeps the hash set at most half full
+// LDS layout of a single-workgroup level: hs[kSingleHash] hash slots, then
+// the list of recorded sets hs[kSingleHash + 1 + i] with its length at
+// hs[kSingleHash].
+constexpr int kSingleLds = kSingleHash + 1 + kSingleMaxMarks;
+
+__device__ __forceinline__ void record_set(int* hs, long long s, Ctl* ctl) {
+  uint32_t h = (static_cast<uint32_t>(s) * 2654435761u) >> (32 - 13);
+  for (int probe = 0; probe < kSingleHash; ++probe) {
+    const int old = atomicCAS(&hs[h], -1, static_cast<int>(s));
+    if (old == -1) {
+      const int idx = atomicAdd(&hs[kSingleHash], 1);
+      hs[kSingleHash + 1 + idx] = static_cast<int>(s);
+      return;
+    }
+    if (old == static_cast<int>(s)) return;
+    h = (h + 1) & (kSingleHash - 1);
+  }
+  __hip_atomic_store(&ctl->error[0], static_cast<int>(BLEST_ERR_INVALID_ARG), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+
 // E0: BVSS top-down with pull mechanics and lazy marking. A wave takes G
 // consecutive queue entries at a time and issues all their slice loads before
 // testing any, so each lane keeps G * K independent loads in flight
 // (K = tau / 64 slices per lane per VSS).
-template <int SIGMA, class SliceT, int K>
+template <int SIGMA, class SliceT, int K, bool REC>
 __device__ long long engine_bvss_k(const BfsArgs& a, const uint4* __restrict__ q, long long qlen, long long gwave,
-                                   long long nwaves) {
+                                   long long nwaves, int* hs) {
   long long work = 0;
   using M = typename MaskOf<SIGMA>::T;
   constexpr int G = 4;
@@ -222,38 +268,45 @@ __device__ long long engine_bvss_k(const BfsArgs& a, const uint4* __restrict__ q
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           const uint32_t row = static_cast<uint32_t>(w[g][k] >> SliceFmt<SliceT>::kRowShift);
-          if (!((vv[g][k] >> (row % SIGMA)) & 1u)) mark[row] = 1;
+          if (!((vv[g][k] >> (row % SIGMA)) & 1u)) {
+            mark[row] = 1;
+            if (REC) record_set(hs, row / SIGMA, a.ctl);
+          }
         }
     } else {
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int k = 0; k < K; ++k)
-          if (w[g][k] & al[g]) mark[static_cast<uint32_t>(w[g][k] >> SliceFmt<SliceT>::kRowShift)] = 1;
+          if (w[g][k] & al[g]) {
+            const uint32_t row = static_cast<uint32_t>(w[g][k] >> SliceFmt<SliceT>::kRowShift);
+            mark[row] = 1;
+            if (REC) record_set(hs, row / SIGMA, a.ctl);
+          }
     }
   }
   return work;
 }
 
-template <int SIGMA, class SliceT>
+template <int SIGMA, class SliceT, bool REC>
 __device__ long long engine_bvss(const BfsArgs& a, const uint4* __restrict__ q, long long qlen, long long gwave,
-                                 long long nwaves) {
+                                 long long nwaves, int* hs) {
   switch (a.tau) {
     case 64:
-      return engine_bvss_k<SIGMA, SliceT, 1>(a, q, qlen, gwave, nwaves);
+      return engine_bvss_k<SIGMA, SliceT, 1, REC>(a, q, qlen, gwave, nwaves, hs);
     case 128:
-      return engine_bvss_k<SIGMA, SliceT, 2>(a, q, qlen, gwave, nwaves);
+      return engine_bvss_k<SIGMA, SliceT, 2, REC>(a, q, qlen, gwave, nwaves, hs);
     case 192:
-      return engine_bvss_k<SIGMA, SliceT, 3>(a, q, qlen, gwave, nwaves);
+      return engine_bvss_k<SIGMA, SliceT, 3, REC>(a, q, qlen, gwave, nwaves, hs);
     default:
-      return engine_bvss_k<SIGMA, SliceT, 4>(a, q, qlen, gwave, nwaves);
+      return engine_bvss_k<SIGMA, SliceT, 4, REC>(a, q, qlen, gwave, nwaves, hs);
   }
 }
 
 // E1: push over the CSR rows of the frontier vertices.
-template <int SIGMA>
+template <int SIGMA, bool REC>
 __device__ long long engine_push(const BfsArgs& a, int sel, long long nlight, long long nheavy, long long gtid,
-                                 long long nthreads, long long gwave, long long nwaves) {
+                                 long long nthreads, long long gwave, long long nwaves, int* hs) {
   long long work = 0;
   using M = typename MaskOf<SIGMA>::T;
   const M* __restrict__ vis = static_cast<const M*>(a.vis);
@@ -270,7 +323,10 @@ __device__ long long engine_push(const BfsArgs& a, int sel, long long nlight, lo
     for (int p = b + lane; p < end; p += 64) {
       const int v = col[p];
       ++work;
-      if (!((vis[v / SIGMA] >> (v % SIGMA)) & 1u)) mark[v] = 1;
+      if (!((vis[v / SIGMA] >> (v % SIGMA)) & 1u)) {
+        mark[v] = 1;
+        if (REC) record_set(hs, v / SIGMA, a.ctl);
+      }
     }
   }
   const int32_t* __restrict__ light = a.flight[sel];
@@ -281,7 +337,10 @@ __device__ long long engine_push(const BfsArgs& a, int sel, long long nlight, lo
     work += e - p0;
     for (int p = p0; p < e; ++p) {
       const int v = col[p];
-      if (!((vis[v / SIGMA] >> (v % SIGMA)) & 1u)) mark[v] = 1;
+      if (!((vis[v / SIGMA] >> (v % SIGMA)) & 1u)) {
+        mark[v] = 1;
+        if (REC) record_set(hs, v / SIGMA, a.ctl);
+      }
     }
   }
   return work;
@@ -320,16 +379,19 @@ __device__ long long engine_pull(const BfsArgs& a, long long gtid, long long nth
     }
     const bool heavy = cand && (e - p > kPullLight);
     if (cand && !heavy) {
+      // four independent neighbour loads per step shorten the dependent chain
       const int p0 = p;
-      for (; p < e; ++p) {
-        const int v = col[p];
-        if ((front[v / SIGMA] >> (v % SIGMA)) & 1u) {
-          mark[u] = 1;
-          ++p;
-          break;
-        }
+      bool found = false;
+      for (; p < e && !found; p += 4) {
+        const int v0 = col[p];
+        const int v1 = p + 1 < e ? col[p + 1] : v0;
+        const int v2 = p + 2 < e ? col[p + 2] : v0;
+        const int v3 = p + 3 < e ? col[p + 3] : v0;
+        found = ((front[v0 / SIGMA] >> (v0 % SIGMA)) & 1u) | ((front[v1 / SIGMA] >> (v1 % SIGMA)) & 1u) |
+                ((front[v2 / SIGMA] >> (v2 % SIGMA)) & 1u) | ((front[v3 / SIGMA] >> (v3 % SIGMA)) & 1u);
       }
-      work += p - p0;
+      if (found) mark[u] = 1;
+      work += min(p, e) - p0;
     }
     unsigned long long hb = __ballot(heavy);
     while (hb) {
@@ -356,65 +418,87 @@ __device__ long long engine_pull(const BfsArgs& a, long long gtid, long long nth
 
 // Runs one engine and adds the adjacency entries it read to the level's
 // F_WORK counter (one atomic per block).
+// hs != nullptr: single-workgroup level, marked slice sets are recorded in hs
+// (only the BVSS and push engines run there).
 template <int SIGMA, class SliceT, int BLOCK>
 __device__ __forceinline__ void run_engine(const BfsArgs& a, int engine, int sel, int slot, const LevelView& v,
-                                           long long gtid, long long nthreads, long long gwave, long long nwaves) {
+                                           long long gtid, long long nthreads, long long gwave, long long nwaves,
+                                           int* hs = nullptr) {
   __shared__ long long lds_work[BLOCK / 64];
   long long work[1];
   if (engine == BLEST_ENGINE_BVSS)
-    work[0] = engine_bvss<SIGMA, SliceT>(a, a.queue[sel], v.queue, gwave, nwaves);
+    work[0] = hs ? engine_bvss<SIGMA, SliceT, true>(a, a.queue[sel], v.queue, gwave, nwaves, hs)
+                 : engine_bvss<SIGMA, SliceT, false>(a, a.queue[sel], v.queue, gwave, nwaves, nullptr);
   else if (engine == BLEST_ENGINE_PUSH)
-    work[0] = engine_push<SIGMA>(a, sel, v.light, v.heavy, gtid, nthreads, gwave, nwaves);
+    work[0] = hs ? engine_push<SIGMA, true>(a, sel, v.light, v.heavy, gtid, nthreads, gwave, nwaves, hs)
+                 : engine_push<SIGMA, false>(a, sel, v.light, v.heavy, gtid, nthreads, gwave, nwaves, nullptr);
   else
     work[0] = engine_pull<SIGMA>(a, gtid, nthreads);
-  block_sum64<BLOCK, 1>(work, lds_work);
-  if (threadIdx.x == 0 && work[0]) add_u64(&a.ctl->acc[slot][F_WORK][0], static_cast<unsigned long long>(work[0]));
+  if (a.count_work || a.probe) {
+    block_sum64<BLOCK, 1>(work, lds_work);
+    if (threadIdx.x == 0 && work[0]) add_u64(&a.ctl->acc[slot][F_WORK][0], static_cast<unsigned long long>(work[0]));
+  }
 }
 
 // ------------------------------------------------------------ Stage 2
 
-// A run of queue descriptors (kind 0: first slice a, slice count b, frontier
-// bits c, set d) or heavy edge chunks (kind 1: vertex a) starting at `out`.
-struct ExpandRec {
-  unsigned long long out;
-  uint32_t n, kind, a, b, c, d;
-};
-constexpr int kExpandMin = 8;
-constexpr int kMaxExpand = 128;
+// Row pointers rp[s*SIGMA .. s*SIGMA + SIGMA] of a slice set's vertices with
+// 16-byte loads. rp is padded on the device to N_s*SIGMA + 1 entries (the
+// tail repeats m), and s*SIGMA*4 is a multiple of 16, so the loads are aligned
+// and in bounds.
+template <int SIGMA>
+__device__ __forceinline__ void load_set_rp(const int32_t* __restrict__ rp, long long s, int (&r)[SIGMA + 1]) {
+  const int4* p = reinterpret_cast<const int4*>(rp + s * SIGMA);
+#pragma unroll
+  for (int i = 0; i < SIGMA / 4; ++i) {
+    const int4 q = p[i];
+    r[4 * i + 0] = q.x;
+    r[4 * i + 1] = q.y;
+    r[4 * i + 2] = q.z;
+    r[4 * i + 3] = q.w;
+  }
+  r[SIGMA] = rp[s * SIGMA + SIGMA];
+}
 
-template <int SIGMA, int BLOCK>
-__device__ void finalize(const BfsArgs& a, int new_level, int slot_out, int sel_out, long long cumv_in,
-                         long long cume_in, unsigned nblocks) {
+
+// Stage 2 over windows of 2*BLOCK slice sets; set_at(win, k) gives the set
+// handled by this thread in slot k of window win, or -1. Accumulates the
+// level statistics of this block into st[]. Output space in the queue and the
+// push lists is reserved per window with one device atomic per list (grid
+// mode) or from the block-local cursors `local` (one workgroup alone: no
+// atomics; the totals are stored by the caller). Queue descriptors and heavy
+// edge chunks are written wave-cooperatively: each lane finds the run that
+// owns its output index by a binary search over the wave's prefix sums, so a
+// hub set with thousands of VSSs costs a few wave steps, not a serial loop.
+template <int SIGMA, int BLOCK, bool LOCAL, class SetAt>
+__device__ void finalize_windows(const BfsArgs& a, int new_level, unsigned long long* acc, int sel_out,
+                                 long long win0, long long nwin, long long wstep, SetAt set_at, long long (&st)[5],
+                                 unsigned long long* local) {
   using M = typename MaskOf<SIGMA>::T;
   constexpr int SPT = 2;
-  constexpr long long WIN = static_cast<long long>(BLOCK) * SPT;
   __shared__ int lds32[3 * (BLOCK / 64)];
-  __shared__ long long lds64[5 * (BLOCK / 64)];
   __shared__ unsigned long long bases[3];
-  __shared__ ExpandRec rec[kMaxExpand];
-  __shared__ int nrec;
-  if (threadIdx.x == 0) nrec = 0;
   M* __restrict__ vis = static_cast<M*>(a.vis);
   M* __restrict__ front = static_cast<M*>(a.front);
   uint8_t* __restrict__ mark = a.mark;
   const int32_t* __restrict__ rp = a.rp;
   const uint32_t* __restrict__ sp = a.slice_ptr;
   const uint32_t tau = static_cast<uint32_t>(a.tau);
-  unsigned long long* acc = &a.ctl->acc[slot_out][0][0];
   int32_t* __restrict__ light = a.flight[sel_out];
   unsigned long long* __restrict__ heavy = a.fheavy[sel_out];
   uint4* __restrict__ queue = a.queue[sel_out];
-  long long st[5] = {0, 0, 0, 0, 0};  // frontier, queued slices, frontier edges, deg>=32, deg>=1024
-  const long long nwin = (a.nsets + WIN - 1) / WIN;
-  for (long long win = blockIdx.x; win < nwin; win += nblocks) {
-    const long long base = win * WIN;
+  const int lane = lane_id();
+  for (long long win = win0; win < nwin; win += wstep) {
     M nw[SPT];
-    int cnt[3] = {0, 0, 0};  // light vertices, heavy chunks, VSSs
+    long long sset[SPT];
+    int nl[SPT], nh[SPT], nq[SPT];
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
-      const long long s = base + k * BLOCK + threadIdx.x;
+      const long long s = set_at(win, k);
+      sset[k] = s;
       nw[k] = 0;
-      if (s < a.nsets) {
+      nl[k] = nh[k] = nq[k] = 0;
+      if (s >= 0) {
         const M bits = load_marks<SIGMA>(mark + s * SIGMA);
         if (bits) {
           clear_marks<SIGMA>(mark + s * SIGMA);
@@ -424,100 +508,129 @@ __device__ void finalize(const BfsArgs& a, int new_level, int slot_out, int sel_
             vis[s] = static_cast<M>(old | x);
             front[s] = x;
             nw[k] = x;
-            uint32_t t = x;
-            while (t) {
-              const int b = __builtin_ctz(t);
-              t &= t - 1;
+            int r[SIGMA + 1];
+            load_set_rp<SIGMA>(rp, s, r);
+#pragma unroll
+            for (int b = 0; b < SIGMA; ++b) {
+              if (!((x >> b) & 1u)) continue;
               const long long u = s * SIGMA + b;
-              const int d = rp[u + 1] - rp[u];
+              const int d = r[b + 1] - r[b];
               st[0] += 1;
               st[2] += d;
               st[3] += d >= 32;
               st[4] += d >= 1024;
               if (d > kLightMax)
-                cnt[1] += (d + kHeavyChunk - 1) / kHeavyChunk;
+                nh[k] += (d + kHeavyChunk - 1) / kHeavyChunk;
               else
-                cnt[0] += 1;
+                nl[k] += 1;
               a.levels[a.orig_id ? a.orig_id[u] : u] = new_level;
             }
             const uint32_t ns = sp[s + 1] - sp[s];
-            cnt[2] += static_cast<int>((ns + tau - 1) / tau);
+            nq[k] = static_cast<int>((ns + tau - 1) / tau);
             st[1] += ns;
           }
         }
       }
     }
+    int cnt[3] = {nl[0] + nl[1], nh[0] + nh[1], nq[0] + nq[1]};
     if (!__syncthreads_or(cnt[0] | cnt[1] | cnt[2])) continue;
     int ex[3], tot[3];
     block_exclusive_scan<BLOCK, 3>(cnt, ex, tot, lds32);
     if (threadIdx.x == 0) {
-      bases[0] = tot[0] ? fetch_add_u64(acc + F_LIGHT * kPad, tot[0]) : 0ULL;
-      bases[1] = tot[1] ? fetch_add_u64(acc + F_HEAVY * kPad, tot[1]) : 0ULL;
-      bases[2] = tot[2] ? fetch_add_u64(acc + F_QUEUE * kPad, tot[2]) : 0ULL;
+      if (LOCAL) {
+        for (int f = 0; f < 3; ++f) {
+          bases[f] = local[f];
+          local[f] += tot[f];
+        }
+      } else {
+        bases[0] = tot[0] ? fetch_add_u64(acc + F_LIGHT * kPad, tot[0]) : 0ULL;
+        bases[1] = tot[1] ? fetch_add_u64(acc + F_HEAVY * kPad, tot[1]) : 0ULL;
+        bases[2] = tot[2] ? fetch_add_u64(acc + F_QUEUE * kPad, tot[2]) : 0ULL;
+      }
     }
     __syncthreads();
+    // light vertices: the owning lane writes its (at most SIGMA) entries
     long long ol = static_cast<long long>(bases[0]) + ex[0];
-    long long oh = static_cast<long long>(bases[1]) + ex[1];
-    long long oq = static_cast<long long>(bases[2]) + ex[2];
-    // Runs longer than kExpandMin entries (hub slice sets, high-degree
-    // vertices) are recorded in LDS and written by the whole block below.
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
-      if (!nw[k]) continue;
-      const long long s = base + k * BLOCK + threadIdx.x;
-      uint32_t t = nw[k];
-      while (t) {
-        const int b = __builtin_ctz(t);
-        t &= t - 1;
-        const long long u = s * SIGMA + b;
-        const int d = rp[u + 1] - rp[u];
-        if (d > kLightMax) {
-          const int nch = (d + kHeavyChunk - 1) / kHeavyChunk;
-          int r = nch > kExpandMin ? atomicAdd(&nrec, 1) : kMaxExpand;
-          if (r < kMaxExpand) {
-            rec[r] = ExpandRec{static_cast<unsigned long long>(oh), static_cast<uint32_t>(nch), 1u,
-                               static_cast<uint32_t>(u), 0u, 0u, 0u};
-            oh += nch;
-          } else {
-            for (int c = 0; c < d; c += kHeavyChunk)
-              heavy[oh++] = (static_cast<unsigned long long>(u) << 32) | static_cast<unsigned long long>(c);
+      if (!nl[k]) continue;
+      int r[SIGMA + 1];
+      load_set_rp<SIGMA>(rp, sset[k], r);
+#pragma unroll
+      for (int b = 0; b < SIGMA; ++b)
+        if (((nw[k] >> b) & 1u) && r[b + 1] - r[b] <= kLightMax) light[ol++] = static_cast<int32_t>(sset[k] * SIGMA + b);
+    }
+    // queue descriptors and heavy chunks: wave-cooperative expansion
+    long long oq = static_cast<long long>(bases[2]) + ex[2];
+    long long oh = static_cast<long long>(bases[1]) + ex[1];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+      const uint32_t s0 = nq[k] ? sp[sset[k]] : 0u;
+      const uint32_t ns = nq[k] ? sp[sset[k] + 1] - s0 : 0u;
+      {  // VSS descriptors of this lane's set k
+        const int incl = wave_inclusive_scan(nq[k]);
+        const int total = __shfl(incl, 63, 64);
+        for (int b0 = 0; b0 < total; b0 += 64) {
+          const int i = b0 + lane;
+          int lo = 0;
+#pragma unroll
+          for (int stp = 32; stp >= 1; stp >>= 1)
+            if (__shfl(incl, lo + stp - 1, 64) <= i) lo += stp;
+          const int owner = lo & 63;
+          const int start = __shfl(incl, owner, 64) - __shfl(nq[k], owner, 64);
+          const long long o = __shfl(oq, owner, 64);
+          const uint32_t os0 = __shfl(s0, owner, 64), ons = __shfl(ns, owner, 64);
+          const uint32_t obits = __shfl(static_cast<uint32_t>(nw[k]), owner, 64);
+          const long long os = __shfl(sset[k], owner, 64);
+          if (i < total) {
+            const uint32_t j = static_cast<uint32_t>(i - start), off = j * tau;
+            queue[o + j] = make_uint4(os0 + off, min(tau, ons - off), obits, static_cast<uint32_t>(os));
           }
-        } else {
-          light[ol++] = static_cast<int32_t>(u);
         }
+        oq += nq[k];
       }
-      const uint32_t s0 = sp[s], ns = sp[s + 1] - s0;
-      const uint32_t nq = (ns + tau - 1) / tau;
-      int r = nq > static_cast<uint32_t>(kExpandMin) ? atomicAdd(&nrec, 1) : kMaxExpand;
-      if (r < kMaxExpand) {
-        rec[r] = ExpandRec{static_cast<unsigned long long>(oq), nq, 0u, s0, ns, static_cast<uint32_t>(nw[k]),
-                           static_cast<uint32_t>(s)};
-        oq += nq;
-      } else {
-        for (uint32_t off = 0; off < ns; off += tau)
-          queue[oq++] =
-              make_uint4(s0 + off, min(tau, ns - off), static_cast<uint32_t>(nw[k]), static_cast<uint32_t>(s));
+      {  // heavy edge chunks of this lane's set k
+        const int incl = wave_inclusive_scan(nh[k]);
+        const int total = __shfl(incl, 63, 64);
+        for (int b0 = 0; b0 < total; b0 += 64) {
+          const int i = b0 + lane;
+          int lo = 0;
+#pragma unroll
+          for (int stp = 32; stp >= 1; stp >>= 1)
+            if (__shfl(incl, lo + stp - 1, 64) <= i) lo += stp;
+          const int owner = lo & 63;
+          const int start = __shfl(incl, owner, 64) - __shfl(nh[k], owner, 64);
+          const long long o = __shfl(oh, owner, 64);
+          const uint32_t obits = __shfl(static_cast<uint32_t>(nw[k]), owner, 64);
+          const long long os = __shfl(sset[k], owner, 64);
+          if (i < total) {
+            int j = i - start;
+            int r[SIGMA + 1];
+            load_set_rp<SIGMA>(rp, os, r);
+#pragma unroll
+            for (int b = 0; b < SIGMA; ++b) {
+              const int d = r[b + 1] - r[b];
+              if (!((obits >> b) & 1u) || d <= kLightMax || j < 0) continue;
+              const int nch = (d + kHeavyChunk - 1) / kHeavyChunk;
+              if (j < nch)
+                heavy[o + (i - start)] = (static_cast<unsigned long long>(os * SIGMA + b) << 32) |
+                                         static_cast<unsigned long long>(j * kHeavyChunk);
+              j -= nch;
+            }
+          }
+        }
+        oh += nh[k];
       }
     }
-    __syncthreads();
-    const int nr = min(nrec, kMaxExpand);
-    for (int r = 0; r < nr; ++r) {
-      const ExpandRec e = rec[r];
-      if (e.kind == 0) {
-        for (uint32_t i = threadIdx.x; i < e.n; i += BLOCK) {
-          const uint32_t off = i * tau;
-          queue[e.out + i] = make_uint4(e.a + off, min(tau, e.b - off), e.c, e.d);
-        }
-      } else {
-        for (uint32_t i = threadIdx.x; i < e.n; i += BLOCK)
-          heavy[e.out + i] = (static_cast<unsigned long long>(e.a) << 32) |
-                             static_cast<unsigned long long>(i * static_cast<uint32_t>(kHeavyChunk));
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) nrec = 0;
     __syncthreads();
   }
+}
+
+// Adds a block's Stage 2 statistics to the level slot (block 0 also carries
+// the cumulative counts of the previous level).
+template <int BLOCK>
+__device__ void finalize_stats(unsigned long long* acc, long long (&st)[5], long long cumv_in, long long cume_in) {
+  __shared__ long long lds64[5 * (BLOCK / 64)];
   block_sum64<BLOCK, 5>(st, lds64);
   if (threadIdx.x == 0) {
     if (st[0]) {
@@ -535,6 +648,82 @@ __device__ void finalize(const BfsArgs& a, int new_level, int slot_out, int sel_
       add_u64(acc + F_CUMV * kPad, cumv_in);
       add_u64(acc + F_CUME * kPad, cume_in);
     }
+  }
+}
+
+// Stage 2 of the whole grid: every slice set, windows spread over the blocks.
+template <int SIGMA, int BLOCK>
+__device__ void finalize(const BfsArgs& a, int new_level, int slot_out, int sel_out, long long cumv_in,
+                         long long cume_in, unsigned nblocks) {
+  constexpr long long WIN = static_cast<long long>(BLOCK) * 2;
+  unsigned long long* acc = &a.ctl->acc[slot_out][0][0];
+  long long st[5] = {0, 0, 0, 0, 0};  // frontier, queued slices, frontier edges, deg>=32, deg>=1024
+  const long long nsets = a.nsets;
+  const long long tid = threadIdx.x;
+  finalize_windows<SIGMA, BLOCK, false>(a, new_level, acc, sel_out, blockIdx.x, (nsets + WIN - 1) / WIN, nblocks,
+                                        [=](long long win, int k) -> long long {
+                                          const long long s = win * WIN + k * BLOCK + tid;
+                                          return s < nsets ? s : -1;
+                                        },
+                                        st, nullptr);
+  finalize_stats<BLOCK>(acc, st, cumv_in, cume_in);
+}
+
+// ------------------------------------------------- single-workgroup levels
+//
+// A level whose Stage 1 can mark at most kSingleMaxMarks rows (BVSS: queued
+// slices; push: frontier edges) is run by workgroup 0 alone: the engine
+// records every slice set it marks in an LDS hash set, and Stage 2 finalises
+// only those sets, with workgroup barriers instead of device-wide ones. The
+// other workgroups wait on a flag until workgroup 0 reaches a level that is
+// not small (or the end), then all continue together.
+
+__device__ __forceinline__ bool single_eligible(const BfsArgs& a, int engine, const LevelView& v) {
+  if (!a.single_block || a.probe) return false;
+  if (engine == BLEST_ENGINE_BVSS) return v.qslices <= kSingleMaxMarks;
+  if (engine == BLEST_ENGINE_PUSH) return v.fedges <= kSingleMaxMarks;
+  return false;
+}
+
+// Stage 2 of one workgroup over the sets recorded during Stage 1 (the LDS
+// list after the hash set); empties both. Output cursors are block-local and
+// the level's counters are stored at the end (the slot was zeroed before).
+template <int SIGMA, int BLOCK>
+__device__ void finalize_list(const BfsArgs& a, int new_level, int slot_out, int sel_out, long long cumv_in,
+                              long long cume_in, int* hs) {
+  constexpr int WIN = BLOCK * 2;
+  __shared__ unsigned long long local[3];
+  __shared__ long long lds64[5 * (BLOCK / 64)];
+  unsigned long long* acc = &a.ctl->acc[slot_out][0][0];
+  if (threadIdx.x < 3) local[threadIdx.x] = 0ULL;
+  __syncthreads();
+  const int count = hs[kSingleHash];
+  const int* list = hs + kSingleHash + 1;
+  long long st[5] = {0, 0, 0, 0, 0};
+  const int tid = threadIdx.x;
+  finalize_windows<SIGMA, BLOCK, true>(a, new_level, acc, sel_out, 0, (count + WIN - 1) / WIN, 1,
+                                       [=](long long win, int k) -> long long {
+                                         const long long i = win * WIN + k * BLOCK + tid;
+                                         return i < count ? static_cast<long long>(list[i]) : -1;
+                                       },
+                                       st, local);
+  __syncthreads();
+  for (int i = tid; i < kSingleHash + 1; i += BLOCK) hs[i] = (i == kSingleHash) ? 0 : -1;
+  block_sum64<BLOCK, 5>(st, lds64);
+  if (threadIdx.x == 0) {
+    auto put = [&](int f, unsigned long long v) {
+      __hip_atomic_store(acc + f * kPad, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    put(F_LIGHT, local[0]);
+    put(F_HEAVY, local[1]);
+    put(F_QUEUE, local[2]);
+    put(F_FRONTIER, static_cast<unsigned long long>(st[0]));
+    put(F_QSLICES, static_cast<unsigned long long>(st[1]));
+    put(F_FEDGES, static_cast<unsigned long long>(st[2]));
+    put(F_DEG32, static_cast<unsigned long long>(st[3]));
+    put(F_DEG1024, static_cast<unsigned long long>(st[4]));
+    put(F_CUMV, static_cast<unsigned long long>(cumv_in + st[0]));
+    put(F_CUME, static_cast<unsigned long long>(cume_in + st[2]));
   }
 }
 
@@ -615,9 +804,52 @@ __device__ __forceinline__ void log_level(const BfsArgs& a, int level, const Lev
 
 // ------------------------------------------------------ persistent kernel
 
+// Waits until every wave of the block has its memory operations performed,
+// then synchronises the block.
+__device__ __forceinline__ void block_sync_mem() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
+// Workgroup 0 runs consecutive small levels alone, starting at `level` with
+// its view, chosen engine and features. Returns the first level it did not
+// run (its slot holds that level's statistics).
+template <int SIGMA, class SliceT, int BLOCK>
+__device__ int single_episode(const BfsArgs& a, int level, int engine, int fallback, float (&feat)[kMaxSwitchFeatures],
+                              LevelView v, const float* s_mlp, int* hs) {
+  const long long gtid = threadIdx.x, nthreads = BLOCK;
+  const long long gwave = wave_in_block(), nwaves = BLOCK / 64;
+  for (;;) {
+    const int slot = level % kStatSlots, nslot = (level + 1) % kStatSlots;
+    if (threadIdx.x == 0) log_level(a, level, v, engine, fallback, feat);
+    if (threadIdx.x < kStatFields)
+      __hip_atomic_store(&a.ctl->acc[nslot][threadIdx.x][0], 0ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    block_sync_mem();
+    run_engine<SIGMA, SliceT, BLOCK>(a, engine, level & 1, slot, v, gtid, nthreads, gwave, nwaves, hs);
+    block_sync_mem();
+    if (threadIdx.x == 0 && level < a.log_cap) a.log[level].t_mid = dev_ticks();
+    finalize_list<SIGMA, BLOCK>(a, level + 1, nslot, (level & 1) ^ 1, v.cumv, v.cume, hs);
+    block_sync_mem();
+    if (threadIdx.x == 0 && level < a.log_cap) {
+      a.log[level].t_end = dev_ticks();
+      a.log[level].work = static_cast<long long>(ld_relaxed_u64(&a.ctl->acc[slot][F_WORK][0]));
+    }
+    const long long prev = v.frontier;
+    ++level;
+    v = read_level_atomic(a.ctl, level % kStatSlots);
+    if (v.frontier == 0) return level;
+    if (__hip_atomic_load(&a.ctl->error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return level;
+    level_features(feat, v, a.n, a.m, level, prev);
+    engine = choose_engine(a, v, feat, level, s_mlp, &fallback);
+    if (!single_eligible(a, engine, v)) return level;
+  }
+}
+
 template <int SIGMA, class SliceT, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
   extern __shared__ float s_mlp[];
+  __shared__ int hs[kSingleLds];
+  __shared__ int s_level;
   const unsigned nblocks = gridDim.x;
   const long long nthreads = static_cast<long long>(nblocks) * BLOCK;
   const long long gtid = static_cast<long long>(blockIdx.x) * BLOCK + threadIdx.x;
@@ -625,21 +857,64 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
   const long long nwaves = static_cast<long long>(nblocks) * (BLOCK / 64);
   const bool learned = a.policy == BLEST_POLICY_LEARNED && a.mlp != nullptr && a.mlp->valid;
   if (learned) mlp_to_lds(a.mlp, s_mlp);
+  for (int i = threadIdx.x; i < kSingleHash + 1; i += BLOCK) hs[i] = (i == kSingleHash) ? 0 : -1;
   clear_state<SIGMA>(a, gtid, nthreads);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->single_gen[0] = 0u;
   BarrierCtx bc;
   if (!barrier_register(a.ctl, &bc, a.timeout_ticks)) return;
   if (blockIdx.x == 0) seed_source<SIGMA>(a);
   if (!grid_barrier(a.ctl, bc)) return;
-  long long prev_frontier = 0;
+  unsigned episodes = 0;
   int level = 0;
-  for (;; ++level) {
+  for (;;) {
     const int slot = level % kStatSlots;
     const LevelView v = read_level(a.ctl, slot);
     if (v.frontier == 0) break;
+    const long long prev_frontier = level > 0 ? read_level(a.ctl, (level + kStatSlots - 1) % kStatSlots).frontier : 0;
     float feat[kMaxSwitchFeatures];
     level_features(feat, v, a.n, a.m, level, prev_frontier);
     int fallback = 0;
     const int engine = choose_engine(a, v, feat, level, learned ? s_mlp : nullptr, &fallback);
+    if (single_eligible(a, engine, v)) {
+      ++episodes;
+      if (blockIdx.x == 0) {
+        const int next = single_episode<SIGMA, SliceT, BLOCK>(a, level, engine, fallback, feat, v,
+                                                              learned ? s_mlp : nullptr, hs);
+        block_sync_mem();
+        if (threadIdx.x == 0) {
+          __hip_atomic_store(&a.ctl->single_level[0], next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&a.ctl->single_gen[0], episodes, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          // counters were updated by device atomics during the episode; drop
+          // any cached copies before the plain loads of grid mode
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          s_level = next;
+        }
+      } else if (threadIdx.x == 0) {
+        // wait for workgroup 0 to finish the episode (bounded like a barrier)
+        const unsigned long long t0 = dev_ticks();
+        bool ok = true;
+        while (__hip_atomic_load(&a.ctl->single_gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < episodes) {
+          if (__hip_atomic_load(&a.ctl->error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            ok = false;
+            break;
+          }
+          if (dev_ticks() - t0 > a.timeout_ticks) {
+            __hip_atomic_store(&a.ctl->error[0], static_cast<int>(BLEST_ERR_TIMEOUT), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_level = ok ? __hip_atomic_load(&a.ctl->single_level[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
+      }
+      __syncthreads();
+      if (s_level < 0 || __hip_atomic_load(&a.ctl->error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+        return;
+      level = s_level;
+      continue;
+    }
     if (blockIdx.x == 0) {
       if (threadIdx.x == 0) log_level(a, level, v, a.probe ? -1 : engine, fallback, feat);
       const int nslot = (level + 1) % kStatSlots;
@@ -664,7 +939,7 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
       a.log[level].t_end = dev_ticks();
       a.log[level].work = static_cast<long long>(a.ctl->acc[slot][F_WORK][0]);
     }
-    prev_frontier = v.frontier;
+    ++level;
   }
   if (blockIdx.x == 0) {
     // Nothing reads the XCD registration after barrier_register; clear it
@@ -829,6 +1104,8 @@ BfsArgs bfs_args(const DevGraph& g) {
   a.log_cap = g.log_cap;
   a.mlp = g.mlp;
   a.prefilter = g.prefilter;
+  a.count_work = g.count_work;
+  a.single_block = g.single_block;
   a.timeout_ticks = 1000000000ULL;  // 10 s at the 100 MHz device clock
   return a;
 }

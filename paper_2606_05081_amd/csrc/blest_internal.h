@@ -59,6 +59,8 @@ struct alignas(256) Ctl {
   int error[kPad * 2];   // first device-side error (BLEST_ERR_*), 0 if none
   int done[kPad * 2];    // per-stage launch mode: 1 once the frontier is empty
   int overflow[kPad * 2];
+  int single_level[kPad];          // first level after a single-workgroup episode
+  unsigned int single_gen[kPad];   // number of finished single-workgroup episodes
   int nlevels[kPad * 2]; // frontier levels of the last traversal
 };
 
@@ -79,6 +81,7 @@ struct MlpDev {
   float params[BLEST_MLP_NPARAMS];
   float mean[BLEST_MLP_IN];
   float inv_std[BLEST_MLP_IN];
+  float max_ratio;  // network used only if sum_k exp(z_k - z_max) <= max_ratio (= 1 / min confidence)
   int valid;
 };
 
@@ -110,6 +113,8 @@ struct BfsArgs {
   uint64_t seed;
   int32_t probe;
   int32_t prefilter;
+  int32_t count_work;  // accumulate F_WORK (adjacency entries read per level)
+  int32_t single_block;  // run small levels on workgroup 0 alone
   unsigned long long timeout_ticks;
 };
 
@@ -135,7 +140,7 @@ struct DevGraph {
   int log_cap = 0;
   MlpDev* mlp = nullptr;
   int* host_flags = nullptr;  // pinned: done flag readback of the per-stage mode
-  int block = 512, grid = 0, num_cu = 0, persistent = 1, prefilter = 1;
+  int block = 512, grid = 0, num_cu = 0, persistent = 1, prefilter = 1, count_work = 0, single_block = 1;
   double tick_us = 0.01;      // device clock period in microseconds
 };
 

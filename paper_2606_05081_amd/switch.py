@@ -78,12 +78,31 @@ def probe_graph(g, srcs, max_levels_per_run=None, rng=None):
             np.array(heur, np.int32), np.array(run_ids, np.int32))
 
 
-def labels_from_times(times, heur):
+LABEL_MARGIN = 0.05     # another engine must beat Eq. 3's choice by 5% to become the label
+MIN_CONFIDENCE = 0.6    # inference trusts the network only above this softmax probability
+
+
+def labels_from_times(times, heur, margin=LABEL_MARGIN):
+    """Fastest engine, unless Eq. 3's choice is within `margin` of it."""
     y = np.argmin(times, axis=1).astype(np.int32)
     best = times[np.arange(len(y)), y]
-    tie = times[np.arange(len(y)), heur] <= best * 1.0 + 1e-9
-    y[tie] = heur[tie]
+    keep = times[np.arange(len(y)), heur] <= best * (1.0 + margin) + 1e-9
+    y[keep] = heur[keep]
     return y
+
+
+def cost_weights(times, family):
+    """Cost-sensitive sample weights: a level weighs as much as the time a
+    wrong choice can lose there (max - min engine time), normalised so every
+    graph family carries the same total weight."""
+    span = (times.max(axis=1) - times.min(axis=1)).astype(np.float64)
+    span = np.maximum(span, 1e-3 * times.min(axis=1))
+    w = np.zeros(len(span))
+    fams = np.unique(family)
+    for f in fams:
+        m = family == f
+        w[m] = span[m] / span[m].sum()
+    return (w * (len(w) / w.sum())).astype(np.float32)
 
 
 def balanced_weights(y, family):
@@ -135,23 +154,30 @@ def train(X, y, w, steps=4000, batch=256, lr=1e-3, seed=1):
     return p.cpu().numpy(), mean.astype(np.float32), std, losses.cpu().numpy()
 
 
-def predict(params, mean, std, X):
-    """Engine choices of the network on the GPU (blest_mlp_forward); -1 = out of range (Eq. 3 fallback)."""
+def predict(params, mean, std, X, min_confidence=None):
+    """Engine choices of the network on the GPU (blest_mlp_forward); -1 where the
+    kernel falls back to Eq. 3 (input outside [-6, 6] or confidence below the floor)."""
     import torch
     from . import blest
     Z = ((X - mean) / std).astype(np.float32)
     dev = torch.device("cuda", 0)
     logits = torch.empty((len(Z), 3), dtype=torch.float32, device=dev)
     blest.blest_mlp_forward(torch.tensor(params, device=dev), torch.tensor(Z, device=dev), logits)
-    ch = logits.cpu().numpy().argmax(axis=1).astype(np.int32)
+    lg = logits.cpu().numpy().astype(np.float64)
+    ch = lg.argmax(axis=1).astype(np.int32)
     ch[(np.abs(Z) > 6).any(axis=1)] = -1
+    if min_confidence is not None:
+        p = np.exp(lg - lg.max(axis=1, keepdims=True))
+        p /= p.sum(axis=1, keepdims=True)
+        ch[p.max(axis=1) < min_confidence] = -1
     return ch
 
 
-def save_model(params, mean, std, meta, path=MODEL_PATH):
+def save_model(params, mean, std, meta, path=MODEL_PATH, min_confidence=MIN_CONFIDENCE):
     with open(path, "w") as f:
         json.dump({"params": [float(x) for x in params], "mean": [float(x) for x in mean],
-                   "std": [float(x) for x in std], "features": FEATURES, "engines": ENGINES, "meta": meta}, f)
+                   "std": [float(x) for x in std], "min_confidence": min_confidence, "features": FEATURES,
+                   "engines": ENGINES, "meta": meta}, f)
 
 
 def load_model(path=MODEL_PATH):
@@ -185,10 +211,10 @@ def evaluate_graph(kind, size, seed, params, mean, std, n_sources=16, log=print)
     from . import blest, inputs
     rp, col = make_graph(kind, size, seed)
     g = blest.Graph(rp, col, **{"async": 1})
-    g.set_switch_model(params, mean, std)
+    g.set_switch_model(params, mean, std, MIN_CONFIDENCE)
     srcs = inputs.sources(rp, n_sources, seed=seed + 1)
     X, T, Hc, _ = probe_graph(g, srcs[: max(4, n_sources // 4)])
-    ch = predict(params, mean, std, X)
+    ch = predict(params, mean, std, X, MIN_CONFIDENCE)
     ch = np.where(ch < 0, Hc, ch)
     res = {"graph": f"{kind}{size}", "levels": int(len(X)), "regret_learned": regret(T, ch),
            "regret_heuristic": regret(T, Hc), "misclassified_learned": float((ch != T.argmin(1)).mean()),
@@ -232,11 +258,11 @@ def main(argv=None):
     args = ap.parse_args(argv)
     X, T, Hc, fam = build_dataset(runs_per_graph=args.runs_per_graph)
     y = labels_from_times(T, Hc)
-    w = balanced_weights(y, fam)
+    w = cost_weights(T, fam)
     print(f"[train] {len(y)} levels, label counts {np.bincount(y, minlength=3).tolist()}", flush=True)
     t0 = time.time()
     params, mean, std, losses = train(X, y, w, steps=args.steps)
-    ch = predict(params, mean, std, X)
+    ch = predict(params, mean, std, X, MIN_CONFIDENCE)
     ch = np.where(ch < 0, Hc, ch)
     meta = {"levels": int(len(y)), "label_counts": np.bincount(y, minlength=3).tolist(),
             "train_loss_first": float(losses[:50].mean()), "train_loss_last": float(losses[-50:].mean()),

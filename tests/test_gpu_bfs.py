@@ -72,6 +72,7 @@ def test_rmat_s16_all_policies(blest):
     dict(sigma=16), dict(sigma=32), dict(tau=64), dict(tau=256), dict(tau=192), dict(wide_slices=1),
     dict(block_size=256), dict(block_size=1024), dict(persistent=0), dict(prefilter=0), dict(reorder=1),
     dict(reorder=0), dict(blocks_per_cu=1), dict(sigma=16, tau=64, block_size=256, persistent=0),
+    dict(single_block=0), dict(single_block=0, block_size=512), dict(block_size=256, sigma=32),
 ])
 def test_option_matrix(blest, opt):
     for rp, col in [inputs.rmat_graph(13, 77), inputs.grid_graph(70, 78)]:
@@ -152,9 +153,10 @@ def test_rcm_export_is_bvss_of_permuted_graph(blest):
     g.close()
 
 
-def test_level_log_matches_oracle_counts_and_eq3_replay(blest):
+@pytest.mark.parametrize("single", [1, 0])
+def test_level_log_matches_oracle_counts_and_eq3_replay(blest, single):
     for rp, col in [inputs.rmat_graph(16, 1010), inputs.grid_graph(96, 4)]:
-        g = blest.Graph(rp, col, reorder=0)
+        g = blest.Graph(rp, col, reorder=0, single_block=single)
         b = g.export_bvss()
         for s in inputs.sources(rp, 3, seed=12):
             s = int(s)

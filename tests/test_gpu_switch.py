@@ -1,0 +1,76 @@
+"""The learned engine switch: what the trained network gains over Eq. 3.
+
+Regret (Sum(t_chosen - t_min) / Sum(t_min), following the paper's per-level
+analysis of its switch) is computed for the learned and the Eq. 3 choices
+from the SAME probe-mode timings, so the comparison does not depend on run to
+run timing noise. Levels are exact regardless of the choices."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_05081_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2606_05081_amd import blest, switch
+    assert torch.cuda.is_available()
+    return blest, switch
+
+
+def test_small_training_run_beats_eq3_on_held_out_graph(env, capsys):
+    blest, switch = env
+    specs = [("rmat", 15, 4015), ("rmat", 16, 4016), ("rmat", 17, 4017), ("grid", 256, 4100), ("grid", 384, 4101)]
+    X, T, H, fam = switch.build_dataset(specs, runs_per_graph=8, grid_levels_per_run=48, log=lambda *a: None)
+    y = switch.labels_from_times(T, H)
+    w = switch.cost_weights(T, fam)
+    params, mean, std, losses = switch.train(X, y, w, steps=2000)
+    assert losses[-100:].mean() < losses[:50].mean()
+    ch = switch.predict(params, mean, std, X, switch.MIN_CONFIDENCE)
+    ch = np.where(ch < 0, H, ch)
+    r_train_l, r_train_h = switch.regret(T, ch), switch.regret(T, H)
+    # held-out graph of the R-MAT family, seeds disjoint from training
+    rp, col = inputs.rmat_graph(18, 4918)
+    g = blest.Graph(rp, col)
+    g.set_switch_model(params, mean, std, switch.MIN_CONFIDENCE)
+    Xh, Th, Hh, _ = switch.probe_graph(g, inputs.sources(rp, 8, seed=4919))
+    chh = switch.predict(params, mean, std, Xh, switch.MIN_CONFIDENCE)
+    chh = np.where(chh < 0, Hh, chh)
+    r_l, r_h = switch.regret(Th, chh), switch.regret(Th, Hh)
+    with capsys.disabled():
+        print(f"\n[switch] train regret learned {r_train_l:.4f} vs Eq.3 {r_train_h:.4f}; "
+              f"held-out R-MAT s18 regret learned {r_l:.4f} vs Eq.3 {r_h:.4f}")
+    assert r_train_l <= r_train_h + 1e-9
+    assert r_l <= r_h + 0.02
+    # the learned policy returns exact levels
+    g.set_policy(blest.Policy.LEARNED)
+    for s in inputs.sources(rp, 3, seed=4920):
+        assert np.array_equal(g.bfs(int(s)).cpu().numpy(), oracle.bfs(rp, col, int(s)))
+    g.close()
+
+
+def test_committed_model_on_held_out_graphs(env, capsys):
+    blest, switch = env
+    if not os.path.exists(switch.MODEL_PATH):
+        pytest.skip("no trained model committed yet (python -m paper_2606_05081_amd.switch)")
+    params, mean, std, meta = switch.load_model()
+    for kind, size, seed in [("rmat", 20, 4920), ("grid", 1024, 4921)]:
+        rp, col = switch.make_graph(kind, size, seed)
+        g = blest.Graph(rp, col)
+        g.set_switch_model(params, mean, std, meta.get("min_confidence", 0.5))
+        X, T, H, _ = switch.probe_graph(g, inputs.sources(rp, 4, seed=seed + 1), 64 if kind == "grid" else None)
+        ch = switch.predict(params, mean, std, X, meta.get("min_confidence", 0.5))
+        ch = np.where(ch < 0, H, ch)
+        r_l, r_h = switch.regret(T, ch), switch.regret(T, H)
+        with capsys.disabled():
+            print(f"\n[switch] committed model on {kind}{size}: regret learned {r_l:.4f} vs Eq.3 {r_h:.4f}")
+        assert r_l <= r_h + 0.02
+        g.set_policy(blest.Policy.LEARNED)
+        s = int(inputs.sources(rp, 1, seed=seed + 2)[0])
+        assert np.array_equal(g.bfs(s).cpu().numpy(), oracle.bfs(rp, col, s))
+        g.close()

@@ -7,9 +7,18 @@ from paper_2606_05081_amd import autotune, switch
 
 
 def test_labels_prefer_fastest_and_break_ties_to_eq3():
-    T = np.array([[3.0, 1.0, 2.0], [1.0, 1.0, 5.0], [2.0, 2.0, 2.0]], np.float32)
-    H = np.array([0, 1, 2], np.int32)
-    assert switch.labels_from_times(T, H).tolist() == [1, 1, 2]
+    T = np.array([[3.0, 1.0, 2.0], [1.0, 1.0, 5.0], [2.0, 2.0, 2.0], [1.03, 1.0, 9.0]], np.float32)
+    H = np.array([0, 1, 2, 0], np.int32)
+    # the last level: Eq. 3's choice is within the 5% margin, so it stays the label
+    assert switch.labels_from_times(T, H).tolist() == [1, 1, 2, 0]
+
+
+def test_cost_weights_follow_time_at_stake_per_family():
+    T = np.array([[1.0, 2.0, 3.0], [1.0, 1.0, 1.0], [10.0, 1.0, 1.0], [5.0, 5.0, 6.0]])
+    fam = np.array(["a", "a", "b", "b"])
+    w = switch.cost_weights(T, fam)
+    assert np.isclose(w[fam == "a"].sum(), w[fam == "b"].sum())
+    assert w[0] > w[1] and w[2] > w[3]
 
 
 def test_regret_definition():
