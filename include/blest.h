@@ -96,7 +96,12 @@ typedef struct {
   int32_t device;       /* HIP device ordinal, -1 = current device */
   int32_t single_block; /* 1 (default): levels whose Stage 1 can mark at most 4096 rows run on one
                            workgroup with workgroup barriers instead of device-wide ones */
-  int32_t reserved[6];
+  int32_t panel;        /* panel-blocked BVSS copy for dense top-down levels (sigma = 8, 32-bit
+                           slices only): 0 = not built, 1 (default) = used when the queued slices
+                           are at least a quarter of all slices, 2 = used at every BVSS level */
+  int32_t panel_log2_rows; /* rows per panel = 2^this, in [5, 16]; 0 (default) = about one panel
+                              per persistent workgroup */
+  int32_t reserved[4];
 } blest_opts;
 
 /* Fills *opts with the defaults listed above. */
@@ -170,7 +175,8 @@ typedef struct {
   int32_t grid_blocks;   /* persistent grid size */
   int32_t block_size;
   int32_t device;
-  int32_t reserved[5];
+  int32_t panel_log2_rows; /* rows per panel of the panel-blocked copy = 2^this; 0 if not built */
+  int32_t reserved[4];
 } blest_graph_stats;
 
 /* Fills *out with structure sizes. Errors: INVALID_ARG. */
@@ -192,7 +198,7 @@ typedef struct {
   double t_stage1_us;   /* device time of the engine's step alone (Stage 1 and its barrier) */
   double t_engine_us[3];/* probe mode: time of each engine from the same state; else -1 */
   int32_t mlp_fallback; /* learned policy: 1 if Eq. 3 was used (input out of range) */
-  int32_t reserved;
+  int32_t bvss_panel;   /* 1 if the BVSS step read the panel-blocked copy (all slices, LDS marks) */
   int64_t work;         /* adjacency entries read by the step's engine: slices (BVSS),
                            CSR edges (push, bottom-up); probe mode: all three engines */
 } blest_level_stat;

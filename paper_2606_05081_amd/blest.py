@@ -72,7 +72,7 @@ class Opts(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("persistent", ctypes.c_int32), ("wide_slices", ctypes.c_int32),
                 ("prefilter", ctypes.c_int32), ("async_", ctypes.c_int32), ("msbfs_width", ctypes.c_int32),
                 ("random_seed", ctypes.c_uint64), ("device", ctypes.c_int32), ("single_block", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("panel", ctypes.c_int32), ("panel_log2_rows", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class GraphStats(ctypes.Structure):
@@ -80,7 +80,8 @@ class GraphStats(ctypes.Structure):
                 ("slice_bytes", ctypes.c_int32), ("reordered", ctypes.c_int32), ("n_slice_sets", ctypes.c_int64),
                 ("n_vss", ctypes.c_int64), ("n_slices", ctypes.c_int64), ("bvss_bytes", ctypes.c_int64),
                 ("csr_bytes", ctypes.c_int64), ("work_bytes", ctypes.c_int64), ("grid_blocks", ctypes.c_int32),
-                ("block_size", ctypes.c_int32), ("device", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("block_size", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("panel_log2_rows", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class LevelStat(ctypes.Structure):
@@ -89,7 +90,7 @@ class LevelStat(ctypes.Structure):
                 ("unvisited", ctypes.c_int64), ("unvisited_edges", ctypes.c_int64), ("deg_ge_32", ctypes.c_int64),
                 ("deg_ge_1024", ctypes.c_int64), ("t_step_us", ctypes.c_double), ("t_stage1_us", ctypes.c_double),
                 ("t_engine_us", ctypes.c_double * 3),
-                ("mlp_fallback", ctypes.c_int32), ("reserved", ctypes.c_int32), ("work", ctypes.c_int64)]
+                ("mlp_fallback", ctypes.c_int32), ("bvss_panel", ctypes.c_int32), ("work", ctypes.c_int64)]
 
 
 # Every exported symbol of the C ABI: name -> (restype, argtypes).

@@ -109,7 +109,7 @@ blest_status wait_and_check(blest_graph* g, hipStream_t st) {
   if (flags[0] != 0) {
     // Leave the working state clean for the next call.
     CK(hipMemset(g->d.ctl, 0, sizeof(blest::Ctl)));
-    CK(hipMemset(g->d.mark, 0, static_cast<size_t>(g->d.nsets) * g->d.sigma));
+    CK(hipMemset(g->d.mark, 0, g->d.mark_bytes));
     blest::ms_reset(&g->ms);
     if (flags[0] == BLEST_ERR_TIMEOUT) return fail(BLEST_ERR_TIMEOUT, "device-wide barrier timed out");
     if (flags[0] == BLEST_ERR_OVERFLOW) return fail(BLEST_ERR_OVERFLOW, "a distance exceeds the int16 range");
@@ -176,6 +176,7 @@ void blest_default_opts(blest_opts* o) {
   o->random_seed = 1;
   o->device = -1;
   o->single_block = 1;
+  o->panel = 1;
 }
 
 blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_graph** out) {
@@ -196,6 +197,9 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   if (!(o.eta >= 0.0f)) return fail(BLEST_ERR_INVALID_ARG, "eta must be >= 0");
   if (o.msbfs_width != 64 && o.msbfs_width != 128 && o.msbfs_width != 256 && o.msbfs_width != 512)
     return fail(BLEST_ERR_UNSUPPORTED, "msbfs_width must be 64, 128, 256 or 512");
+  if (o.panel < 0 || o.panel > 2) return fail(BLEST_ERR_INVALID_ARG, "panel must be 0, 1 or 2");
+  if (o.panel_log2_rows != 0 && (o.panel_log2_rows < 5 || o.panel_log2_rows > 16))
+    return fail(BLEST_ERR_UNSUPPORTED, "panel_log2_rows must be 0 (auto) or in [5, 16]");
   const int64_t n = csr->n, m = csr->m;
   std::string why;
   if (!blest::validate_csr(n, m, csr->row_ptr, csr->col_idx, &why)) return fail(BLEST_ERR_INVALID_GRAPH, why);
@@ -226,6 +230,7 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   }
   const bool wide = o.sigma != 8 || o.wide_slices || n > (int64_t(1) << 24);
   blest::Bvss b;
+  blest::Panels pn;
   try {
     blest::build_bvss(n, rp, col, o.sigma, o.tau, wide, &b);
   } catch (...) {
@@ -248,6 +253,26 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   d.prefilter = o.prefilter;
   d.single_block = o.single_block;
   d.tick_us = tick_us;
+  {
+    hipError_t ge = blest::bfs_grid_size(d, 1, o.blocks_per_cu, &d.grid);
+    if (ge != hipSuccess) {
+      delete g;
+      return hip_fail(ge, "bfs_grid_size");
+    }
+  }
+  if (o.panel) {
+    try {
+      const int rb = o.panel_log2_rows ? o.panel_log2_rows : blest::panel_log2_rows(n, d.grid);
+      blest::build_panels(n, b, rb, &pn);
+    } catch (...) {
+      delete g;
+      return fail(BLEST_ERR_OOM, "host allocation during panel build");
+    }
+  }
+  d.npanels = pn.npanels;
+  d.nchunks = pn.nchunks;
+  d.panel_rb = pn.rb;
+  d.panel_mode = pn.npanels > 0 ? o.panel : 0;
   d.log_cap = 1 << 16;
   int64_t nheavy = 0;
   for (int64_t u = 0; u < n; ++u) {
@@ -275,9 +300,25 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   TRY(dalloc_t(g, &d.slice_ptr, ns + 1));
   TRY(dalloc(g, &d.slices, static_cast<size_t>(std::max<int64_t>(b.nslices, 1)) * (wide ? 8 : 4)));
   TRY(dalloc(g, &d.degmask, ns * mb));
-  TRY(dalloc(g, &d.vis, ns * mb));
-  TRY(dalloc(g, &d.front, ns * mb));
-  TRY(dalloc_t(g, &d.mark, ns * static_cast<size_t>(o.sigma)));
+  // The panel engine reads visited words and writes mark bytes in whole
+  // 32-row groups up to the end of the last panel.
+  const size_t prow = static_cast<size_t>(pn.npanels) << pn.rb;
+  // 512 bytes of slack: a wave reads a chunk's frontier window as 64 8-byte
+  // words starting at its first set (rounded down to 8).
+  const size_t state_bytes = std::max(ns * mb, prow / 8) + 512;
+  const size_t mark_bytes = std::max(ns * static_cast<size_t>(o.sigma), prow);
+  TRY(dalloc(g, &d.vis, state_bytes));
+  TRY(dalloc(g, &d.front, state_bytes));
+  TRY(dalloc_t(g, &d.mark, mark_bytes));
+  d.mark_bytes = mark_bytes;
+  if (pn.npanels > 0) {
+    TRY(dalloc_t(g, &d.pwords, pn.words.size()));
+    TRY(dalloc_t(g, &d.pbase, pn.base.size()));
+    TRY(dalloc_t(g, &d.pptr, pn.ptr.size()));
+    TRY(hipMemcpy(d.pwords, pn.words.data(), 4 * pn.words.size(), hipMemcpyHostToDevice));
+    TRY(hipMemcpy(d.pbase, pn.base.data(), 4 * pn.base.size(), hipMemcpyHostToDevice));
+    TRY(hipMemcpy(d.pptr, pn.ptr.data(), 4 * pn.ptr.size(), hipMemcpyHostToDevice));
+  }
   for (int i = 0; i < 2; ++i) {
     TRY(dalloc_t(g, &d.queue[i], static_cast<size_t>(std::max<int64_t>(b.nvss, 1))));
     TRY(dalloc_t(g, &d.flight[i], static_cast<size_t>(n)));
@@ -309,20 +350,20 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
     for (size_t s2 = 0; s2 < ns; ++s2) std::memcpy(&dm[s2 * mb], &b.degmask[s2], mb);  // little endian
     TRY(hipMemcpy(d.degmask, dm.data(), dm.size(), hipMemcpyHostToDevice));
   }
-  TRY(hipMemset(d.mark, 0, ns * o.sigma));
+  TRY(hipMemset(d.mark, 0, mark_bytes));
   TRY(hipMemset(d.ctl, 0, sizeof(blest::Ctl)));
   TRY(hipMemset(d.mlp, 0, sizeof(blest::MlpDev)));
   {
     std::lock_guard<std::mutex> lk(g_model_mu);
     if (g_model_set) TRY(hipMemcpy(d.mlp, &g_model, sizeof(g_model), hipMemcpyHostToDevice));
   }
-  TRY(blest::bfs_grid_size(d, 1, o.blocks_per_cu, &d.grid));
   TRY(hipDeviceSynchronize());
 #undef TRY
   g->real_ptrs = std::move(b.real_ptrs);
   g->slice_ptr = std::move(b.slice_ptr);
   g->csr_bytes = 4 * (n + 1) + 4 * m;
-  g->bvss_bytes = 4 * static_cast<int64_t>(ns + 1) + (wide ? 8 : 4) * b.nslices;
+  g->bvss_bytes = 4 * static_cast<int64_t>(ns + 1) + (wide ? 8 : 4) * b.nslices +
+                  4 * static_cast<int64_t>(pn.words.size() + pn.base.size() + pn.ptr.size());
   g->work_bytes = static_cast<int64_t>(ns * mb * 3 + ns * o.sigma) + 2 * 16 * std::max<int64_t>(b.nvss, 1) +
                   2 * 4 * n + 2 * 8 * d.nheavy_cap;
   g->ms.device = dev;
@@ -380,6 +421,7 @@ blest_status blest_graph_info(const blest_graph* g, blest_graph_stats* out) {
   out->grid_blocks = g->d.grid;
   out->block_size = g->d.block;
   out->device = g->d.device;
+  out->panel_log2_rows = g->d.npanels > 0 ? g->d.panel_rb : 0;
   return BLEST_OK;
 }
 
@@ -409,6 +451,7 @@ blest_status blest_last_level_stats(const blest_graph* g, blest_level_stat* buf,
     o.t_stage1_us = r.t_mid > r.t_begin ? (r.t_mid - r.t_begin) * g->d.tick_us : 0.0;
     for (int e = 0; e < 3; ++e) o.t_engine_us[e] = r.t_engine[e] ? r.t_engine[e] * g->d.tick_us : -1.0;
     o.mlp_fallback = r.fallback;
+    o.bvss_panel = r.panel;
     o.work = r.work;
   }
   return BLEST_OK;

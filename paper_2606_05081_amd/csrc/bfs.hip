@@ -32,7 +32,7 @@ struct LevelView {
 };
 
 __device__ __forceinline__ LevelView read_level(const Ctl* ctl, int slot) {
-  const unsigned long long* acc = &ctl->acc[slot][0][0];
+  const gptr<const unsigned long long> acc = to_global(&ctl->acc[slot][0][0]);
   LevelView v;
   v.frontier = static_cast<long long>(acc[F_FRONTIER * kPad]);
   v.queue = static_cast<long long>(acc[F_QUEUE * kPad]);
@@ -50,7 +50,7 @@ __device__ __forceinline__ LevelView read_level(const Ctl* ctl, int slot) {
 // Same, with agent-scope loads (used inside a single-workgroup episode, where
 // the counters were just updated by device atomics without a barrier).
 __device__ __forceinline__ LevelView read_level_atomic(const Ctl* ctl, int slot) {
-  const unsigned long long* acc = &ctl->acc[slot][0][0];
+  const gptr<const unsigned long long> acc = to_global(&ctl->acc[slot][0][0]);
   LevelView v;
   v.frontier = static_cast<long long>(ld_relaxed_u64(acc + F_FRONTIER * kPad));
   v.queue = static_cast<long long>(ld_relaxed_u64(acc + F_QUEUE * kPad));
@@ -202,12 +202,14 @@ constexpr long long kSingleMaxMarks = 4096;    // keeps the hash set at most hal
 // hs[kSingleHash].
 constexpr int kSingleLds = kSingleHash + 1 + kSingleMaxMarks;
 
-__device__ __forceinline__ void record_set(int* hs, long long s, Ctl* ctl) {
+__device__ __forceinline__ void record_set(lptr<int> hs, long long s, Ctl* ctl) {
   uint32_t h = (static_cast<uint32_t>(s) * 2654435761u) >> (32 - 13);
   for (int probe = 0; probe < kSingleHash; ++probe) {
-    const int old = atomicCAS(&hs[h], -1, static_cast<int>(s));
+    int old = -1;
+    __hip_atomic_compare_exchange_strong(hs + h, &old, static_cast<int>(s), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
     if (old == -1) {
-      const int idx = atomicAdd(&hs[kSingleHash], 1);
+      const int idx = __hip_atomic_fetch_add(hs + kSingleHash, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       hs[kSingleHash + 1 + idx] = static_cast<int>(s);
       return;
     }
@@ -225,18 +227,19 @@ __device__ __forceinline__ void record_set(int* hs, long long s, Ctl* ctl) {
 // (K = tau / 64 slices per lane per VSS).
 template <int SIGMA, class SliceT, int K, bool REC>
 __device__ long long engine_bvss_k(const BfsArgs& a, const uint4* __restrict__ q, long long qlen, long long gwave,
-                                   long long nwaves, int* hs) {
+                                   long long nwaves, lptr<int> hs) {
   long long work = 0;
   using M = typename MaskOf<SIGMA>::T;
   constexpr int G = 4;
-  const SliceT* __restrict__ sl = static_cast<const SliceT*>(a.slices);
-  const M* __restrict__ vis = static_cast<const M*>(a.vis);
-  uint8_t* __restrict__ mark = a.mark;
+  const gptr<const uint4> qg = to_global(q);
+  gptr<const SliceT> __restrict__ sl = to_global(static_cast<const SliceT*>(a.slices));
+  gptr<const M> __restrict__ vis = to_global(static_cast<const M*>(a.vis));
+  gptr<uint8_t> __restrict__ mark = to_global(a.mark);
   const uint32_t lane = static_cast<uint32_t>(lane_id());
   const bool pre = a.prefilter != 0;
   for (long long base = gwave * G; base < qlen; base += nwaves * G) {
     uint4 dl = make_uint4(0u, 0u, 0u, 0u);
-    if (lane < G && base + lane < qlen) dl = q[base + lane];
+    if (lane < G && base + lane < qlen) dl = qg[base + lane];
     uint32_t st[G], cn[G];
     SliceT al[G];
 #pragma unroll
@@ -290,7 +293,7 @@ __device__ long long engine_bvss_k(const BfsArgs& a, const uint4* __restrict__ q
 
 template <int SIGMA, class SliceT, bool REC>
 __device__ long long engine_bvss(const BfsArgs& a, const uint4* __restrict__ q, long long qlen, long long gwave,
-                                 long long nwaves, int* hs) {
+                                 long long nwaves, lptr<int> hs) {
   switch (a.tau) {
     case 64:
       return engine_bvss_k<SIGMA, SliceT, 1, REC>(a, q, qlen, gwave, nwaves, hs);
@@ -303,18 +306,174 @@ __device__ long long engine_bvss(const BfsArgs& a, const uint4* __restrict__ q, 
   }
 }
 
+// E0 on the panel-blocked copy, for dense levels. Workgroup b owns panels
+// b, b + G, ... (2^rb consecutive rows each) and reads every chunk of its
+// panel: 256 slice words, one 16-byte load per lane, plus the chunk's
+// 512-byte window of frontier words (one 8-byte load per lane); a lane finds
+// the frontier word of each of its slices' sets in the window by two wave
+// shuffles. A slice hits when its mask meets that word, and the hit row's bit
+// is set in an LDS bitmap with an LDS atomic. Loads of the next batch of
+// chunks are issued before the current batch is tested. After the panel, the
+// bitmap minus the visited words is written to the mark bytes, 32 rows per
+// pair of 16-byte stores; the workgroup owns those rows, so each new vertex
+// is written once and no visited word is read per hit.
+// Frontier words of sets with no new vertex are stale (they keep an older
+// frontier); their extra hits land on visited rows and are dropped at the
+// flush. pm: LDS scratch of at least 2^(rb-5) words, left filled with ones
+// (the single-workgroup hash set shares it).
+constexpr int kPanelChunk = 256;      // slices per chunk (host layout)
+constexpr int kPanelUnroll = 4;       // chunks per wave per batch
+constexpr int kPanelMaxWords = 2048;  // rb <= 16
+constexpr long long kPanelDenom = 4;  // dense: queued slices >= panel slots / 4
+
+__device__ __forceinline__ bool use_panel(const BfsArgs& a, const LevelView& v) {
+  if (a.npanels <= 0) return false;
+  if (a.panel_mode == 2) return true;
+  return v.qslices > kSingleMaxMarks && kPanelDenom * v.qslices >= a.panel_slots;
+}
+
+struct PanelPtrs {
+  gptr<const uint4> words;    // 64 uint4 per chunk
+  gptr<const uint2> front8;   // 8 frontier bytes per element
+  gptr<const uint32_t> base;  // first set of each chunk
+};
+
+// Loads chunk c (clamped to the panel's last chunk `cl`, so every load is in
+// bounds; the caller skips chunks past the end): this lane's 4 slice words and
+// its 8 bytes of the chunk's frontier window.
+__device__ __forceinline__ void panel_load(const PanelPtrs& pp, uint32_t c, uint32_t cl, uint32_t lane, uint32_t b,
+                                           uint4& w, uint2& f) {
+  w = pp.words[static_cast<size_t>(min(c, cl)) * (kPanelChunk / 4) + lane];
+  f = pp.front8[(b >> 3) + lane];
+}
+
+// Tests the 4 slices of one lane of one chunk; the frontier byte of a slice's
+// set is taken from the lane holding it in the chunk's window.
+__device__ __forceinline__ void panel_test4(const uint4& w, uint32_t b7, const uint2& f, uint32_t dmask, int rshift,
+                                            lptr<uint32_t> pm) {
+  const uint32_t s[4] = {w.x, w.y, w.z, w.w};
+  uint32_t d[4], lo[4], hi[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    d[q] = ((s[q] >> 8) & dmask) + b7;
+    const int src = static_cast<int>(d[q] >> 3);
+    lo[q] = static_cast<uint32_t>(__shfl(static_cast<int>(f.x), src, 64));
+    hi[q] = static_cast<uint32_t>(__shfl(static_cast<int>(f.y), src, 64));
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t al = (((d[q] >> 2) & 1u) ? hi[q] : lo[q]) >> (8u * (d[q] & 3u));
+    if (s[q] & al & 0xffu) {
+      const uint32_t r = s[q] >> rshift;
+      __hip_atomic_fetch_or(pm + (r >> 5), 1u << (r & 31u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  }
+}
+
+template <int BLOCK>
+__device__ __attribute__((noinline)) long long engine_panel(const BfsArgs& a, lptr<uint32_t> pm) {
+  constexpr int U = kPanelUnroll;
+  constexpr uint32_t NW = BLOCK / 64;
+  constexpr uint32_t STEP = NW * U;
+  const int rb = a.panel_rb;
+  const int npanels = a.npanels;
+  const uint32_t W = 1u << (rb - 5);
+  const uint32_t dmask = (1u << (24 - rb)) - 1u;
+  const int rshift = 32 - rb;
+  PanelPtrs pp;
+  pp.words = to_global(reinterpret_cast<const uint4*>(a.pwords));
+  pp.front8 = to_global(static_cast<const uint2*>(a.front));
+  pp.base = to_global(static_cast<const uint32_t*>(a.pbase));
+  const gptr<const uint32_t> pptr = to_global(static_cast<const uint32_t*>(a.pptr));
+  const gptr<const uint32_t> vis32 = to_global(static_cast<const uint32_t*>(a.vis));
+  const gptr<uint4> mark16 = to_global(reinterpret_cast<uint4*>(a.mark));
+  const uint32_t lane = static_cast<uint32_t>(lane_id());
+  const uint32_t wv = static_cast<uint32_t>(wave_in_block());
+  long long work = 0;
+  for (int p = blockIdx.x; p < npanels; p += gridDim.x) {
+    for (uint32_t j = threadIdx.x; j < W; j += BLOCK) pm[j] = 0u;
+    __syncthreads();
+    const uint32_t c0 = pptr[p], c1 = pptr[p + 1];
+    const uint32_t cl = c1 - 1;  // used only when the panel has a chunk (c < c1)
+    uint32_t c = c0 + wv * U;
+    if (c < c1) {
+      // Software pipeline over batches of U chunks. The bases of a batch are
+      // one vector load (lane u holds chunk c+u's) issued before the previous
+      // batch's slice and window loads, so reading them never waits for the
+      // slices; while batch k is tested, batch k+1's slices and windows and
+      // batch k+2's bases are in flight.
+      uint32_t bv = pp.base[min(c + lane % U, cl)];
+      uint32_t b[U];
+      uint4 w[U];
+      uint2 f[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) b[u] = __builtin_amdgcn_readlane(bv, u);
+      bv = pp.base[min(c + STEP + lane % U, cl)];
+#pragma unroll
+      for (int u = 0; u < U; ++u) panel_load(pp, c + u, cl, lane, b[u], w[u], f[u]);
+      for (;;) {
+        const uint32_t cn = c + STEP;
+        uint32_t bn[U];
+        uint4 wn[U];
+        uint2 fn[U];
+        const bool more = cn < c1;
+        if (more) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) bn[u] = __builtin_amdgcn_readlane(bv, u);
+          bv = pp.base[min(cn + STEP + lane % U, cl)];
+#pragma unroll
+          for (int u = 0; u < U; ++u) panel_load(pp, cn + u, cl, lane, bn[u], wn[u], fn[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (c + u >= c1) break;
+          panel_test4(w[u], b[u] & 7u, f[u], dmask, rshift, pm);
+          work += kPanelChunk;
+        }
+        if (!more) break;
+        c = cn;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          b[u] = bn[u];
+          w[u] = wn[u];
+          f[u] = fn[u];
+        }
+      }
+    }
+    __syncthreads();
+    const size_t wb = static_cast<size_t>(p) * W;
+    for (uint32_t j = threadIdx.x; j < W; j += BLOCK) {
+      const uint32_t m = pm[j];
+      if (!m) continue;
+      const uint32_t x = m & ~vis32[wb + j];
+      if (!x) continue;
+      uint32_t q[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t nib = (x >> (4 * k)) & 0xfu;
+        q[k] = (nib & 1u) | ((nib & 2u) << 7) | ((nib & 4u) << 14) | ((nib & 8u) << 21);
+      }
+      mark16[2 * (wb + j)] = make_uint4(q[0], q[1], q[2], q[3]);
+      mark16[2 * (wb + j) + 1] = make_uint4(q[4], q[5], q[6], q[7]);
+    }
+    __syncthreads();
+  }
+  for (uint32_t j = threadIdx.x; j < W; j += BLOCK) pm[j] = 0xffffffffu;
+  return lane == 0 ? work : 0;
+}
+
 // E1: push over the CSR rows of the frontier vertices.
 template <int SIGMA, bool REC>
-__device__ long long engine_push(const BfsArgs& a, int sel, long long nlight, long long nheavy, long long gtid,
-                                 long long nthreads, long long gwave, long long nwaves, int* hs) {
+__device__ __attribute__((noinline)) long long engine_push(const BfsArgs& a, int sel, long long nlight, long long nheavy, long long gtid,
+                                 long long nthreads, long long gwave, long long nwaves, lptr<int> hs) {
   long long work = 0;
   using M = typename MaskOf<SIGMA>::T;
-  const M* __restrict__ vis = static_cast<const M*>(a.vis);
-  const int32_t* __restrict__ rp = a.rp;
-  const int32_t* __restrict__ col = a.col;
-  uint8_t* __restrict__ mark = a.mark;
+  gptr<const M> __restrict__ vis = to_global(static_cast<const M*>(a.vis));
+  gptr<const int32_t> __restrict__ rp = to_global(a.rp);
+  gptr<const int32_t> __restrict__ col = to_global(a.col);
+  gptr<uint8_t> __restrict__ mark = to_global(a.mark);
   const int lane = lane_id();
-  const unsigned long long* __restrict__ heavy = a.fheavy[sel];
+  gptr<const unsigned long long> __restrict__ heavy = to_global(a.fheavy[sel]);
   for (long long i = gwave; i < nheavy; i += nwaves) {
     const unsigned long long e = heavy[i];
     const int u = static_cast<int>(e >> 32);
@@ -329,7 +488,7 @@ __device__ long long engine_push(const BfsArgs& a, int sel, long long nlight, lo
       }
     }
   }
-  const int32_t* __restrict__ light = a.flight[sel];
+  gptr<const int32_t> __restrict__ light = to_global(a.flight[sel]);
   for (long long i = gtid; i < nlight; i += nthreads) {
     const int u = light[i];
     const int e = rp[u + 1];
@@ -353,15 +512,15 @@ __device__ long long engine_push(const BfsArgs& a, int sel, long long nlight, lo
 constexpr int kPullLight = 32;
 
 template <int SIGMA>
-__device__ long long engine_pull(const BfsArgs& a, long long gtid, long long nthreads) {
+__device__ __attribute__((noinline)) long long engine_pull(const BfsArgs& a, long long gtid, long long nthreads) {
   long long work = 0;
   using M = typename MaskOf<SIGMA>::T;
-  const M* __restrict__ vis = static_cast<const M*>(a.vis);
-  const M* __restrict__ front = static_cast<const M*>(a.front);
-  const M* __restrict__ degm = static_cast<const M*>(a.degmask);
-  const int32_t* __restrict__ rp = a.rp;
-  const int32_t* __restrict__ col = a.col;
-  uint8_t* __restrict__ mark = a.mark;
+  gptr<const M> __restrict__ vis = to_global(static_cast<const M*>(a.vis));
+  gptr<const M> __restrict__ front = to_global(static_cast<const M*>(a.front));
+  gptr<const M> __restrict__ degm = to_global(static_cast<const M*>(a.degmask));
+  gptr<const int32_t> __restrict__ rp = to_global(a.rp);
+  gptr<const int32_t> __restrict__ col = to_global(a.col);
+  gptr<uint8_t> __restrict__ mark = to_global(a.mark);
   const long long nv = a.nsets * SIGMA;
   const int lane = lane_id();
   for (long long ubase = gtid - lane; ubase < nv; ubase += nthreads) {
@@ -419,14 +578,18 @@ __device__ long long engine_pull(const BfsArgs& a, long long gtid, long long nth
 // Runs one engine and adds the adjacency entries it read to the level's
 // F_WORK counter (one atomic per block).
 // hs != nullptr: single-workgroup level, marked slice sets are recorded in hs
-// (only the BVSS and push engines run there).
+// (only the BVSS and push engines run there). pm: LDS scratch for the
+// panel-blocked BVSS step (nullptr: that step is not available).
 template <int SIGMA, class SliceT, int BLOCK>
 __device__ __forceinline__ void run_engine(const BfsArgs& a, int engine, int sel, int slot, const LevelView& v,
                                            long long gtid, long long nthreads, long long gwave, long long nwaves,
-                                           int* hs = nullptr) {
+                                           lptr<int> hs, lptr<uint32_t> pm) {
   __shared__ long long lds_work[BLOCK / 64];
   long long work[1];
-  if (engine == BLEST_ENGINE_BVSS)
+  constexpr bool kPanelFmt = SIGMA == 8 && sizeof(SliceT) == 4;
+  if (kPanelFmt && engine == BLEST_ENGINE_BVSS && !hs && pm && use_panel(a, v))
+    work[0] = engine_panel<BLOCK>(a, pm);
+  else if (engine == BLEST_ENGINE_BVSS)
     work[0] = hs ? engine_bvss<SIGMA, SliceT, true>(a, a.queue[sel], v.queue, gwave, nwaves, hs)
                  : engine_bvss<SIGMA, SliceT, false>(a, a.queue[sel], v.queue, gwave, nwaves, nullptr);
   else if (engine == BLEST_ENGINE_PUSH)
@@ -447,8 +610,8 @@ __device__ __forceinline__ void run_engine(const BfsArgs& a, int engine, int sel
 // tail repeats m), and s*SIGMA*4 is a multiple of 16, so the loads are aligned
 // and in bounds.
 template <int SIGMA>
-__device__ __forceinline__ void load_set_rp(const int32_t* __restrict__ rp, long long s, int (&r)[SIGMA + 1]) {
-  const int4* p = reinterpret_cast<const int4*>(rp + s * SIGMA);
+__device__ __forceinline__ void load_set_rp(gptr<const int32_t> rp, long long s, int (&r)[SIGMA + 1]) {
+  const gptr<const int4> p = (gptr<const int4>)(rp + s * SIGMA);
 #pragma unroll
   for (int i = 0; i < SIGMA / 4; ++i) {
     const int4 q = p[i];
@@ -471,22 +634,24 @@ __device__ __forceinline__ void load_set_rp(const int32_t* __restrict__ rp, long
 // owns its output index by a binary search over the wave's prefix sums, so a
 // hub set with thousands of VSSs costs a few wave steps, not a serial loop.
 template <int SIGMA, int BLOCK, bool LOCAL, class SetAt>
-__device__ void finalize_windows(const BfsArgs& a, int new_level, unsigned long long* acc, int sel_out,
+__device__ void finalize_windows(const BfsArgs& a, int new_level, gptr<unsigned long long> acc, int sel_out,
                                  long long win0, long long nwin, long long wstep, SetAt set_at, long long (&st)[5],
                                  unsigned long long* local) {
   using M = typename MaskOf<SIGMA>::T;
   constexpr int SPT = 2;
   __shared__ int lds32[3 * (BLOCK / 64)];
   __shared__ unsigned long long bases[3];
-  M* __restrict__ vis = static_cast<M*>(a.vis);
-  M* __restrict__ front = static_cast<M*>(a.front);
-  uint8_t* __restrict__ mark = a.mark;
-  const int32_t* __restrict__ rp = a.rp;
-  const uint32_t* __restrict__ sp = a.slice_ptr;
+  gptr<M> __restrict__ vis = to_global(static_cast<M*>(a.vis));
+  gptr<M> __restrict__ front = to_global(static_cast<M*>(a.front));
+  gptr<uint8_t> __restrict__ mark = to_global(a.mark);
+  gptr<const int32_t> __restrict__ rp = to_global(a.rp);
+  gptr<const uint32_t> __restrict__ sp = to_global(a.slice_ptr);
   const uint32_t tau = static_cast<uint32_t>(a.tau);
-  int32_t* __restrict__ light = a.flight[sel_out];
-  unsigned long long* __restrict__ heavy = a.fheavy[sel_out];
-  uint4* __restrict__ queue = a.queue[sel_out];
+  gptr<int32_t> __restrict__ light = to_global(a.flight[sel_out]);
+  gptr<unsigned long long> __restrict__ heavy = to_global(a.fheavy[sel_out]);
+  gptr<uint4> __restrict__ queue = to_global(a.queue[sel_out]);
+  gptr<int32_t> __restrict__ levels = to_global(a.levels);
+  const gptr<const int32_t> __restrict__ orig_id = to_global(a.orig_id);
   const int lane = lane_id();
   for (long long win = win0; win < nwin; win += wstep) {
     M nw[SPT];
@@ -523,7 +688,7 @@ __device__ void finalize_windows(const BfsArgs& a, int new_level, unsigned long 
                 nh[k] += (d + kHeavyChunk - 1) / kHeavyChunk;
               else
                 nl[k] += 1;
-              a.levels[a.orig_id ? a.orig_id[u] : u] = new_level;
+              levels[orig_id ? orig_id[u] : u] = new_level;
             }
             const uint32_t ns = sp[s + 1] - sp[s];
             nq[k] = static_cast<int>((ns + tau - 1) / tau);
@@ -629,7 +794,7 @@ __device__ void finalize_windows(const BfsArgs& a, int new_level, unsigned long 
 // Adds a block's Stage 2 statistics to the level slot (block 0 also carries
 // the cumulative counts of the previous level).
 template <int BLOCK>
-__device__ void finalize_stats(unsigned long long* acc, long long (&st)[5], long long cumv_in, long long cume_in) {
+__device__ void finalize_stats(gptr<unsigned long long> acc, long long (&st)[5], long long cumv_in, long long cume_in) {
   __shared__ long long lds64[5 * (BLOCK / 64)];
   block_sum64<BLOCK, 5>(st, lds64);
   if (threadIdx.x == 0) {
@@ -656,7 +821,7 @@ template <int SIGMA, int BLOCK>
 __device__ void finalize(const BfsArgs& a, int new_level, int slot_out, int sel_out, long long cumv_in,
                          long long cume_in, unsigned nblocks) {
   constexpr long long WIN = static_cast<long long>(BLOCK) * 2;
-  unsigned long long* acc = &a.ctl->acc[slot_out][0][0];
+  const gptr<unsigned long long> acc = to_global(&a.ctl->acc[slot_out][0][0]);
   long long st[5] = {0, 0, 0, 0, 0};  // frontier, queued slices, frontier edges, deg>=32, deg>=1024
   const long long nsets = a.nsets;
   const long long tid = threadIdx.x;
@@ -680,7 +845,7 @@ __device__ void finalize(const BfsArgs& a, int new_level, int slot_out, int sel_
 
 __device__ __forceinline__ bool single_eligible(const BfsArgs& a, int engine, const LevelView& v) {
   if (!a.single_block || a.probe) return false;
-  if (engine == BLEST_ENGINE_BVSS) return v.qslices <= kSingleMaxMarks;
+  if (engine == BLEST_ENGINE_BVSS) return v.qslices <= kSingleMaxMarks && !(a.npanels > 0 && a.panel_mode == 2);
   if (engine == BLEST_ENGINE_PUSH) return v.fedges <= kSingleMaxMarks;
   return false;
 }
@@ -690,15 +855,15 @@ __device__ __forceinline__ bool single_eligible(const BfsArgs& a, int engine, co
 // the level's counters are stored at the end (the slot was zeroed before).
 template <int SIGMA, int BLOCK>
 __device__ void finalize_list(const BfsArgs& a, int new_level, int slot_out, int sel_out, long long cumv_in,
-                              long long cume_in, int* hs) {
+                              long long cume_in, lptr<int> hs) {
   constexpr int WIN = BLOCK * 2;
   __shared__ unsigned long long local[3];
   __shared__ long long lds64[5 * (BLOCK / 64)];
-  unsigned long long* acc = &a.ctl->acc[slot_out][0][0];
+  const gptr<unsigned long long> acc = to_global(&a.ctl->acc[slot_out][0][0]);
   if (threadIdx.x < 3) local[threadIdx.x] = 0ULL;
   __syncthreads();
   const int count = hs[kSingleHash];
-  const int* list = hs + kSingleHash + 1;
+  const lptr<const int> list = hs + kSingleHash + 1;
   long long st[5] = {0, 0, 0, 0, 0};
   const int tid = threadIdx.x;
   finalize_windows<SIGMA, BLOCK, true>(a, new_level, acc, sel_out, 0, (count + WIN - 1) / WIN, 1,
@@ -793,6 +958,7 @@ __device__ __forceinline__ void log_level(const BfsArgs& a, int level, const Lev
   r.deg1024 = v.deg1024;
   r.engine = engine;
   r.fallback = fallback;
+  r.panel = engine == BLEST_ENGINE_BVSS && use_panel(a, v);
   r.t_begin = dev_ticks();
   r.t_mid = 0;
   r.t_end = 0;
@@ -816,7 +982,7 @@ __device__ __forceinline__ void block_sync_mem() {
 // run (its slot holds that level's statistics).
 template <int SIGMA, class SliceT, int BLOCK>
 __device__ int single_episode(const BfsArgs& a, int level, int engine, int fallback, float (&feat)[kMaxSwitchFeatures],
-                              LevelView v, const float* s_mlp, int* hs) {
+                              LevelView v, const float* s_mlp, lptr<int> hs) {
   const long long gtid = threadIdx.x, nthreads = BLOCK;
   const long long gwave = wave_in_block(), nwaves = BLOCK / 64;
   for (;;) {
@@ -825,7 +991,7 @@ __device__ int single_episode(const BfsArgs& a, int level, int engine, int fallb
     if (threadIdx.x < kStatFields)
       __hip_atomic_store(&a.ctl->acc[nslot][threadIdx.x][0], 0ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     block_sync_mem();
-    run_engine<SIGMA, SliceT, BLOCK>(a, engine, level & 1, slot, v, gtid, nthreads, gwave, nwaves, hs);
+    run_engine<SIGMA, SliceT, BLOCK>(a, engine, level & 1, slot, v, gtid, nthreads, gwave, nwaves, hs, nullptr);
     block_sync_mem();
     if (threadIdx.x == 0 && level < a.log_cap) a.log[level].t_mid = dev_ticks();
     finalize_list<SIGMA, BLOCK>(a, level + 1, nslot, (level & 1) ^ 1, v.cumv, v.cume, hs);
@@ -879,7 +1045,7 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
       ++episodes;
       if (blockIdx.x == 0) {
         const int next = single_episode<SIGMA, SliceT, BLOCK>(a, level, engine, fallback, feat, v,
-                                                              learned ? s_mlp : nullptr, hs);
+                                                              learned ? s_mlp : nullptr, to_lds(hs));
         block_sync_mem();
         if (threadIdx.x == 0) {
           __hip_atomic_store(&a.ctl->single_level[0], next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -924,12 +1090,14 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
     if (a.probe) {
       for (int e = 0; e < 3; ++e) {
         const unsigned long long t0 = dev_ticks();
-        run_engine<SIGMA, SliceT, BLOCK>(a, e, sel, slot, v, gtid, nthreads, gwave, nwaves);
+        run_engine<SIGMA, SliceT, BLOCK>(a, e, sel, slot, v, gtid, nthreads, gwave, nwaves, nullptr,
+                                         to_lds(reinterpret_cast<uint32_t*>(hs)));
         if (!grid_barrier(a.ctl, bc)) return;
         if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_engine[e] = dev_ticks() - t0;
       }
     } else {
-      run_engine<SIGMA, SliceT, BLOCK>(a, engine, sel, slot, v, gtid, nthreads, gwave, nwaves);
+      run_engine<SIGMA, SliceT, BLOCK>(a, engine, sel, slot, v, gtid, nthreads, gwave, nwaves, nullptr,
+                                       to_lds(reinterpret_cast<uint32_t*>(hs)));
       if (!grid_barrier(a.ctl, bc)) return;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_mid = dev_ticks();
@@ -996,7 +1164,9 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_stage1(BfsArgs a, int level, long
     const int nslot = (level + 1) % kStatSlots;
     for (int t = threadIdx.x; t < kStatFields; t += BLOCK) a.ctl->acc[nslot][t][0] = 0ULL;
   }
-  run_engine<SIGMA, SliceT, BLOCK>(a, engine, level & 1, level % kStatSlots, v, gtid, nthreads, gwave, nwaves);
+  __shared__ uint32_t pm[kPanelMaxWords];
+  run_engine<SIGMA, SliceT, BLOCK>(a, engine, level & 1, level % kStatSlots, v, gtid, nthreads, gwave, nwaves, nullptr,
+                                   to_lds(pm));
 }
 
 template <int SIGMA, int BLOCK>
@@ -1106,6 +1276,13 @@ BfsArgs bfs_args(const DevGraph& g) {
   a.prefilter = g.prefilter;
   a.count_work = g.count_work;
   a.single_block = g.single_block;
+  a.pwords = g.pwords;
+  a.pbase = g.pbase;
+  a.pptr = g.pptr;
+  a.npanels = static_cast<int32_t>(g.npanels);
+  a.panel_rb = g.panel_rb;
+  a.panel_mode = g.panel_mode;
+  a.panel_slots = g.nchunks * 64;
   a.timeout_ticks = 1000000000ULL;  // 10 s at the 100 MHz device clock
   return a;
 }

@@ -74,6 +74,7 @@ struct LevelRec {
   unsigned long long t_engine[3]; // probe mode: ticks of each engine
   int engine;
   int fallback;
+  int panel;                      // BVSS step ran on the panel-blocked copy
   float feat[kMaxSwitchFeatures];
 };
 
@@ -115,6 +116,14 @@ struct BfsArgs {
   int32_t prefilter;
   int32_t count_work;  // accumulate F_WORK (adjacency entries read per level)
   int32_t single_block;  // run small levels on workgroup 0 alone
+  // panel-blocked BVSS copy (sigma = 8, 32-bit slices); npanels = 0 if absent
+  const uint32_t* pwords;  // nchunks * 64 slice words
+  const uint32_t* pbase;   // first set of each chunk
+  const uint32_t* pptr;    // npanels + 1 chunk offsets
+  int32_t npanels;
+  int32_t panel_rb;        // log2 rows per panel
+  int32_t panel_mode;      // 1: dense levels only, 2: every BVSS level
+  long long panel_slots;   // nchunks * 64
   unsigned long long timeout_ticks;
 };
 
@@ -141,6 +150,12 @@ struct DevGraph {
   MlpDev* mlp = nullptr;
   int* host_flags = nullptr;  // pinned: done flag readback of the per-stage mode
   int block = 512, grid = 0, num_cu = 0, persistent = 1, prefilter = 1, count_work = 0, single_block = 1;
+  uint32_t* pwords = nullptr;
+  uint32_t* pbase = nullptr;
+  uint32_t* pptr = nullptr;
+  int64_t npanels = 0, nchunks = 0;
+  int panel_rb = 0, panel_mode = 0;
+  size_t mark_bytes = 0;
   double tick_us = 0.01;      // device clock period in microseconds
 };
 

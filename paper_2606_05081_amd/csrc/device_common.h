@@ -41,6 +41,39 @@ __device__ __forceinline__ unsigned long long dev_ticks() { return __builtin_amd
 
 __device__ __forceinline__ int lane_id() { return static_cast<int>(threadIdx.x & 63u); }
 
+// Pointers to device (global) memory. Pointers read from an argument struct
+// that lives on the stack reach a callee with no address space, and accesses
+// through them become flat instructions, which also count against the
+// LDS/scalar wait counter (so an LDS wait also waits for every load in
+// flight). Hot loops access device memory through gptr<T>, which makes the
+// compiler emit global loads, stores and atomics.
+// (The host pass of the single-source compile only parses device code; there
+// the qualifiers are dropped, since x86 has no generic address space that
+// contains them.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+using lptr = __attribute__((address_space(3))) T*;
+#else
+template <class T>
+using gptr = T*;
+template <class T>
+using lptr = T*;
+#endif
+template <class T>
+__device__ __forceinline__ gptr<T> to_global(T* p) {
+  return (gptr<T>)p;
+}
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
+// Same for LDS: pointers into a __shared__ array handed to a function that is
+// not inlined stay ds_* accesses.
+template <class T>
+__device__ __forceinline__ lptr<T> to_lds(T* p) {
+  return (lptr<T>)p;
+}
+
 // Wave index inside the block, known uniform to the compiler.
 __device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6)); }
 
@@ -111,16 +144,20 @@ __device__ __forceinline__ void block_sum64(long long (&v)[N], long long* lds) {
   __syncthreads();
 }
 
-__device__ __forceinline__ unsigned long long ld_acquire_u64(const unsigned long long* p) {
+template <class P>
+__device__ __forceinline__ unsigned long long ld_acquire_u64(P p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ unsigned long long ld_relaxed_u64(const unsigned long long* p) {
+template <class P>
+__device__ __forceinline__ unsigned long long ld_relaxed_u64(P p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void add_u64(unsigned long long* p, unsigned long long v) {
+template <class P>
+__device__ __forceinline__ void add_u64(P p, unsigned long long v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ unsigned long long fetch_add_u64(unsigned long long* p, unsigned long long v) {
+template <class P>
+__device__ __forceinline__ unsigned long long fetch_add_u64(P p, unsigned long long v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -154,8 +191,9 @@ struct BarrierCtx {
   unsigned long long timeout;
 };
 
-__device__ __forceinline__ bool spin_until_changed(const unsigned* flag, unsigned old, Ctl* ctl,
+__device__ __forceinline__ bool spin_until_changed(gptr<const unsigned> flag, unsigned old, gptr<Ctl> ctl,
                                                    unsigned long long t0, unsigned long long timeout) {
+
   while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == old) {
     if (__hip_atomic_load(&ctl->error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
     if (dev_ticks() - t0 > timeout) {
@@ -168,8 +206,9 @@ __device__ __forceinline__ bool spin_until_changed(const unsigned* flag, unsigne
   return true;
 }
 
-__device__ __forceinline__ bool grid_barrier(Ctl* ctl, const BarrierCtx& bc) {
+__device__ __forceinline__ bool grid_barrier(Ctl* ctl_in, const BarrierCtx& bc) {
   __shared__ int ok_flag;
+  const gptr<Ctl> ctl = to_global(ctl_in);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -205,7 +244,8 @@ __device__ __forceinline__ bool grid_barrier(Ctl* ctl, const BarrierCtx& bc) {
 // step of a persistent kernel; it uses a flat barrier on bar_count/bar_gen
 // (one release RMW per block) because the per-XCD counts are not known yet.
 // The host zeroes xcd_blocks/xcd_active before every launch.
-__device__ __forceinline__ bool barrier_register(Ctl* ctl, BarrierCtx* bc, unsigned long long timeout) {
+__device__ __forceinline__ bool barrier_register(Ctl* ctl_in, BarrierCtx* bc, unsigned long long timeout) {
+  const gptr<Ctl> ctl = to_global(ctl_in);
   __shared__ unsigned s_xcc, s_nlocal, s_nxcd;
   __shared__ int ok_flag;
   __syncthreads();
@@ -246,28 +286,28 @@ __device__ __forceinline__ uint32_t gather8(unsigned long long x) {
 }
 
 template <int SIGMA>
-__device__ __forceinline__ typename MaskOf<SIGMA>::T load_marks(const uint8_t* p) {
+__device__ __forceinline__ typename MaskOf<SIGMA>::T load_marks(gptr<const uint8_t> p) {
   if constexpr (SIGMA == 8) {
-    return static_cast<uint8_t>(gather8(*reinterpret_cast<const unsigned long long*>(p)));
+    return static_cast<uint8_t>(gather8(*(gptr<const unsigned long long>)p));
   } else if constexpr (SIGMA == 16) {
-    ulonglong2 x = *reinterpret_cast<const ulonglong2*>(p);
+    const u64x2 x = *(gptr<const u64x2>)p;
     return static_cast<uint16_t>(gather8(x.x) | (gather8(x.y) << 8));
   } else {
-    ulonglong2 x = *reinterpret_cast<const ulonglong2*>(p);
-    ulonglong2 y = *reinterpret_cast<const ulonglong2*>(p + 16);
+    const u64x2 x = *(gptr<const u64x2>)p;
+    const u64x2 y = *(gptr<const u64x2>)(p + 16);
     return gather8(x.x) | (gather8(x.y) << 8) | (gather8(y.x) << 16) | (gather8(y.y) << 24);
   }
 }
 
 template <int SIGMA>
-__device__ __forceinline__ void clear_marks(uint8_t* p) {
+__device__ __forceinline__ void clear_marks(gptr<uint8_t> p) {
   if constexpr (SIGMA == 8) {
-    *reinterpret_cast<unsigned long long*>(p) = 0ULL;
+    *(gptr<unsigned long long>)p = 0ULL;
   } else if constexpr (SIGMA == 16) {
-    *reinterpret_cast<ulonglong2*>(p) = make_ulonglong2(0ULL, 0ULL);
+    *(gptr<u64x2>)p = u64x2{0ULL, 0ULL};
   } else {
-    *reinterpret_cast<ulonglong2*>(p) = make_ulonglong2(0ULL, 0ULL);
-    *reinterpret_cast<ulonglong2*>(p + 16) = make_ulonglong2(0ULL, 0ULL);
+    *(gptr<u64x2>)p = u64x2{0ULL, 0ULL};
+    *(gptr<u64x2>)(p + 16) = u64x2{0ULL, 0ULL};
   }
 }
 

@@ -291,4 +291,102 @@ bool build_bvss(int64_t n, const int32_t* rp, const int32_t* col, int sigma, int
   return true;
 }
 
+int panel_log2_rows(int64_t n, int64_t workgroups) {
+  const int64_t rows = (n + std::max<int64_t>(workgroups, 1) - 1) / std::max<int64_t>(workgroups, 1);
+  int lg = 0;
+  while ((int64_t(1) << lg) < rows) ++lg;
+  return std::max(5, std::min(16, lg));
+}
+
+bool build_panels(int64_t n, const Bvss& b, int rb, Panels* out) {
+  if (b.wide || b.nslices == 0 || n > (int64_t(1) << 24) || rb < 5 || rb > 16) return false;
+  const int rshift = 32 - rb;
+  const uint32_t dlim = std::min<uint32_t>(1u << (24 - rb), 505u);
+  const int64_t np = (n + (int64_t(1) << rb) - 1) >> rb;
+  const int64_t ns = b.nsets;
+  // Counting sort of (set, slice) pairs by panel, stable in set order: each
+  // thread owns a contiguous range of sets and writes behind the counts of
+  // the threads before it in every panel.
+  const int t = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(host_threads(), ns / 1024 + 1)));
+  const int64_t span = (ns + t - 1) / t;
+  std::vector<int64_t> hist(static_cast<size_t>(t) * np, 0);
+  auto run = [&](auto&& body) {
+    std::vector<std::thread> pool;
+    for (int i = 0; i < t; ++i) pool.emplace_back([&, i] { body(i); });
+    for (auto& th : pool) th.join();
+  };
+  run([&](int i) {
+    int64_t* h = &hist[static_cast<size_t>(i) * np];
+    const int64_t s0 = std::min(ns, i * span), s1 = std::min(ns, s0 + span);
+    for (uint32_t k = b.slice_ptr[s0]; k < b.slice_ptr[s1]; ++k) ++h[(b.slices32[k] >> 8) >> rb];
+  });
+  std::vector<int64_t> start(np + 1, 0);
+  {
+    int64_t acc = 0;
+    for (int64_t p = 0; p < np; ++p) {
+      start[p] = acc;
+      for (int i = 0; i < t; ++i) {
+        const int64_t c = hist[static_cast<size_t>(i) * np + p];
+        hist[static_cast<size_t>(i) * np + p] = acc;
+        acc += c;
+      }
+    }
+    start[np] = acc;
+  }
+  std::vector<uint32_t> tset(static_cast<size_t>(b.nslices)), tword(static_cast<size_t>(b.nslices));
+  run([&](int i) {
+    int64_t* h = &hist[static_cast<size_t>(i) * np];
+    const int64_t s0 = std::min(ns, i * span), s1 = std::min(ns, s0 + span);
+    for (int64_t s = s0; s < s1; ++s)
+      for (uint32_t k = b.slice_ptr[s]; k < b.slice_ptr[s + 1]; ++k) {
+        const uint32_t w = b.slices32[k];
+        const uint32_t row = w >> 8;
+        const int64_t o = h[row >> rb]++;
+        tset[o] = static_cast<uint32_t>(s);
+        tword[o] = ((row & ((1u << rb) - 1u)) << rshift) | (w & 0xffu);
+      }
+  });
+  // Chunking per panel: kPanelChunk slices, or fewer where the next slice's
+  // set is dlim or more past the chunk's first set.
+  auto chunk_panel = [&](int64_t p, auto&& emit) {
+    int64_t i = start[p];
+    const int64_t e = start[p + 1];
+    int64_t c = 0;
+    while (i < e) {
+      const uint32_t base = tset[i];
+      const uint32_t lim = std::min<uint32_t>(dlim, 512u - (base & 7u));
+      int k = 0;
+      while (i < e && k < kPanelChunk && tset[i] - base < lim) {
+        emit(c, k, base, tword[i] | ((tset[i] - base) << 8));
+        ++i;
+        ++k;
+      }
+      ++c;
+    }
+    return c;
+  };
+  std::vector<int64_t> cnt(np, 0);
+  parallel_for(np, [&](int64_t p0, int64_t p1) {
+    for (int64_t p = p0; p < p1; ++p) cnt[p] = chunk_panel(p, [](int64_t, int, uint32_t, uint32_t) {});
+  });
+  out->rb = rb;
+  out->npanels = np;
+  out->ptr.assign(np + 1, 0);
+  for (int64_t p = 0; p < np; ++p) out->ptr[p + 1] = out->ptr[p] + static_cast<uint32_t>(cnt[p]);
+  out->nchunks = out->ptr[np];
+  out->words.assign(static_cast<size_t>(out->nchunks) * kPanelChunk, 0u);
+  out->base.assign(static_cast<size_t>(out->nchunks), 0u);
+  parallel_for(np, [&](int64_t p0, int64_t p1) {
+    for (int64_t p = p0; p < p1; ++p) {
+      const int64_t c0 = out->ptr[p];
+      chunk_panel(p, [&](int64_t c, int k, uint32_t base, uint32_t word) {
+        out->base[c0 + c] = base;
+        out->words[(c0 + c) * kPanelChunk + k] = word;
+      });
+    }
+  });
+  return true;
+}
+
 }  // namespace blest
+

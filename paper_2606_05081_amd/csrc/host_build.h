@@ -32,4 +32,30 @@ void permute_csr(int64_t n, const int32_t* rp, const int32_t* col, const std::ve
 
 bool build_bvss(int64_t n, const int32_t* rp, const int32_t* col, int sigma, int tau, bool wide, Bvss* out);
 
+// Panel-blocked copy of a sigma = 8, 32-bit BVSS for dense top-down levels.
+// Rows are cut into panels of 2^rb consecutive rows; a panel's slices are
+// listed set by set (ascending set, then row) in chunks of kPanelChunk. A
+// chunk records the set of its first slice (base); each slice word is
+//   (row - panel start) << (32 - rb) | (set - base) << 8 | mask.
+// A chunk is closed early (and padded with zero words, which never hit) so
+// that set - base stays below 2^(24 - rb) and (base mod 8) + (set - base)
+// stays below 512: the frontier words of a chunk's sets then lie in one
+// 512-byte window that a wave loads with one 8-byte load per lane.
+constexpr int kPanelChunk = 256;
+struct Panels {
+  int rb = 0;                     // log2 rows per panel (0: no panel copy)
+  int64_t npanels = 0, nchunks = 0;
+  std::vector<uint32_t> words;    // nchunks * kPanelChunk
+  std::vector<uint32_t> base;     // nchunks
+  std::vector<uint32_t> ptr;      // npanels + 1: chunk range of each panel
+};
+
+// log2 of the panel height for an n-vertex graph traversed by `workgroups`
+// persistent workgroups: about one panel per workgroup, within [5, 16].
+int panel_log2_rows(int64_t n, int64_t workgroups);
+
+// rb = log2 rows per panel, in [5, 16]. Returns false (and builds nothing)
+// for 64-bit slices, an empty BVSS or n > 2^24.
+bool build_panels(int64_t n, const Bvss& b, int rb, Panels* out);
+
 }  // namespace blest

@@ -73,6 +73,8 @@ def test_rmat_s16_all_policies(blest):
     dict(block_size=256), dict(block_size=1024), dict(persistent=0), dict(prefilter=0), dict(reorder=1),
     dict(reorder=0), dict(blocks_per_cu=1), dict(sigma=16, tau=64, block_size=256, persistent=0),
     dict(single_block=0), dict(single_block=0, block_size=512), dict(block_size=256, sigma=32),
+    dict(panel=0), dict(panel=2), dict(panel=2, block_size=256), dict(panel=2, persistent=0),
+    dict(panel=2, blocks_per_cu=1, single_block=0),
 ])
 def test_option_matrix(blest, opt):
     for rp, col in [inputs.rmat_graph(13, 77), inputs.grid_graph(70, 78)]:
@@ -80,6 +82,41 @@ def test_option_matrix(blest, opt):
         for s in inputs.sources(rp, 2, seed=79):
             run_all_policies(blest, g, int(s), oracle.bfs(rp, col, int(s)), seeds=(4,))
         g.close()
+
+
+@pytest.mark.parametrize("name", ["path", "star", "hypercube", "grid40perm", "gnp", "rmat12", "tiny"])
+def test_panel_copy_every_bvss_level(blest, name):
+    """panel=2: every BVSS level reads the panel-blocked copy (LDS marks,
+    stale frontier words filtered at the flush); levels must not change."""
+    if name == "path":
+        rp, col = H.path(1000)
+    elif name == "star":
+        rp, col = H.star(3000)
+    elif name == "hypercube":
+        rp, col = H.hypercube(12)
+    elif name == "grid40perm":
+        rp0, col0 = inputs.grid(40, 0.0, seed=1, permute=False)
+        rp, col, _ = inputs.permute(rp0, col0, seed=3)
+    elif name == "gnp":
+        rp, col = H.gnp(300, 0.02, 5)
+    elif name == "rmat12":
+        rp, col = inputs.rmat_graph(12, 88)
+    else:
+        rp, col = inputs.from_pairs(13, [0, 1, 2, 5, 6], [1, 2, 3, 6, 7])
+    g = blest.Graph(rp, col, panel=2)
+    assert g.info()["panel_log2_rows"] >= 5
+    n = rp.size - 1
+    for src in sorted({0, n // 3, n - 1}):
+        ref = oracle.bfs(rp, col, src)
+        for pol in ("BVSS", "HEURISTIC", "RANDOM"):
+            g.set_policy(getattr(blest.Policy, pol), 10.0, 9)
+            lev = g.bfs(src).cpu().numpy()
+            assert np.array_equal(lev, ref), (name, pol, src)
+        g.set_policy(blest.Policy.BVSS, 10.0)
+        g.bfs(src)
+        st = g.level_stats()
+        assert all(r["bvss_panel"] == 1 for r in st[:-1]), (name, src)
+    g.close()
 
 
 def test_edge_cases(blest):
@@ -222,4 +259,7 @@ def test_full_size_sampled_sources(blest, which):
             assert oracle.certificate(rp, col, s, lev) == (0, -1), pol
             if i == 0:
                 assert np.array_equal(lev, oracle.bfs(rp, col, s)), pol
+            if which == "rmat22" and pol == "BVSS":
+                # the dense levels of the plain method read the panel-blocked copy
+                assert any(r["bvss_panel"] for r in g.level_stats()[:-1])
     g.close()
