@@ -47,18 +47,22 @@ def traversal_edges(rp, levels):
 
 
 def algorithmic_bytes(stats, n, nsets, sigma, slice_bytes, deg, levels):
-    """Bytes a traversal must move, from its per-level log:
-    init 4n + 2n/8; per step the engine's reads (BVSS: slice words + 16 B per
-    queued VSS; push: 4 B per edge + 12 B per frontier vertex; bottom-up: 4 B
-    per scanned edge + 8 B per unvisited vertex of nonzero degree) and the
-    finalisation (n_hat mark bytes + 12 B per new vertex + 16 B per enqueued
-    VSS + n/4 visited/frontier words)."""
+    """Bytes a traversal must move, from its per-level log: init 4n + 2n/8;
+    per step the engine's reads (BVSS over the queue: slice words + 16 B per
+    queued VSS; BVSS over the panel copy: 4 B per slice slot + 4 B per
+    256-slot chunk + the n/8 visited bytes read at the flush; push: 4 B per
+    edge + 12 B per frontier vertex; bottom-up: 4 B per scanned edge + 8 B per
+    unvisited vertex of nonzero degree) and the finalisation (n_hat mark bytes
+    + 12 B per new vertex + 16 B per enqueued VSS + n/4 visited/frontier
+    words)."""
     total = 4 * n + 2 * n // 8
     nhat = nsets * sigma
     lev = np.where(levels < 0, np.iinfo(np.int32).max, levels)
     for i, r in enumerate(stats[:-1]):
         eng = r["engine"]
-        if eng == 0:
+        if eng == 0 and r.get("bvss_panel"):
+            total += 4 * r["work"] + 4 * (r["work"] // 256) + n // 8
+        elif eng == 0:
             total += slice_bytes * r["work"] + 16 * r["queue"]
         elif eng == 1:
             total += 4 * r["work"] + 12 * r["frontier"]

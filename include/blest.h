@@ -98,7 +98,7 @@ typedef struct {
                            workgroup with workgroup barriers instead of device-wide ones */
   int32_t panel;        /* panel-blocked BVSS copy for dense top-down levels (sigma = 8, 32-bit
                            slices only): 0 = not built, 1 (default) = used when the queued slices
-                           are at least a quarter of all slices, 2 = used at every BVSS level */
+                           are at least an eighth of all slices, 2 = used at every BVSS level */
   int32_t panel_log2_rows; /* rows per panel = 2^this, in [5, 16]; 0 (default) = about one panel
                               per persistent workgroup */
   int32_t reserved[4];

@@ -324,7 +324,7 @@ __device__ long long engine_bvss(const BfsArgs& a, const uint4* __restrict__ q, 
 constexpr int kPanelChunk = 256;      // slices per chunk (host layout)
 constexpr int kPanelUnroll = 4;       // chunks per wave per batch
 constexpr int kPanelMaxWords = 2048;  // rb <= 16
-constexpr long long kPanelDenom = 4;  // dense: queued slices >= panel slots / 4
+constexpr long long kPanelDenom = 8;  // dense: queued slices >= panel slots / 8
 
 __device__ __forceinline__ bool use_panel(const BfsArgs& a, const LevelView& v) {
   if (a.npanels <= 0) return false;
