@@ -9,7 +9,9 @@ built and resident in HBM before timing starts.
 value = harmonic-mean GTEPS over the sources, where a traversal's edge count
 is half the degree sum of the vertices it reaches (undirected edges of the
 source's component). The switch policy is the learned network when a trained
-model is installed (paper_2606_05081_amd/switch_model.json), else Eq. 3.
+model is installed (paper_2606_05081_amd/switch_model.json) and three trial
+traversals on other sources show it faster than Eq. 3 on this graph (the
+paper's per-graph enable); otherwise Eq. 3. Both are measured and reported.
 
 Also measured in the same run and printed in the JSON line: the plain
 method (BVSS top-down at every level) on the same sources with its roofline,
@@ -229,12 +231,18 @@ def main():
 
     heur_gteps, heur_step_ms, heur_t = run_policy(blest.Policy.HEURISTIC, args.steps, args.warmup)
     print(f"# heuristic: {heur_gteps:.1f} GTEPS, mean {np.mean(heur_t):.3f} ms/source", file=sys.stderr, flush=True)
-    learned_gteps = None
+    learned_gteps, enabled, trial_ms = None, None, None
     value, step_ms = heur_gteps, heur_step_ms
     if model is not None:
         learned_gteps, learned_step_ms, _ = run_policy(blest.Policy.LEARNED, args.steps, args.warmup)
         print(f"# learned: {learned_gteps:.1f} GTEPS", file=sys.stderr, flush=True)
-        value, step_ms, policy = learned_gteps, learned_step_ms, "learned"
+        # per-graph enable by three trial traversals on sources outside the timed set
+        from paper_2606_05081_amd import switch
+        enabled, trial_ms = switch.per_graph_enable(g, inputs.sources(rp, 3, seed=1022))
+        if enabled:
+            value, step_ms, policy = learned_gteps, learned_step_ms, "learned"
+        else:
+            policy = "heuristic (learned switch disabled for this graph by its trial traversals)"
 
     # plain method (BVSS top-down every level): roofline of the persistent kernel
     td_gteps, _, td_t = run_policy(blest.Policy.BVSS, 1, 1)
@@ -268,7 +276,9 @@ def main():
 
     extras = {"heuristic_gteps": round(heur_gteps, 3), "learned_gteps": None if learned_gteps is None else
               round(learned_gteps, 3), "learned_over_heuristic": None if learned_gteps is None else
-              round(learned_gteps / heur_gteps, 4), "plain_method_gteps": round(td_gteps, 3),
+              round(learned_gteps / heur_gteps, 4), "learned_enabled_by_trials": enabled,
+              "trial_ms_per_source": None if trial_ms is None else {k: round(v, 4) for k, v in trial_ms.items()},
+              "plain_method_gteps": round(td_gteps, 3),
               "ms_per_source": round(float(np.mean(heur_t)), 4), "switched_achieved_GBs": round(sw_ach, 1)}
     g.close()
 

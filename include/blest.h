@@ -101,7 +101,13 @@ typedef struct {
                            are at least an eighth of all slices, 2 = used at every BVSS level */
   int32_t panel_log2_rows; /* rows per panel = 2^this, in [5, 16]; 0 (default) = about one panel
                               per persistent workgroup */
-  int32_t reserved[4];
+  int32_t stage2_count_first; /* Stage 2 of a grid level either builds the frontier lists in the same
+                                 pass as the visited update, or counts first and writes the lists
+                                 only if the next level's engine reads them (one more device-wide
+                                 barrier then). 0: same pass always; 1 (default): count first after a
+                                 bottom-up or panel step or a frontier of mean degree >= 8; 2: count
+                                 first always */
+  int32_t reserved[3];
 } blest_opts;
 
 /* Fills *opts with the defaults listed above. */
@@ -237,7 +243,13 @@ blest_status blest_set_switch_model(blest_graph* g, const float* params, int32_t
 blest_status blest_set_switch_confidence(blest_graph* g, float min_prob);
 
 /* Per-level features (12 floats, the network's inputs before standardising)
- * of the last BFS's levels, to host: feat[nlev][12]. */
+ * of the last BFS's levels, to host: feat[nlev][12]. With F the frontier, Q its
+ * VSSs, S their slices, m_f its edges, U the unvisited vertices, m_u their
+ * edges, N_v / N_slices the BVSS totals, all logarithms base 2:
+ * log(1+|F|), log(1+S), log(1+|F|) - log n, log(1+|Q|) - log(1+N_v),
+ * log(1+S) - log(1+N_slices), log(1+m_f) - log(1+m), log(1+|U|) - log n,
+ * log(1+m_u) - log(1+m), log(1+|Q|) - log(1+|U|) (Eq. 3's ratio), and three
+ * reserved zeros. */
 blest_status blest_last_level_features(const blest_graph* g, float* feat, int32_t cap, int32_t* nlevels);
 
 /* Forward pass on the device: logits_dev[b][3] for x_dev[b][12] (already

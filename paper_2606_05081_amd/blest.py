@@ -72,7 +72,8 @@ class Opts(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("persistent", ctypes.c_int32), ("wide_slices", ctypes.c_int32),
                 ("prefilter", ctypes.c_int32), ("async_", ctypes.c_int32), ("msbfs_width", ctypes.c_int32),
                 ("random_seed", ctypes.c_uint64), ("device", ctypes.c_int32), ("single_block", ctypes.c_int32),
-                ("panel", ctypes.c_int32), ("panel_log2_rows", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("panel", ctypes.c_int32), ("panel_log2_rows", ctypes.c_int32),
+                ("stage2_count_first", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class GraphStats(ctypes.Structure):

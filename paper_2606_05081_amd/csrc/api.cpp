@@ -177,6 +177,7 @@ void blest_default_opts(blest_opts* o) {
   o->device = -1;
   o->single_block = 1;
   o->panel = 1;
+  o->stage2_count_first = 1;
 }
 
 blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_graph** out) {
@@ -198,6 +199,8 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   if (o.msbfs_width != 64 && o.msbfs_width != 128 && o.msbfs_width != 256 && o.msbfs_width != 512)
     return fail(BLEST_ERR_UNSUPPORTED, "msbfs_width must be 64, 128, 256 or 512");
   if (o.panel < 0 || o.panel > 2) return fail(BLEST_ERR_INVALID_ARG, "panel must be 0, 1 or 2");
+  if (o.stage2_count_first < 0 || o.stage2_count_first > 2)
+    return fail(BLEST_ERR_INVALID_ARG, "stage2_count_first must be 0, 1 or 2");
   if (o.panel_log2_rows != 0 && (o.panel_log2_rows < 5 || o.panel_log2_rows > 16))
     return fail(BLEST_ERR_UNSUPPORTED, "panel_log2_rows must be 0 (auto) or in [5, 16]");
   const int64_t n = csr->n, m = csr->m;
@@ -252,6 +255,7 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   d.persistent = o.persistent;
   d.prefilter = o.prefilter;
   d.single_block = o.single_block;
+  d.count_first = o.stage2_count_first;
   d.tick_us = tick_us;
   {
     hipError_t ge = blest::bfs_grid_size(d, 1, o.blocks_per_cu, &d.grid);
@@ -325,6 +329,7 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
     TRY(dalloc_t(g, &d.fheavy[i], static_cast<size_t>(d.nheavy_cap)));
   }
   TRY(dalloc_t(g, &d.ctl, 1));
+  TRY(dalloc_t(g, &d.part, static_cast<size_t>(d.grid) * 8));
   TRY(dalloc_t(g, &d.log, static_cast<size_t>(d.log_cap)));
   TRY(dalloc_t(g, &d.mlp, 1));
   if (g->reordered) {

@@ -66,22 +66,32 @@ __device__ __forceinline__ LevelView read_level_atomic(const Ctl* ctl, int slot)
 }
 
 // The 12 switch features of a level (network inputs before standardising).
-__device__ __forceinline__ void level_features(float (&f)[kMaxSwitchFeatures], const LevelView& v, long long n,
-                                               long long m, int level, long long prev_frontier) {
-  const long long unv = n - v.cumv, unv_e = m - v.cume;
-  f[0] = log2f(1.0f + static_cast<float>(v.frontier));
-  f[1] = log2f(1.0f + static_cast<float>(v.queue));
-  f[2] = log2f(1.0f + static_cast<float>(v.qslices));
-  f[3] = log2f(1.0f + static_cast<float>(v.fedges));
-  f[4] = log2f(1.0f + static_cast<float>(unv));
-  f[5] = log2f(1.0f + static_cast<float>(unv_e));
-  f[6] = log2f(static_cast<float>(n));
-  f[7] = log2f(1.0f + static_cast<float>(m));
-  f[8] = log2f(1.0f + static_cast<float>(level));
-  f[9] = f[0] - log2f(1.0f + static_cast<float>(prev_frontier));
-  const float inv = v.frontier > 0 ? 1.0f / static_cast<float>(v.frontier) : 0.0f;
-  f[10] = static_cast<float>(v.deg32) * inv;
-  f[11] = static_cast<float>(v.deg1024) * inv;
+__device__ __forceinline__ void level_features(float (&f)[kMaxSwitchFeatures], const LevelView& v, const BfsArgs& a,
+                                               int level, long long prev_frontier) {
+  (void)level;
+  const long long unv = a.n - v.cumv, unv_e = a.m - v.cume;
+  const float lf = log2f(1.0f + static_cast<float>(v.frontier));
+  const float lqs = log2f(1.0f + static_cast<float>(v.qslices));
+  const float ln = log2f(static_cast<float>(a.n));
+  const float lm = log2f(1.0f + static_cast<float>(a.m));
+  (void)lm;
+  f[0] = lf;
+  f[1] = lqs;
+  f[2] = lf - ln;
+  f[3] = log2f(1.0f + static_cast<float>(v.queue)) - log2f(1.0f + static_cast<float>(a.nvss));
+  f[4] = lqs - log2f(1.0f + static_cast<float>(a.nslices));
+  f[5] = log2f(1.0f + static_cast<float>(v.fedges)) - lm;
+  f[6] = log2f(1.0f + static_cast<float>(unv)) - ln;
+  f[7] = log2f(1.0f + static_cast<float>(unv_e)) - lm;
+  // Eq. 3's own quantities, as a log ratio
+  f[8] = log2f(1.0f + static_cast<float>(v.queue)) - log2f(1.0f + static_cast<float>(unv));
+  // Reserved (zero). The frontier degree histogram and the growth ratio were
+  // inputs once; on R-MAT + grid training data they let the network learn
+  // family shortcuts that failed on Erdos-Renyi graphs.
+  (void)prev_frontier;
+  f[9] = 0.0f;
+  f[10] = 0.0f;
+  f[11] = 0.0f;
 }
 
 // Eq. 3: bottom-up iff #unvisited < eta * |Q_curr| (|Q| counts VSSs).
@@ -488,17 +498,39 @@ __device__ __attribute__((noinline)) long long engine_push(const BfsArgs& a, int
       }
     }
   }
+  // Light vertices, 64 per wave step: the wave walks the concatenation of
+  // their rows, 64 edges at a time; each lane finds the vertex owning its edge
+  // by a binary search over the wave's prefix sums of the degrees, so every
+  // lane has an edge (not a vertex's serial chain of loads) in flight.
   gptr<const int32_t> __restrict__ light = to_global(a.flight[sel]);
-  for (long long i = gtid; i < nlight; i += nthreads) {
-    const int u = light[i];
-    const int e = rp[u + 1];
-    const int p0 = rp[u];
-    work += e - p0;
-    for (int p = p0; p < e; ++p) {
-      const int v = col[p];
-      if (!((vis[v / SIGMA] >> (v % SIGMA)) & 1u)) {
-        mark[v] = 1;
-        if (REC) record_set(hs, v / SIGMA, a.ctl);
+  (void)gtid;
+  (void)nthreads;
+  for (long long base = gwave * 64; base < nlight; base += nwaves * 64) {
+    const long long i = base + lane;
+    int p0 = 0, d = 0;
+    if (i < nlight) {
+      const int u = light[i];
+      p0 = rp[u];
+      d = rp[u + 1] - p0;
+    }
+    const int incl = wave_inclusive_scan(d);
+    const int total = __shfl(incl, 63, 64);
+    work += lane == 0 ? total : 0;
+    for (int e0 = 0; e0 < total; e0 += 64) {
+      const int e = e0 + lane;
+      int lo = 0;
+#pragma unroll
+      for (int stp = 32; stp >= 1; stp >>= 1)
+        if (__shfl(incl, lo + stp - 1, 64) <= e) lo += stp;
+      const int owner = lo & 63;
+      const int start = __shfl(incl, owner, 64) - __shfl(d, owner, 64);
+      const int op0 = __shfl(p0, owner, 64);
+      if (e < total) {
+        const int v = col[op0 + (e - start)];
+        if (!((vis[v / SIGMA] >> (v % SIGMA)) & 1u)) {
+          mark[v] = 1;
+          if (REC) record_set(hs, v / SIGMA, a.ctl);
+        }
       }
     }
   }
@@ -625,20 +657,32 @@ __device__ __forceinline__ void load_set_rp(gptr<const int32_t> rp, long long s,
 
 
 // Stage 2 over windows of 2*BLOCK slice sets; set_at(win, k) gives the set
-// handled by this thread in slot k of window win, or -1. Accumulates the
-// level statistics of this block into st[]. Output space in the queue and the
-// push lists is reserved per window with one device atomic per list (grid
-// mode) or from the block-local cursors `local` (one workgroup alone: no
-// atomics; the totals are stored by the caller). Queue descriptors and heavy
-// edge chunks are written wave-cooperatively: each lane finds the run that
-// owns its output index by a binary search over the wave's prefix sums, so a
-// hub set with thousands of VSSs costs a few wave steps, not a serial loop.
-template <int SIGMA, int BLOCK, bool LOCAL, class SetAt>
+// handled by this thread in slot k of window win, or -1. MODE:
+//  FIN_ATOMIC  marks -> visited/frontier/levels, and the lists, with output
+//              space reserved per window by one device atomic per list;
+//  FIN_LOCAL   the same with the block-local cursors `local` (one workgroup
+//              alone: no atomics; the caller stores the totals);
+//  FIN_COUNT   marks -> visited/frontier/levels and counts only: every set's
+//              frontier word is rewritten (0 if it gained nothing) and the
+//              list sizes are added to st[5..7]; no list is written;
+//  FIN_EMIT    no state change: the frontier words written by FIN_COUNT give
+//              the new vertices, and the lists asked for (want_push,
+//              want_queue) are written from the cursors `local`, which the
+//              caller presets to this block's offsets.
+// st[] accumulates frontier, queued slices, frontier edges, degree >= 32,
+// degree >= 1024 and (FIN_COUNT) light, heavy and queue entries. Queue
+// descriptors and heavy edge chunks are written wave-cooperatively: each lane
+// finds the run that owns its output index by a binary search over the wave's
+// prefix sums, so a hub set with thousands of VSSs costs a few wave steps.
+enum FinMode : int { FIN_ATOMIC = 0, FIN_LOCAL = 1, FIN_COUNT = 2, FIN_EMIT = 3 };
+
+template <int SIGMA, int BLOCK, int MODE, class SetAt>
 __device__ void finalize_windows(const BfsArgs& a, int new_level, gptr<unsigned long long> acc, int sel_out,
-                                 long long win0, long long nwin, long long wstep, SetAt set_at, long long (&st)[5],
-                                 unsigned long long* local) {
+                                 long long win0, long long nwin, long long wstep, SetAt set_at, long long (&st)[8],
+                                 unsigned long long* local, bool want_push = true, bool want_queue = true) {
   using M = typename MaskOf<SIGMA>::T;
   constexpr int SPT = 2;
+  constexpr bool UPDATE = MODE != FIN_EMIT;
   __shared__ int lds32[3 * (BLOCK / 64)];
   __shared__ unsigned long long bases[3];
   gptr<M> __restrict__ vis = to_global(static_cast<M*>(a.vis));
@@ -663,46 +707,69 @@ __device__ void finalize_windows(const BfsArgs& a, int new_level, gptr<unsigned 
       sset[k] = s;
       nw[k] = 0;
       nl[k] = nh[k] = nq[k] = 0;
-      if (s >= 0) {
+      if (s < 0) continue;
+      M x = 0;
+      if constexpr (UPDATE) {
         const M bits = load_marks<SIGMA>(mark + s * SIGMA);
         if (bits) {
           clear_marks<SIGMA>(mark + s * SIGMA);
           const M old = vis[s];
-          const M x = static_cast<M>(bits & ~old);
-          if (x) {
-            vis[s] = static_cast<M>(old | x);
-            front[s] = x;
-            nw[k] = x;
-            int r[SIGMA + 1];
-            load_set_rp<SIGMA>(rp, s, r);
+          x = static_cast<M>(bits & ~old);
+          if (x) vis[s] = static_cast<M>(old | x);
+        }
+        if (MODE == FIN_COUNT)
+          front[s] = x;
+        else if (x)
+          front[s] = x;
+      } else {
+        x = front[s];
+      }
+      if (!x) continue;
+      nw[k] = x;
+      const bool need_rp = UPDATE || want_push;
+      if (need_rp) {
+        int r[SIGMA + 1];
+        load_set_rp<SIGMA>(rp, s, r);
 #pragma unroll
-            for (int b = 0; b < SIGMA; ++b) {
-              if (!((x >> b) & 1u)) continue;
-              const long long u = s * SIGMA + b;
-              const int d = r[b + 1] - r[b];
-              st[0] += 1;
-              st[2] += d;
-              st[3] += d >= 32;
-              st[4] += d >= 1024;
-              if (d > kLightMax)
-                nh[k] += (d + kHeavyChunk - 1) / kHeavyChunk;
-              else
-                nl[k] += 1;
-              levels[orig_id ? orig_id[u] : u] = new_level;
-            }
-            const uint32_t ns = sp[s + 1] - sp[s];
-            nq[k] = static_cast<int>((ns + tau - 1) / tau);
-            st[1] += ns;
+        for (int b = 0; b < SIGMA; ++b) {
+          if (!((x >> b) & 1u)) continue;
+          const long long u = s * SIGMA + b;
+          const int d = r[b + 1] - r[b];
+          if constexpr (UPDATE) {
+            st[0] += 1;
+            st[2] += d;
+            st[3] += d >= 32;
+            st[4] += d >= 1024;
+            levels[orig_id ? orig_id[u] : u] = new_level;
           }
+          if (d > kLightMax)
+            nh[k] += (d + kHeavyChunk - 1) / kHeavyChunk;
+          else
+            nl[k] += 1;
         }
       }
+      if (UPDATE || want_queue) {
+        const uint32_t ns = sp[s + 1] - sp[s];
+        nq[k] = static_cast<int>((ns + tau - 1) / tau);
+        if constexpr (UPDATE) st[1] += ns;
+      }
+      if (MODE == FIN_EMIT && !want_push) nl[k] = nh[k] = 0;
     }
+    if constexpr (UPDATE) {
+#pragma unroll
+      for (int k = 0; k < SPT; ++k) {
+        st[5] += nl[k];
+        st[6] += nh[k];
+        st[7] += nq[k];
+      }
+    }
+    if constexpr (MODE == FIN_COUNT) continue;
     int cnt[3] = {nl[0] + nl[1], nh[0] + nh[1], nq[0] + nq[1]};
     if (!__syncthreads_or(cnt[0] | cnt[1] | cnt[2])) continue;
     int ex[3], tot[3];
     block_exclusive_scan<BLOCK, 3>(cnt, ex, tot, lds32);
     if (threadIdx.x == 0) {
-      if (LOCAL) {
+      if (MODE != FIN_ATOMIC) {
         for (int f = 0; f < 3; ++f) {
           bases[f] = local[f];
           local[f] += tot[f];
@@ -794,8 +861,10 @@ __device__ void finalize_windows(const BfsArgs& a, int new_level, gptr<unsigned 
 // Adds a block's Stage 2 statistics to the level slot (block 0 also carries
 // the cumulative counts of the previous level).
 template <int BLOCK>
-__device__ void finalize_stats(gptr<unsigned long long> acc, long long (&st)[5], long long cumv_in, long long cume_in) {
+__device__ void finalize_stats(gptr<unsigned long long> acc, const long long (&st8)[8], long long cumv_in,
+                               long long cume_in) {
   __shared__ long long lds64[5 * (BLOCK / 64)];
+  long long st[5] = {st8[0], st8[1], st8[2], st8[3], st8[4]};
   block_sum64<BLOCK, 5>(st, lds64);
   if (threadIdx.x == 0) {
     if (st[0]) {
@@ -822,16 +891,106 @@ __device__ void finalize(const BfsArgs& a, int new_level, int slot_out, int sel_
                          long long cume_in, unsigned nblocks) {
   constexpr long long WIN = static_cast<long long>(BLOCK) * 2;
   const gptr<unsigned long long> acc = to_global(&a.ctl->acc[slot_out][0][0]);
-  long long st[5] = {0, 0, 0, 0, 0};  // frontier, queued slices, frontier edges, deg>=32, deg>=1024
+  long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // frontier, queued slices, frontier edges, deg>=32, deg>=1024
   const long long nsets = a.nsets;
   const long long tid = threadIdx.x;
-  finalize_windows<SIGMA, BLOCK, false>(a, new_level, acc, sel_out, blockIdx.x, (nsets + WIN - 1) / WIN, nblocks,
+  finalize_windows<SIGMA, BLOCK, FIN_ATOMIC>(a, new_level, acc, sel_out, blockIdx.x, (nsets + WIN - 1) / WIN, nblocks,
                                         [=](long long win, int k) -> long long {
                                           const long long s = win * WIN + k * BLOCK + tid;
                                           return s < nsets ? s : -1;
                                         },
                                         st, nullptr);
   finalize_stats<BLOCK>(acc, st, cumv_in, cume_in);
+}
+
+// ------------------------------------------------- two-phase grid Stage 2
+//
+// In the persistent kernel a grid level's Stage 2 runs in two phases with no
+// device atomics. Count: every workgroup sweeps its windows (marks ->
+// visited/frontier/levels) and stores its partial counters with plain stores.
+// After the barrier every workgroup sums the partials in the same order, so
+// all of them hold the same level statistics and pick the same engine for
+// the next level, and each knows the sum of the list sizes of the workgroups
+// before it. Emit: only when that engine reads a list (the VSS queue for BVSS
+// over the queue, the vertex lists for push; all lists in probe mode) do the
+// workgroups sweep again and write it at those offsets, behind one more
+// barrier. Bottom-up and panel levels skip the emit phase.
+constexpr int kParts = 8;  // frontier, queued slices, frontier edges, deg>=32, deg>=1024, light, heavy, queue
+
+// MODE = FIN_COUNT (counts only) or FIN_ATOMIC (lists too, output space
+// reserved with one device atomic per window and list on the cursors of
+// slot `slot_out`); either way the level statistics go to the partials.
+template <int SIGMA, int BLOCK, int MODE>
+__device__ void finalize_count(const BfsArgs& a, int new_level, int slot_out, int sel_out) {
+  constexpr long long WIN = static_cast<long long>(BLOCK) * 2;
+  __shared__ long long lds64[kParts * (BLOCK / 64)];
+  long long st[kParts] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const long long nsets = a.nsets;
+  const long long tid = threadIdx.x;
+  finalize_windows<SIGMA, BLOCK, MODE>(a, new_level, to_global(&a.ctl->acc[slot_out][0][0]), sel_out, blockIdx.x,
+                                            (nsets + WIN - 1) / WIN, gridDim.x,
+                                            [=](long long win, int k) -> long long {
+                                              const long long s = win * WIN + k * BLOCK + tid;
+                                              return s < nsets ? s : -1;
+                                            },
+                                            st, nullptr);
+  block_sum64<BLOCK, kParts>(st, lds64);
+  const gptr<long long> part = to_global(a.part);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int f = 0; f < kParts; ++f) part[static_cast<long long>(blockIdx.x) * kParts + f] = st[f];
+  }
+}
+
+// Sums the partial counters of all workgroups (after the barrier that follows
+// finalize_count). before[] = light, heavy and queue entries of the
+// workgroups with a smaller index (this workgroup's list offsets).
+template <int BLOCK>
+__device__ void reduce_parts(const BfsArgs& a, long long (&tot)[kParts], long long (&before)[3]) {
+  __shared__ long long s_tot[kParts], s_bef[3];
+  const gptr<const long long> part = to_global(static_cast<const long long*>(a.part));
+  const int nb = static_cast<int>(gridDim.x);
+  const int me = static_cast<int>(blockIdx.x);
+  const int lane = lane_id(), w = wave_in_block();
+  for (int f = w; f < kParts; f += BLOCK / 64) {
+    long long t = 0, bs = 0;
+    for (int b = lane; b < nb; b += 64) {
+      const long long x = part[static_cast<long long>(b) * kParts + f];
+      t += x;
+      bs += b < me ? x : 0;
+    }
+    t = wave_sum(t);
+    bs = wave_sum(bs);
+    if (lane == 0) {
+      s_tot[f] = t;
+      if (f >= 5) s_bef[f - 5] = bs;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int f = 0; f < kParts; ++f) tot[f] = s_tot[f];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) before[f] = s_bef[f];
+  __syncthreads();
+}
+
+template <int SIGMA, int BLOCK>
+__device__ void finalize_emit(const BfsArgs& a, int sel_out, const long long (&before)[3], bool want_push,
+                              bool want_queue) {
+  constexpr long long WIN = static_cast<long long>(BLOCK) * 2;
+  __shared__ unsigned long long cursor[3];
+  if (threadIdx.x < 3) cursor[threadIdx.x] = static_cast<unsigned long long>(before[threadIdx.x]);
+  __syncthreads();
+  long long st[kParts] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const long long nsets = a.nsets;
+  const long long tid = threadIdx.x;
+  finalize_windows<SIGMA, BLOCK, FIN_EMIT>(a, 0, to_global(&a.ctl->acc[0][0][0]), sel_out, blockIdx.x,
+                                           (nsets + WIN - 1) / WIN, gridDim.x,
+                                           [=](long long win, int k) -> long long {
+                                             const long long s = win * WIN + k * BLOCK + tid;
+                                             return s < nsets ? s : -1;
+                                           },
+                                           st, cursor, want_push, want_queue);
 }
 
 // ------------------------------------------------- single-workgroup levels
@@ -864,16 +1023,17 @@ __device__ void finalize_list(const BfsArgs& a, int new_level, int slot_out, int
   __syncthreads();
   const int count = hs[kSingleHash];
   const lptr<const int> list = hs + kSingleHash + 1;
-  long long st[5] = {0, 0, 0, 0, 0};
+  long long st8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int tid = threadIdx.x;
-  finalize_windows<SIGMA, BLOCK, true>(a, new_level, acc, sel_out, 0, (count + WIN - 1) / WIN, 1,
+  finalize_windows<SIGMA, BLOCK, FIN_LOCAL>(a, new_level, acc, sel_out, 0, (count + WIN - 1) / WIN, 1,
                                        [=](long long win, int k) -> long long {
                                          const long long i = win * WIN + k * BLOCK + tid;
                                          return i < count ? static_cast<long long>(list[i]) : -1;
                                        },
-                                       st, local);
+                                       st8, local);
   __syncthreads();
   for (int i = tid; i < kSingleHash + 1; i += BLOCK) hs[i] = (i == kSingleHash) ? 0 : -1;
+  long long st[5] = {st8[0], st8[1], st8[2], st8[3], st8[4]};
   block_sum64<BLOCK, 5>(st, lds64);
   if (threadIdx.x == 0) {
     auto put = [&](int f, unsigned long long v) {
@@ -1005,7 +1165,7 @@ __device__ int single_episode(const BfsArgs& a, int level, int engine, int fallb
     v = read_level_atomic(a.ctl, level % kStatSlots);
     if (v.frontier == 0) return level;
     if (__hip_atomic_load(&a.ctl->error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return level;
-    level_features(feat, v, a.n, a.m, level, prev);
+    level_features(feat, v, a, level, prev);
     engine = choose_engine(a, v, feat, level, s_mlp, &fallback);
     if (!single_eligible(a, engine, v)) return level;
   }
@@ -1032,15 +1192,21 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
   if (!grid_barrier(a.ctl, bc)) return;
   unsigned episodes = 0;
   int level = 0;
+  constexpr bool kPanelFmt = SIGMA == 8 && sizeof(SliceT) == 4;
+  LevelView v = read_level(a.ctl, 0);
+  long long prev_frontier = 0;
+  bool decided = false;  // engine/feat/fallback already computed for `level`
+  int engine = 0, fallback = 0;
+  float feat[kMaxSwitchFeatures];
   for (;;) {
     const int slot = level % kStatSlots;
-    const LevelView v = read_level(a.ctl, slot);
     if (v.frontier == 0) break;
-    const long long prev_frontier = level > 0 ? read_level(a.ctl, (level + kStatSlots - 1) % kStatSlots).frontier : 0;
-    float feat[kMaxSwitchFeatures];
-    level_features(feat, v, a.n, a.m, level, prev_frontier);
-    int fallback = 0;
-    const int engine = choose_engine(a, v, feat, level, learned ? s_mlp : nullptr, &fallback);
+    if (!decided) {
+      level_features(feat, v, a, level, prev_frontier);
+      fallback = 0;
+      engine = choose_engine(a, v, feat, level, learned ? s_mlp : nullptr, &fallback);
+    }
+    decided = false;
     if (single_eligible(a, engine, v)) {
       ++episodes;
       if (blockIdx.x == 0) {
@@ -1079,6 +1245,8 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
       if (s_level < 0 || __hip_atomic_load(&a.ctl->error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
         return;
       level = s_level;
+      v = read_level(a.ctl, level % kStatSlots);
+      prev_frontier = level > 0 ? read_level(a.ctl, (level + kStatSlots - 1) % kStatSlots).frontier : 0;
       continue;
     }
     if (blockIdx.x == 0) {
@@ -1101,12 +1269,69 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
       if (!grid_barrier(a.ctl, bc)) return;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_mid = dev_ticks();
-    finalize<SIGMA, BLOCK>(a, level + 1, (level + 1) % kStatSlots, sel ^ 1, v.cumv, v.cume, nblocks);
-    if (!grid_barrier(a.ctl, bc)) return;
+    // Stage 2. When the next level is likely dense (this step was bottom-up
+    // or BVSS over the panel copy, or the frontier's mean degree is at least
+    // 8, so the next frontier will be much larger) it will likely read no
+    // list: the two-phase form counts first and writes lists only if the
+    // chosen engine needs them. Otherwise the lists are built in the same
+    // pass (one device atomic per window and list), which saves a barrier.
+    // The level statistics come from the per-workgroup partials either way.
+    const bool dense_next = engine == BLEST_ENGINE_BOTTOM_UP ||
+                            (engine == BLEST_ENGINE_BVSS && kPanelFmt && use_panel(a, v)) ||
+                            v.fedges >= 8 * v.frontier;
+    const bool two_phase = !a.probe && (a.count_first == 2 || (a.count_first == 1 && dense_next));
+    LevelView nv;
+    bool emitted = false;
+    long long before[3] = {0, 0, 0};
+    {
+      if (two_phase)
+        finalize_count<SIGMA, BLOCK, FIN_COUNT>(a, level + 1, (level + 1) % kStatSlots, sel ^ 1);
+      else
+        finalize_count<SIGMA, BLOCK, FIN_ATOMIC>(a, level + 1, (level + 1) % kStatSlots, sel ^ 1);
+      if (!grid_barrier(a.ctl, bc)) return;
+      long long tot[kParts];
+      reduce_parts<BLOCK>(a, tot, before);
+      nv.frontier = tot[0];
+      nv.qslices = tot[1];
+      nv.fedges = tot[2];
+      nv.deg32 = tot[3];
+      nv.deg1024 = tot[4];
+      nv.light = tot[5];
+      nv.heavy = tot[6];
+      nv.queue = tot[7];
+      nv.cumv = v.cumv + tot[0];
+      nv.cume = v.cume + tot[2];
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // the level's counters, for a single-workgroup episode that may follow
+        unsigned long long* acc = &a.ctl->acc[(level + 1) % kStatSlots][0][0];
+        const long long vals[10] = {nv.frontier, nv.queue, nv.qslices, nv.fedges, nv.deg32,
+                                    nv.deg1024,  nv.light, nv.heavy,   nv.cumv,   nv.cume};
+        for (int f = 0; f < 10; ++f)
+          __hip_atomic_store(acc + f * kPad, static_cast<unsigned long long>(vals[f]), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    if (nv.frontier > 0) {
+      level_features(feat, nv, a, level + 1, v.frontier);
+      fallback = 0;
+      engine = choose_engine(a, nv, feat, level + 1, learned ? s_mlp : nullptr, &fallback);
+      decided = true;
+      if (two_phase) {
+        const bool want_queue = engine == BLEST_ENGINE_BVSS && !(kPanelFmt && use_panel(a, nv));
+        const bool want_push = engine == BLEST_ENGINE_PUSH;
+        if (want_queue || want_push) {
+          finalize_emit<SIGMA, BLOCK>(a, sel ^ 1, before, want_push, want_queue);
+          emitted = true;
+        }
+      }
+    }
+    if (emitted && !grid_barrier(a.ctl, bc)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) {
       a.log[level].t_end = dev_ticks();
       a.log[level].work = static_cast<long long>(a.ctl->acc[slot][F_WORK][0]);
     }
+    prev_frontier = v.frontier;
+    v = nv;
     ++level;
   }
   if (blockIdx.x == 0) {
@@ -1156,7 +1381,7 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_stage1(BfsArgs a, int level, long
     __syncthreads();
   }
   float feat[kMaxSwitchFeatures];
-  level_features(feat, v, a.n, a.m, level, prev);
+  level_features(feat, v, a, level, prev);
   int fallback = 0;
   const int engine = choose_engine(a, v, feat, level, learned ? s_mlp : nullptr, &fallback);
   if (blockIdx.x == 0) {
@@ -1270,6 +1495,7 @@ BfsArgs bfs_args(const DevGraph& g) {
     a.fheavy[i] = g.fheavy[i];
   }
   a.ctl = g.ctl;
+  a.part = g.part;
   a.log = g.log;
   a.log_cap = g.log_cap;
   a.mlp = g.mlp;
@@ -1282,7 +1508,10 @@ BfsArgs bfs_args(const DevGraph& g) {
   a.npanels = static_cast<int32_t>(g.npanels);
   a.panel_rb = g.panel_rb;
   a.panel_mode = g.panel_mode;
-  a.panel_slots = g.nchunks * 64;
+  a.panel_slots = g.nchunks * kPanelChunk;
+  a.nvss = g.nvss;
+  a.nslices = g.nslices;
+  a.count_first = g.count_first;
   a.timeout_ticks = 1000000000ULL;  // 10 s at the 100 MHz device clock
   return a;
 }

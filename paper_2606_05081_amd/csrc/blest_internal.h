@@ -95,6 +95,7 @@ struct BfsArgs {
   const void* degmask;
   const int32_t* orig_id;
   int64_t n, m, nsets;
+  int64_t nvss, nslices;  // totals of the BVSS (switch features)
   int32_t tau;
   // working state
   void* vis;       // sigma-bit visited word per slice set (V_curr)
@@ -104,6 +105,7 @@ struct BfsArgs {
   int32_t* flight[2];             // light frontier vertices
   unsigned long long* fheavy[2];  // heavy frontier edge chunks: (vertex << 32) | first edge offset
   Ctl* ctl;
+  long long* part;  // per-workgroup partial Stage 2 counters (grid size x 8)
   LevelRec* log;
   int32_t log_cap;
   const MlpDev* mlp;
@@ -123,7 +125,8 @@ struct BfsArgs {
   int32_t npanels;
   int32_t panel_rb;        // log2 rows per panel
   int32_t panel_mode;      // 1: dense levels only, 2: every BVSS level
-  long long panel_slots;   // nchunks * 64
+  long long panel_slots;   // nchunks * kPanelChunk
+  int32_t count_first;     // two-phase Stage 2 after dense steps
   unsigned long long timeout_ticks;
 };
 
@@ -145,6 +148,7 @@ struct DevGraph {
   int32_t* flight[2] = {nullptr, nullptr};
   unsigned long long* fheavy[2] = {nullptr, nullptr};
   Ctl* ctl = nullptr;
+  long long* part = nullptr;
   LevelRec* log = nullptr;
   int log_cap = 0;
   MlpDev* mlp = nullptr;
@@ -155,6 +159,7 @@ struct DevGraph {
   uint32_t* pptr = nullptr;
   int64_t npanels = 0, nchunks = 0;
   int panel_rb = 0, panel_mode = 0;
+  int count_first = 1;
   size_t mark_bytes = 0;
   double tick_us = 0.01;      // device clock period in microseconds
 };

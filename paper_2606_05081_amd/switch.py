@@ -13,7 +13,9 @@ builds that criterion:
    (ties go to Eq. 3's choice).
 2. Training: the 12 -> 64 -> 64 -> 3 network is trained by the library's own
    HIP kernels (blest_mlp_train: minibatch softmax cross-entropy, Adam), with
-   class- and family-balanced sample weights.
+   cost-sensitive sample weights (a level weighs what a wrong choice can lose
+   there, each graph family carrying the same total) and labels that keep
+   Eq. 3's choice unless another engine is at least 5% faster.
 3. Evaluation: on held-out graphs, per-level regret against the per-level
    optimum, Sum(t_chosen - t_min) / Sum(t_min), as in Fig. 5, for the learned
    choices and for Eq. 3, plus end-to-end GTEPS of both policies.
@@ -28,9 +30,16 @@ import time
 
 import numpy as np
 
-FEATURES = ["log2(1+|F|)", "log2(1+|Q|)", "log2(1+queued slices)", "log2(1+m_f)", "log2(1+#unvisited)",
-            "log2(1+m_u)", "log2 n", "log2(1+m)", "log2(1+level)", "log2 |F_l|/|F_l-1|", "frac deg>=32",
-            "frac deg>=1024"]
+# The 12 per-level inputs (base-2 logarithms). Only the first two are
+# absolute sizes (they place a level in the latency-bound regime); the others
+# are shares of the graph's totals, so a graph larger than the training graphs
+# still lands inside the training distribution. The last three are reserved
+# zeros: the frontier degree histogram and the frontier growth ratio were
+# inputs once, and on R-MAT + grid training data they let the network learn
+# family shortcuts that failed on Erdos-Renyi graphs.
+FEATURES = ["log(1+|F|)", "log(1+queued slices)", "log |F|/n", "log |Q|/N_v", "log queued slices/all slices",
+            "log m_f/m", "log #unvisited/n", "log m_u/m", "log |Q|/#unvisited", "reserved", "reserved",
+            "reserved"]
 ENGINES = ["bvss", "push", "bottom_up"]
 MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "switch_model.json")
 
@@ -205,6 +214,30 @@ def build_dataset(specs=TRAIN_SPECS, runs_per_graph=20, grid_levels_per_run=96, 
     return np.concatenate(Xs), np.concatenate(Ts), np.concatenate(Hs), np.array(fam)
 
 
+def per_graph_enable(g, srcs, trials=3):
+    """Per-graph enable, as the paper enables its switch per graph by trial
+    traversals (Fig. 5 discussion): the learned policy is kept for this graph
+    only if its trial traversals take less device time than Eq. 3's.
+    Returns (enabled, {policy name: mean ms})."""
+    import torch
+    from . import blest
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    times = {}
+    for name, pol in (("heuristic", blest.Policy.HEURISTIC), ("learned", blest.Policy.LEARNED)):
+        g.set_policy(pol)
+        g.bfs(int(srcs[0]), out)
+        g.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for s in srcs[:trials]:
+            g.bfs(int(s), out)
+        e1.record()
+        g.sync()
+        torch.cuda.synchronize()
+        times[name] = e0.elapsed_time(e1) / min(trials, len(srcs))
+    return times["learned"] < times["heuristic"], times
+
+
 def evaluate_graph(kind, size, seed, params, mean, std, n_sources=16, log=print):
     """Regret of both policies on probe timings and end-to-end GTEPS of both."""
     import torch
@@ -242,8 +275,13 @@ def evaluate_graph(kind, size, seed, params, mean, std, n_sources=16, log=print)
         t = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(len(srcs))])
         res[f"gteps_{name}"] = float(len(t) / np.sum(t * 1e-3 / np.array(edges) * 1e9))
     res["learned_over_heuristic"] = res["gteps_learned"] / res["gteps_heuristic"]
+    enabled, trial_ms = per_graph_enable(g, inputs.sources(rp, 3, seed=seed + 2))
+    res["learned_enabled"] = bool(enabled)
+    res["trial_ms"] = trial_ms
+    res["gteps_learned_per_graph"] = res["gteps_learned"] if enabled else res["gteps_heuristic"]
     g.close()
     log(f"[eval] {res}")
+    res["probe"] = {"X": X, "T": T, "H": Hc}
     return res
 
 
@@ -273,8 +311,13 @@ def main(argv=None):
     if args.dataset_out:
         np.savez(args.dataset_out, X=X, T=T, H=Hc, fam=fam)
     if args.eval:
+        probes = {}
         for kind, size, seed in EVAL_SPECS:
-            evaluate_graph(kind, size, seed, params, mean, std)
+            r = evaluate_graph(kind, size, seed, params, mean, std)
+            for k, v in r.pop("probe").items():
+                probes[f"{r['graph']}_{k}"] = v
+        if args.dataset_out:
+            np.savez(args.dataset_out.replace(".npz", "_eval.npz"), **probes)
 
 
 if __name__ == "__main__":

@@ -75,6 +75,7 @@ def test_rmat_s16_all_policies(blest):
     dict(single_block=0), dict(single_block=0, block_size=512), dict(block_size=256, sigma=32),
     dict(panel=0), dict(panel=2), dict(panel=2, block_size=256), dict(panel=2, persistent=0),
     dict(panel=2, blocks_per_cu=1, single_block=0),
+    dict(stage2_count_first=0), dict(stage2_count_first=2), dict(stage2_count_first=2, single_block=0, panel=0),
 ])
 def test_option_matrix(blest, opt):
     for rp, col in [inputs.rmat_graph(13, 77), inputs.grid_graph(70, 78)]:
