@@ -17,7 +17,9 @@ Also measured in the same run and printed in the JSON line: the plain
 method (BVSS top-down at every level) on the same sources with its roofline,
 the 2048x2048 grid with 10% edge deletion (RCM-reordered), batched
 multi-source BFS sources/s on scale-20 R-MAT (960 sources in batches of
-64/128/256/512, one launch) and the CPU oracle on a bounded sample.
+64/128/256/512, one launch), exact closeness (all 262,144 sources of
+scale-18 R-MAT; 16,384 sources of scale-23 R-MAT) and the CPU oracle on a
+bounded sample.
 """
 from __future__ import annotations
 
@@ -316,6 +318,24 @@ def main():
         extras["msbfs_sources_per_s"] = round(960 / ms_ms * 1e3, 1)
         extras["msbfs_ms"] = round(ms_ms, 3)
         mg.close()
+        # exact closeness: all sources of scale-18 R-MAT, 16,384 sources of scale-23 R-MAT (512 per batch)
+        for tag, scale, gseed, k in (("closeness_rmat18_all", 18, 1050, None), ("closeness_rmat23_16k", 23, 1052, 16384)):
+            crp, ccol = inputs.rmat_graph(scale, gseed)
+            cs = np.arange(crp.size - 1, dtype=np.int32) if k is None else inputs.sources(crp, k, seed=gseed + 1)
+            cg = blest.Graph(crp, ccol, device=0, msbfs_width=512, **{"async": 1})
+            cg.closeness(cs[:512])
+            cg.sync()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            cg.closeness(cs)
+            e1.record()
+            cg.sync()
+            torch.cuda.synchronize()
+            cms = e0.elapsed_time(e1)
+            extras[tag] = {"sources": int(cs.size), "ms": round(cms, 1), "sources_per_s": round(cs.size / cms * 1e3, 1)}
+            print(f"# {tag}: {cs.size} sources in {cms:.1f} ms", file=sys.stderr, flush=True)
+            cg.close()
         cpu = cpu_baseline(rp, col, srcs)
 
     line = {

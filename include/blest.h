@@ -85,7 +85,7 @@ typedef struct {
   int32_t reorder;      /* BLEST_REORDER_* (default AUTO) */
   int32_t policy;       /* BLEST_POLICY_* (default HEURISTIC) */
   float eta;            /* Eq. 3 switching constant (default 10) */
-  int32_t block_size;   /* threads per workgroup of the persistent kernel (default 1024) */
+  int32_t block_size;   /* threads per workgroup of the persistent kernel: 256, 512 (default) or 1024 */
   int32_t blocks_per_cu;/* persistent workgroups per compute unit, 0 = as many as fit */
   int32_t persistent;   /* 1 (default): one cooperative launch per BFS; 0: one launch per stage */
   int32_t wide_slices;  /* 1: 64-bit slices (row | mask) even where 32-bit packing fits */

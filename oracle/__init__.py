@@ -11,6 +11,8 @@ Contents, each following the passage cited beside it:
   closeness      -- per-source sums/reach/cc (Closeness Centrality, Eq. 4/5,
                     normalised per source as (reach-1)/sum)
   far            -- per-target sums of Eq. 4
+  components     -- connected-component labels (reach(s) = size of s's
+                    component, the reachable set of Eq. 4's sums)
   certificate    -- O(m) proof that a level array is the BFS distance
   bvss           -- BVSS slices, realPtrs, virtualToReal (Section BVSS)
   get_vi         -- the multi-source index remap (Multi-Source BFS)
@@ -61,6 +63,8 @@ def _load():
     lib.oracle_bvss_count.restype = i32
     lib.oracle_bvss_fill.argtypes = [i64, p32, p32, i32, i32, p64, p64, p64, p32, pu64]
     lib.oracle_bvss_fill.restype = i32
+    lib.oracle_components.argtypes = [i64, p32, p32, p32]
+    lib.oracle_components.restype = i64
     _lib = lib
     return lib
 
@@ -124,6 +128,16 @@ def closeness(rp, col, srcs, threads: int = 0):
     if r < 0:
         raise ValueError(f"oracle_closeness failed ({r})")
     return sums, reach, cc
+
+
+def components(rp, col) -> np.ndarray:
+    """Component label of every vertex, components numbered by smallest vertex."""
+    rp, col, n = _csr(rp, col)
+    lab = np.empty(n, dtype=np.int32)
+    r = _load().oracle_components(n, _ptr(rp, ctypes.c_int32), _ptr(col, ctypes.c_int32), _ptr(lab, ctypes.c_int32))
+    if r < 0:
+        raise ValueError(f"oracle_components failed ({r})")
+    return lab
 
 
 def far(rp, col, srcs, threads: int = 0) -> np.ndarray:

@@ -62,6 +62,37 @@ int32_t oracle_bfs(int64_t n, const int32_t *rp, const int32_t *col, int32_t src
   return maxlev + 1;
 }
 
+/* Connected components of the undirected graph: label[v] = index of v's
+ * component, components numbered in order of their smallest vertex (a FIFO
+ * BFS from each vertex not yet labelled, in vertex order). Returns the number
+ * of components. Used to check reach counts: reach(s) = |component of s|. */
+int64_t oracle_components(int64_t n, const int32_t *rp, const int32_t *col, int32_t *label) {
+  if (n <= 0) return ORACLE_ERR_ARG;
+  int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  if (!queue) return ORACLE_ERR_OOM;
+  for (int64_t v = 0; v < n; ++v) label[v] = -1;
+  int64_t ncomp = 0;
+  for (int64_t s = 0; s < n; ++s) {
+    if (label[s] != -1) continue;
+    int64_t head = 0, tail = 0;
+    label[s] = (int32_t)ncomp;
+    queue[tail++] = (int32_t)s;
+    while (head < tail) {
+      int32_t u = queue[head++];
+      for (int32_t p = rp[u]; p < rp[u + 1]; ++p) {
+        int32_t v = col[p];
+        if (label[v] == -1) {
+          label[v] = (int32_t)ncomp;
+          queue[tail++] = v;
+        }
+      }
+    }
+    ++ncomp;
+  }
+  free(queue);
+  return ncomp;
+}
+
 /* ---- multi-source work split over threads ---------------------------------- */
 
 typedef struct {

@@ -29,7 +29,7 @@ SPACE = {
     "prefilter": [1, 0],
 }
 MS_WIDTHS = [64, 128, 256, 512]
-DEFAULTS = {"sigma": 8, "tau": 128, "wide_slices": 0, "block_size": 1024, "blocks_per_cu": 0, "prefilter": 1}
+DEFAULTS = {"sigma": 8, "tau": 128, "wide_slices": 0, "block_size": 512, "blocks_per_cu": 0, "prefilter": 1}
 
 
 def cache_key(device_name: str, family: str, n: int, m: int) -> str:

@@ -166,7 +166,7 @@ void blest_default_opts(blest_opts* o) {
   o->reorder = BLEST_REORDER_AUTO;
   o->policy = BLEST_POLICY_HEURISTIC;
   o->eta = 10.0f;
-  o->block_size = 1024;
+  o->block_size = 512;
   o->blocks_per_cu = 0;
   o->persistent = 1;
   o->wide_slices = 0;

@@ -72,7 +72,7 @@ def test_rmat_s16_all_policies(blest):
     dict(sigma=16), dict(sigma=32), dict(tau=64), dict(tau=256), dict(tau=192), dict(wide_slices=1),
     dict(block_size=256), dict(block_size=1024), dict(persistent=0), dict(prefilter=0), dict(reorder=1),
     dict(reorder=0), dict(blocks_per_cu=1), dict(sigma=16, tau=64, block_size=256, persistent=0),
-    dict(single_block=0), dict(single_block=0, block_size=512), dict(block_size=256, sigma=32),
+    dict(single_block=0), dict(single_block=0, block_size=1024), dict(block_size=256, sigma=32),
     dict(panel=0), dict(panel=2), dict(panel=2, block_size=256), dict(panel=2, persistent=0),
     dict(panel=2, blocks_per_cu=1, single_block=0),
     dict(stage2_count_first=0), dict(stage2_count_first=2), dict(stage2_count_first=2, single_block=0, panel=0),

@@ -141,3 +141,41 @@ def test_closeness_rmat18_subset(blest):
     assert np.array_equal(r.cpu().numpy(), oreach)
     assert np.array_equal(c.cpu().numpy(), occ)
     g.close()
+
+
+def _component_sizes(rp, col):
+    lab = oracle.components(rp, col)
+    return np.bincount(lab)[lab]
+
+
+@pytest.mark.parametrize("which", ["rmat18_all", "rmat23_16k"])
+def test_closeness_full_size(blest, which):
+    """The closeness workloads at full size: all 262,144 sources of scale-18
+    R-MAT, and 16,384 seeded sources of scale-23 R-MAT (512 per batch). Every
+    source's reach equals its component size, every cc is
+    (reach-1)/sum in IEEE double (0 when sum = 0), and sampled sources' sums
+    equal the oracle's. Component sizes come from the oracle's labelling."""
+    if which == "rmat18_all":
+        rp, col = inputs.rmat_graph(18, 1050)
+        srcs = np.arange(rp.size - 1, dtype=np.int32)
+        sample = srcs[::4099]
+    else:
+        rp, col = inputs.rmat_graph(23, 1052)
+        srcs = inputs.sources(rp, 16384, seed=1053)
+        sample = srcs[::2731]
+    print(f"[{which}] n={rp.size - 1} m={col.size} k={srcs.size}", flush=True)
+    g = blest.Graph(rp, col, msbfs_width=512)
+    s, r, c = g.closeness(srcs)
+    s, r, c = s.cpu().numpy(), r.cpu().numpy(), c.cpu().numpy()
+    g.close()
+    comp = _component_sizes(rp, col)
+    assert np.array_equal(r, comp[srcs])
+    assert np.array_equal(s == 0, r == 1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        want = np.where(s > 0, (r - 1).astype(np.float64) / s.astype(np.float64), 0.0)
+    assert np.array_equal(c, want)
+    idx = np.searchsorted(srcs, sample) if which == "rmat18_all" else np.array([list(srcs).index(x) for x in sample])
+    osum, oreach, occ = oracle.closeness(rp, col, sample)
+    assert np.array_equal(s[idx], osum)
+    assert np.array_equal(r[idx], oreach)
+    assert np.array_equal(c[idx], occ)

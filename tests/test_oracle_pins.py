@@ -264,6 +264,43 @@ def test_level_counts_sum_to_component():
     assert cnt[0] == 1 and cnt.sum() == (lev >= 0).sum() and (cnt > 0).all()
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_components_match_union_find_and_scipy(seed):
+    # union-find written here on the edge list, and scipy's BFS labelling
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 400))
+    k = int(rng.integers(0, n))
+    rp, col = inputs.from_pairs(n, rng.integers(0, n, k), rng.integers(0, n, k))
+    lab = oracle.components(rp, col)
+    parent = list(range(n))
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+    for u in range(n):
+        for v in col[rp[u]:rp[u + 1]]:
+            parent[find(u)] = find(int(v))
+    roots = [find(u) for u in range(n)]
+    for u in range(n):
+        for v in range(0, n, 7):
+            assert (lab[u] == lab[v]) == (roots[u] == roots[v])
+    # numbered by smallest vertex
+    first = {}
+    for u in range(n):
+        first.setdefault(lab[u], u)
+    assert [first[i] for i in range(len(first))] == sorted(first.values())
+    ncomp, slab = connected_components(csr_matrix((np.ones(col.size), col, rp), shape=(n, n)), directed=False)
+    assert lab.max() + 1 == ncomp
+    # reach of each vertex = its component size (closeness's reach)
+    sizes = np.bincount(lab)[lab]
+    _, reach, _ = oracle.closeness(rp, col, np.arange(n, dtype=np.int32))
+    assert np.array_equal(reach, sizes)
+
+
 # ---------------------------------------------------------------------- MLP
 
 def _rand_params(seed, scale=0.3):
