@@ -116,8 +116,11 @@ def cpu_baseline(rp, col, srcs, budget_s=20.0):
             "sample": f"{len(times)} of the {len(srcs)} R-MAT scale-22 sources, FIFO-queue BFS on one host thread"}
 
 
+# The persistent kernel and what fixes its launch (block size, panel layout):
+# a counter summary taken on other versions of these files is not reported.
 KERNEL_SOURCES = ["paper_2606_05081_amd/csrc/bfs.hip", "paper_2606_05081_amd/csrc/device_common.h",
-                  "paper_2606_05081_amd/csrc/blest_internal.h"]
+                  "paper_2606_05081_amd/csrc/blest_internal.h", "paper_2606_05081_amd/csrc/api.cpp",
+                  "paper_2606_05081_amd/csrc/host_build.cpp"]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_bfs_persistent_rmat22_bvss_traffic.txt")
 
 
