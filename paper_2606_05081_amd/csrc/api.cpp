@@ -300,7 +300,8 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   // pointers can be read with aligned 16-byte loads.
   const size_t rp_len = static_cast<size_t>(b.nsets) * o.sigma + 1;
   TRY(dalloc_t(g, &d.rp, rp_len + 4));
-  TRY(dalloc_t(g, &d.col, static_cast<size_t>(std::max<int64_t>(m, 1))));
+  // col is padded by 4 entries: the bottom-up engine reads 4 neighbours at a time
+  TRY(dalloc_t(g, &d.col, static_cast<size_t>(m) + 4));
   TRY(dalloc_t(g, &d.slice_ptr, ns + 1));
   TRY(dalloc(g, &d.slices, static_cast<size_t>(std::max<int64_t>(b.nslices, 1)) * (wide ? 8 : 4)));
   TRY(dalloc(g, &d.degmask, ns * mb));

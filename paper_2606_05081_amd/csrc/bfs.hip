@@ -574,10 +574,14 @@ __device__ __attribute__((noinline)) long long engine_pull(const BfsArgs& a, lon
       const int p0 = p;
       bool found = false;
       for (; p < e && !found; p += 4) {
-        const int v0 = col[p];
-        const int v1 = p + 1 < e ? col[p + 1] : v0;
-        const int v2 = p + 2 < e ? col[p + 2] : v0;
-        const int v3 = p + 3 < e ? col[p + 3] : v0;
+        // one 16-byte load of 4 neighbours (col is padded by 4 entries, so
+        // the load stays in bounds at the end of the array)
+        int q[4];
+        __builtin_memcpy(q, reinterpret_cast<const int32_t*>(col + p), sizeof(q));
+        const int v0 = q[0];
+        const int v1 = p + 1 < e ? q[1] : v0;
+        const int v2 = p + 2 < e ? q[2] : v0;
+        const int v3 = p + 3 < e ? q[3] : v0;
         found = ((front[v0 / SIGMA] >> (v0 % SIGMA)) & 1u) | ((front[v1 / SIGMA] >> (v1 % SIGMA)) & 1u) |
                 ((front[v2 / SIGMA] >> (v2 % SIGMA)) & 1u) | ((front[v3 / SIGMA] >> (v3 % SIGMA)) & 1u);
       }
