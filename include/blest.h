@@ -207,6 +207,8 @@ typedef struct {
   int32_t bvss_panel;   /* 1 if the BVSS step read the panel-blocked copy (all slices, LDS marks) */
   int64_t work;         /* adjacency entries read by the step's engine: slices (BVSS),
                            CSR edges (push, bottom-up); probe mode: all three engines */
+  double t_count_us;    /* grid levels: time from the step's start until Stage 2's statistics
+                           were known (before any list emission); 0 for one-workgroup levels */
 } blest_level_stat;
 
 /* Copies up to cap records of the last BFS to buf (host); *nlevels = number

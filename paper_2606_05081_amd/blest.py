@@ -91,7 +91,8 @@ class LevelStat(ctypes.Structure):
                 ("unvisited", ctypes.c_int64), ("unvisited_edges", ctypes.c_int64), ("deg_ge_32", ctypes.c_int64),
                 ("deg_ge_1024", ctypes.c_int64), ("t_step_us", ctypes.c_double), ("t_stage1_us", ctypes.c_double),
                 ("t_engine_us", ctypes.c_double * 3),
-                ("mlp_fallback", ctypes.c_int32), ("bvss_panel", ctypes.c_int32), ("work", ctypes.c_int64)]
+                ("mlp_fallback", ctypes.c_int32), ("bvss_panel", ctypes.c_int32), ("work", ctypes.c_int64),
+                ("t_count_us", ctypes.c_double)]
 
 
 # Every exported symbol of the C ABI: name -> (restype, argtypes).

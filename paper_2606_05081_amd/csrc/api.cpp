@@ -455,6 +455,7 @@ blest_status blest_last_level_stats(const blest_graph* g, blest_level_stat* buf,
     o.deg_ge_1024 = r.deg1024;
     o.t_step_us = r.t_end > r.t_begin ? (r.t_end - r.t_begin) * g->d.tick_us : 0.0;
     o.t_stage1_us = r.t_mid > r.t_begin ? (r.t_mid - r.t_begin) * g->d.tick_us : 0.0;
+    o.t_count_us = r.t_count > r.t_begin ? (r.t_count - r.t_begin) * g->d.tick_us : 0.0;
     for (int e = 0; e < 3; ++e) o.t_engine_us[e] = r.t_engine[e] ? r.t_engine[e] * g->d.tick_us : -1.0;
     o.mlp_fallback = r.fallback;
     o.bvss_panel = r.panel;

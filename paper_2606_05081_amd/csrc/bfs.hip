@@ -1126,6 +1126,7 @@ __device__ __forceinline__ void log_level(const BfsArgs& a, int level, const Lev
   r.t_begin = dev_ticks();
   r.t_mid = 0;
   r.t_end = 0;
+  r.t_count = 0;
   r.t_engine[0] = r.t_engine[1] = r.t_engine[2] = 0;
   r.work = 0;
 #pragma unroll
@@ -1306,6 +1307,7 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
       nv.cumv = v.cumv + tot[0];
       nv.cume = v.cume + tot[2];
       if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (level < a.log_cap) a.log[level].t_count = dev_ticks();
         // the level's counters, for a single-workgroup episode that may follow
         unsigned long long* acc = &a.ctl->acc[(level + 1) % kStatSlots][0][0];
         const long long vals[10] = {nv.frontier, nv.queue, nv.qslices, nv.fedges, nv.deg32,

@@ -71,6 +71,7 @@ struct LevelRec {
   unsigned long long t_begin;     // device clock (100 MHz) when the step started
   unsigned long long t_mid;       // ... when Stage 1 ended (after its barrier)
   unsigned long long t_end;       // ... when its finalisation ended
+  unsigned long long t_count;     // ... when Stage 2's statistics were known (grid levels)
   unsigned long long t_engine[3]; // probe mode: ticks of each engine
   int engine;
   int fallback;

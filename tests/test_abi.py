@@ -43,7 +43,7 @@ def test_status_strings_and_defaults():
     assert (o.sigma, o.tau, o.eta, o.policy, o.persistent, o.msbfs_width) == (8, 128, 10.0, 0, 1, 512)
     # layout of blest_opts in include/blest.h: 12 int32/float fields, a uint64, an int32, int32[7]
     assert ctypes.sizeof(blest.Opts) == 88 and blest.Opts.random_seed.offset == 48
-    assert ctypes.sizeof(blest.LevelStat) == 8 + 8 * 8 + 16 + 24 + 8 + 8
+    assert ctypes.sizeof(blest.LevelStat) == 8 + 8 * 8 + 16 + 24 + 8 + 8 + 8
     assert ctypes.sizeof(blest.GraphStats) == 16 + 16 + 48 + 12 + 20
 
 
