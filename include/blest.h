@@ -99,7 +99,7 @@ typedef struct {
   int32_t panel;        /* panel-blocked BVSS copy for dense top-down levels (sigma = 8, 32-bit
                            slices only): 0 = not built, 1 (default) = used when the queued slices
                            are at least an eighth of all slices, 2 = used at every BVSS level */
-  int32_t panel_log2_rows; /* rows per panel = 2^this, in [5, 16]; 0 (default) = about one panel
+  int32_t panel_log2_rows; /* rows per panel = 2^this, in [5, 15]; 0 (default) = about one panel
                               per persistent workgroup */
   int32_t stage2_count_first; /* Stage 2 of a grid level either builds the frontier lists in the same
                                  pass as the visited update, or counts first and writes the lists

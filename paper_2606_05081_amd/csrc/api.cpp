@@ -201,8 +201,8 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   if (o.panel < 0 || o.panel > 2) return fail(BLEST_ERR_INVALID_ARG, "panel must be 0, 1 or 2");
   if (o.stage2_count_first < 0 || o.stage2_count_first > 2)
     return fail(BLEST_ERR_INVALID_ARG, "stage2_count_first must be 0, 1 or 2");
-  if (o.panel_log2_rows != 0 && (o.panel_log2_rows < 5 || o.panel_log2_rows > 16))
-    return fail(BLEST_ERR_UNSUPPORTED, "panel_log2_rows must be 0 (auto) or in [5, 16]");
+  if (o.panel_log2_rows != 0 && (o.panel_log2_rows < 5 || o.panel_log2_rows > 15))
+    return fail(BLEST_ERR_UNSUPPORTED, "panel_log2_rows must be 0 (auto) or in [5, 15]");
   const int64_t n = csr->n, m = csr->m;
   std::string why;
   if (!blest::validate_csr(n, m, csr->row_ptr, csr->col_idx, &why)) return fail(BLEST_ERR_INVALID_GRAPH, why);

@@ -321,19 +321,19 @@ __device__ long long engine_bvss(const BfsArgs& a, const uint4* __restrict__ q, 
 // panel: 256 slice words, one 16-byte load per lane, plus the chunk's
 // 512-byte window of frontier words (one 8-byte load per lane); a lane finds
 // the frontier word of each of its slices' sets in the window by two wave
-// shuffles. A slice hits when its mask meets that word, and the hit row's bit
-// is set in an LDS bitmap with an LDS atomic. Loads of the next batch of
-// chunks are issued before the current batch is tested. After the panel, the
-// bitmap minus the visited words is written to the mark bytes, 32 rows per
-// pair of 16-byte stores; the workgroup owns those rows, so each new vertex
-// is written once and no visited word is read per hit.
-// Frontier words of sets with no new vertex are stale (they keep an older
-// frontier); their extra hits land on visited rows and are dropped at the
-// flush. pm: LDS scratch of at least 2^(rb-5) words, left filled with ones
-// (the single-workgroup hash set shares it).
+// shuffles. A slice hits when its mask meets that word, and the hit row's
+// byte in an LDS byte map is set with a plain store (lazy marking is
+// idempotent, so no atomic is needed). Loads of the next batch of chunks are
+// issued before the current batch is tested. After the panel, the byte map
+// minus the visited words is written to the mark bytes, 32 rows per pair of
+// 16-byte stores; the workgroup owns those rows, so each new vertex is
+// written once and no visited word is read per hit.
+// pm: LDS scratch of at least 2^rb bytes, left filled with ones (the
+// single-workgroup hash set shares it).
 constexpr int kPanelChunk = 256;      // slices per chunk (host layout)
-constexpr int kPanelUnroll = 4;       // chunks per wave per batch
-constexpr int kPanelMaxWords = 2048;  // rb <= 16
+constexpr int kPanelUnroll = 8;       // chunks per wave per batch
+constexpr int kPanelMaxBytes = 1 << 15;  // LDS byte map of one panel (rb <= 15)
+static_assert(kSingleHash * 4 >= kPanelMaxBytes, "the panel byte map lives in the hash-set slots");
 constexpr long long kPanelDenom = 8;  // dense: queued slices >= panel slots / 8
 
 __device__ __forceinline__ bool use_panel(const BfsArgs& a, const LevelView& v) {
@@ -373,10 +373,7 @@ __device__ __forceinline__ void panel_test4(const uint4& w, uint32_t b7, const u
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const uint32_t al = (((d[q] >> 2) & 1u) ? hi[q] : lo[q]) >> (8u * (d[q] & 3u));
-    if (s[q] & al & 0xffu) {
-      const uint32_t r = s[q] >> rshift;
-      __hip_atomic_fetch_or(pm + (r >> 5), 1u << (r & 31u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
+    if (s[q] & al & 0xffu) reinterpret_cast<lptr<uint8_t>>(pm)[s[q] >> rshift] = 1;
   }
 }
 
@@ -387,7 +384,9 @@ __device__ __attribute__((noinline)) long long engine_panel(const BfsArgs& a, lp
   constexpr uint32_t STEP = NW * U;
   const int rb = a.panel_rb;
   const int npanels = a.npanels;
-  const uint32_t W = 1u << (rb - 5);
+  const uint32_t W = 1u << (rb - 5);  // 32-row groups per panel
+  const lptr<u32x4> pm16 = reinterpret_cast<lptr<u32x4>>(pm);
+  const lptr<const unsigned long long> pm64 = reinterpret_cast<lptr<const unsigned long long>>(pm);
   const uint32_t dmask = (1u << (24 - rb)) - 1u;
   const int rshift = 32 - rb;
   PanelPtrs pp;
@@ -401,7 +400,7 @@ __device__ __attribute__((noinline)) long long engine_panel(const BfsArgs& a, lp
   const uint32_t wv = static_cast<uint32_t>(wave_in_block());
   long long work = 0;
   for (int p = blockIdx.x; p < npanels; p += gridDim.x) {
-    for (uint32_t j = threadIdx.x; j < W; j += BLOCK) pm[j] = 0u;
+    for (uint32_t j = threadIdx.x; j < 2 * W; j += BLOCK) pm16[j] = u32x4{0u, 0u, 0u, 0u};
     __syncthreads();
     const uint32_t c0 = pptr[p], c1 = pptr[p + 1];
     const uint32_t cl = c1 - 1;  // used only when the panel has a chunk (c < c1)
@@ -453,7 +452,8 @@ __device__ __attribute__((noinline)) long long engine_panel(const BfsArgs& a, lp
     __syncthreads();
     const size_t wb = static_cast<size_t>(p) * W;
     for (uint32_t j = threadIdx.x; j < W; j += BLOCK) {
-      const uint32_t m = pm[j];
+      const uint32_t m = gather8(pm64[4 * j]) | (gather8(pm64[4 * j + 1]) << 8) | (gather8(pm64[4 * j + 2]) << 16) |
+                         (gather8(pm64[4 * j + 3]) << 24);
       if (!m) continue;
       const uint32_t x = m & ~vis32[wb + j];
       if (!x) continue;
@@ -468,7 +468,7 @@ __device__ __attribute__((noinline)) long long engine_panel(const BfsArgs& a, lp
     }
     __syncthreads();
   }
-  for (uint32_t j = threadIdx.x; j < W; j += BLOCK) pm[j] = 0xffffffffu;
+  for (uint32_t j = threadIdx.x; j < 8 * W; j += BLOCK) pm[j] = 0xffffffffu;
   return lane == 0 ? work : 0;
 }
 
@@ -1179,7 +1179,7 @@ __device__ int single_episode(const BfsArgs& a, int level, int engine, int fallb
 template <int SIGMA, class SliceT, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
   extern __shared__ float s_mlp[];
-  __shared__ int hs[kSingleLds];
+  __shared__ __attribute__((aligned(16))) int hs[kSingleLds];
   __shared__ int s_level;
   const unsigned nblocks = gridDim.x;
   const long long nthreads = static_cast<long long>(nblocks) * BLOCK;
@@ -1395,7 +1395,7 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_stage1(BfsArgs a, int level, long
     const int nslot = (level + 1) % kStatSlots;
     for (int t = threadIdx.x; t < kStatFields; t += BLOCK) a.ctl->acc[nslot][t][0] = 0ULL;
   }
-  __shared__ uint32_t pm[kPanelMaxWords];
+  __shared__ __attribute__((aligned(16))) uint32_t pm[kPanelMaxBytes / 4];
   run_engine<SIGMA, SliceT, BLOCK>(a, engine, level & 1, level % kStatSlots, v, gtid, nthreads, gwave, nwaves, nullptr,
                                    to_lds(pm));
 }

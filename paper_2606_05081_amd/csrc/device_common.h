@@ -66,6 +66,7 @@ __device__ __forceinline__ gptr<T> to_global(T* p) {
   return (gptr<T>)p;
 }
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Same for LDS: pointers into a __shared__ array handed to a function that is
 // not inlined stay ds_* accesses.

@@ -295,11 +295,11 @@ int panel_log2_rows(int64_t n, int64_t workgroups) {
   const int64_t rows = (n + std::max<int64_t>(workgroups, 1) - 1) / std::max<int64_t>(workgroups, 1);
   int lg = 0;
   while ((int64_t(1) << lg) < rows) ++lg;
-  return std::max(5, std::min(16, lg));
+  return std::max(5, std::min(15, lg));
 }
 
 bool build_panels(int64_t n, const Bvss& b, int rb, Panels* out) {
-  if (b.wide || b.nslices == 0 || n > (int64_t(1) << 24) || rb < 5 || rb > 16) return false;
+  if (b.wide || b.nslices == 0 || n > (int64_t(1) << 24) || rb < 5 || rb > 15) return false;
   const int rshift = 32 - rb;
   const uint32_t dlim = std::min<uint32_t>(1u << (24 - rb), 505u);
   const int64_t np = (n + (int64_t(1) << rb) - 1) >> rb;

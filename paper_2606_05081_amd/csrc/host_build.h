@@ -51,10 +51,10 @@ struct Panels {
 };
 
 // log2 of the panel height for an n-vertex graph traversed by `workgroups`
-// persistent workgroups: about one panel per workgroup, within [5, 16].
+// persistent workgroups: about one panel per workgroup, within [5, 15].
 int panel_log2_rows(int64_t n, int64_t workgroups);
 
-// rb = log2 rows per panel, in [5, 16]. Returns false (and builds nothing)
+// rb = log2 rows per panel, in [5, 15]. Returns false (and builds nothing)
 // for 64-bit slices, an empty BVSS or n > 2^24.
 bool build_panels(int64_t n, const Bvss& b, int rb, Panels* out);
 
