@@ -320,7 +320,32 @@ def main():
         ms_ms = e0.elapsed_time(e1)
         extras["msbfs_sources_per_s"] = round(960 / ms_ms * 1e3, 1)
         extras["msbfs_ms"] = round(ms_ms, 3)
+        per_width = {}
+        for w in (64, 128, 256, 512):  # each batch width alone over the same 960 sources
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            mg.msbfs_batched(msrcs, [w], mout)
+            e1.record()
+            mg.sync()
+            torch.cuda.synchronize()
+            per_width[str(w)] = round(960 / e0.elapsed_time(e1) * 1e3, 1)
+        extras["msbfs_sources_per_s_by_width"] = per_width
         mg.close()
+        # small single-source case: R-MAT scale 16, plain method and Eq. 3
+        srp, scol = inputs.rmat_graph(16, 1010)
+        ss = inputs.sources(srp, 64, seed=1011)
+        sg = blest.Graph(srp, scol, device=0, **{"async": 1})
+        sout = torch.empty(sg.n, dtype=torch.int32, device=dev)
+        sedges = []
+        for s in ss:
+            sg.bfs(int(s), sout)
+            sg.sync()
+            sedges.append(traversal_edges(srp, sout.cpu().numpy()))
+        for name, pol in (("rmat16_plain_gteps", blest.Policy.BVSS), ("rmat16_heuristic_gteps", blest.Policy.HEURISTIC)):
+            sg.set_policy(pol)
+            timed_sources(sg, ss, sout, torch)
+            extras[name] = round(harmonic_gteps(sedges, timed_sources(sg, ss, sout, torch)), 3)
+        sg.close()
         # exact closeness: all sources of scale-18 R-MAT, 16,384 sources of scale-23 R-MAT (512 per batch)
         for tag, scale, gseed, k in (("closeness_rmat18_all", 18, 1050, None), ("closeness_rmat23_16k", 23, 1052, 16384)):
             crp, ccol = inputs.rmat_graph(scale, gseed)
