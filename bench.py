@@ -331,6 +331,18 @@ def main():
             per_width[str(w)] = round(960 / e0.elapsed_time(e1) * 1e3, 1)
         extras["msbfs_sources_per_s_by_width"] = per_width
         mg.close()
+        # the same 960 sources with the levels as a replayed hipGraph of per-phase kernels
+        gmg = blest.Graph(mrp, mcol, device=0, msbfs_graph=1, **{"async": 1})
+        gmg.msbfs_batched(msrcs, [64, 128, 256, 512], mout)
+        gmg.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        gmg.msbfs_batched(msrcs, [64, 128, 256, 512], mout)
+        e1.record()
+        gmg.sync()
+        torch.cuda.synchronize()
+        extras["msbfs_graph_sources_per_s"] = round(960 / e0.elapsed_time(e1) * 1e3, 1)
+        gmg.close()
         # small single-source case: R-MAT scale 16, plain method and Eq. 3
         srp, scol = inputs.rmat_graph(16, 1010)
         ss = inputs.sources(srp, 64, seed=1011)

@@ -107,7 +107,10 @@ typedef struct {
                                  barrier then). 0: same pass always; 1 (default): count first after a
                                  bottom-up or panel step or a frontier of mean degree >= 8; 2: count
                                  first always */
-  int32_t reserved[3];
+  int32_t msbfs_graph;  /* 1: multi-source BFS and closeness run as a hipGraph of per-phase kernels
+                           (batch set-up, each level's engine and Stage 2, batch reduction),
+                           replayed until done, instead of one persistent launch (default 0) */
+  int32_t reserved[2];
 } blest_opts;
 
 /* Fills *opts with the defaults listed above. */

@@ -73,7 +73,8 @@ class Opts(ctypes.Structure):
                 ("prefilter", ctypes.c_int32), ("async_", ctypes.c_int32), ("msbfs_width", ctypes.c_int32),
                 ("random_seed", ctypes.c_uint64), ("device", ctypes.c_int32), ("single_block", ctypes.c_int32),
                 ("panel", ctypes.c_int32), ("panel_log2_rows", ctypes.c_int32),
-                ("stage2_count_first", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("stage2_count_first", ctypes.c_int32), ("msbfs_graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class GraphStats(ctypes.Structure):

@@ -199,6 +199,7 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   if (o.msbfs_width != 64 && o.msbfs_width != 128 && o.msbfs_width != 256 && o.msbfs_width != 512)
     return fail(BLEST_ERR_UNSUPPORTED, "msbfs_width must be 64, 128, 256 or 512");
   if (o.panel < 0 || o.panel > 2) return fail(BLEST_ERR_INVALID_ARG, "panel must be 0, 1 or 2");
+  if (o.msbfs_graph < 0 || o.msbfs_graph > 1) return fail(BLEST_ERR_INVALID_ARG, "msbfs_graph must be 0 or 1");
   if (o.stage2_count_first < 0 || o.stage2_count_first > 2)
     return fail(BLEST_ERR_INVALID_ARG, "stage2_count_first must be 0, 1 or 2");
   if (o.panel_log2_rows != 0 && (o.panel_log2_rows < 5 || o.panel_log2_rows > 15))
@@ -579,7 +580,7 @@ blest_status blest_msbfs(blest_graph* g, const int32_t* srcs, int32_t k, int16_t
     for (auto& s : internal) s = g->perm[s];
   const int32_t w = g->opts.msbfs_width;
   hipError_t e = blest::ms_run(g->d, &g->ms, internal.data(), k, &w, 1, g->opts.policy, g->opts.eta,
-                               g->opts.random_seed, levels_dev, nullptr, nullptr, nullptr, st);
+                               g->opts.random_seed, levels_dev, nullptr, nullptr, nullptr, st, g->opts.msbfs_graph);
   if (e != hipSuccess) return hip_fail(e, "msbfs");
   if (g->opts.async) return BLEST_OK;
   return wait_and_check(g, st);
@@ -602,7 +603,7 @@ blest_status blest_msbfs_batched(blest_graph* g, const int32_t* srcs, int32_t k,
   if (!g->perm.empty())
     for (auto& s : internal) s = g->perm[s];
   hipError_t e = blest::ms_run(g->d, &g->ms, internal.data(), k, widths, nwidths, g->opts.policy, g->opts.eta,
-                               g->opts.random_seed, levels_dev, nullptr, nullptr, nullptr, st);
+                               g->opts.random_seed, levels_dev, nullptr, nullptr, nullptr, st, g->opts.msbfs_graph);
   if (e != hipSuccess) return hip_fail(e, "msbfs");
   if (g->opts.async) return BLEST_OK;
   return wait_and_check(g, st);
@@ -623,7 +624,8 @@ blest_status blest_closeness(blest_graph* g, const int32_t* srcs, int64_t k, int
     for (auto& s : internal) s = g->perm[s];
   const int32_t w = g->opts.msbfs_width;
   hipError_t e = blest::ms_run(g->d, &g->ms, internal.data(), static_cast<int32_t>(k), &w, 1, g->opts.policy,
-                               g->opts.eta, g->opts.random_seed, nullptr, sums_dev, reach_dev, cc_dev, st);
+                               g->opts.eta, g->opts.random_seed, nullptr, sums_dev, reach_dev, cc_dev, st,
+                               g->opts.msbfs_graph);
   if (e != hipSuccess) return hip_fail(e, "closeness");
   if (g->opts.async) return BLEST_OK;
   return wait_and_check(g, st);

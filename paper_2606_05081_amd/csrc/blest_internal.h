@@ -62,6 +62,7 @@ struct alignas(256) Ctl {
   int single_level[kPad];          // first level after a single-workgroup episode
   unsigned int single_gen[kPad];   // number of finished single-workgroup episodes
   int nlevels[kPad * 2]; // frontier levels of the last traversal
+  int ms_state[2][kPad];   // multi-source graph mode: {phase, batch, level} read by even/odd kernels
 };
 
 // One record per frontier level, written by workgroup 0 of the persistent kernel.

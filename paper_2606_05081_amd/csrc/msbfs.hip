@@ -493,6 +493,165 @@ __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
   }
 }
 
+// ------------------------------------------------ hipGraph-captured levels
+//
+// The same traversal as k_ms_persistent, cut into one kernel per grid-wide
+// phase so that a fixed sequence of launches can be captured in a hipGraph
+// and replayed: the kernel's work is chosen by a state {phase, batch, level}
+// in the control block. Kernel i of a graph reads state slot i % 2 and
+// workgroup 0 writes the next state to the other slot (the next kernel starts
+// only after every workgroup of this one has finished, so no workgroup reads a
+// slot while it is being written). After the last batch the phase is
+// MS_DONE and the remaining kernels of a replay do nothing.
+enum MsPhase : int { MS_INIT = 0, MS_SEED = 1, MS_FIN0 = 2, MS_ENGINE = 3, MS_FIN = 4, MS_END = 5, MS_DONE = 6 };
+constexpr int kMsGraphKernels = 32;  // kernels per captured graph (even)
+
+template <int SIGMA, class SliceT, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_ms_phase(MsArgs a, int parity) {
+  __shared__ unsigned long long lds_f[(BLOCK / 64) * SIGMA * kWMax];
+  __shared__ int lds_cnt[64 * kWMax];
+  const int phase = a.ctl->ms_state[parity][0];
+  const int bi = a.ctl->ms_state[parity][1];
+  const int level = a.ctl->ms_state[parity][2];
+  int next[3] = {MS_DONE, bi, level};
+  if (phase != MS_DONE) {
+    const long long nthreads = static_cast<long long>(gridDim.x) * BLOCK;
+    const long long gtid = static_cast<long long>(blockIdx.x) * BLOCK + threadIdx.x;
+    const int wave = wave_in_block();
+    const long long gwave = static_cast<long long>(blockIdx.x) * (BLOCK / 64) + wave;
+    const long long nwaves = static_cast<long long>(gridDim.x) * (BLOCK / 64);
+    unsigned long long* my_f = lds_f + wave * SIGMA * kWMax;
+    const long long rho = a.nsets;
+    const long long nhat = a.nsets * SIGMA;
+    const bool count_sources = a.sums != nullptr || a.reach != nullptr || a.cc != nullptr;
+    for (int q = threadIdx.x; q < 64 * kWMax; q += BLOCK) lds_cnt[q] = 0;
+    __syncthreads();
+    const MsBatch bt = a.batches[bi];
+    const int W = bt.W;
+    switch (phase) {
+      case MS_INIT:
+        for (long long i = gtid; i < nhat * W; i += nthreads) {
+          a.F[i] = 0ULL;
+          a.V[i] = 0ULL;
+        }
+        if (a.levels16) fill_minus_one(a.levels16 + static_cast<long long>(bt.offset) * a.n,
+                                       static_cast<long long>(bt.count) * a.n, gtid, nthreads);
+        if (count_sources) {
+          long long* part = a.part + static_cast<long long>(blockIdx.x) * (2 * 64 * kWMax);
+          for (int q = threadIdx.x; q < 2 * 64 * kWMax; q += BLOCK) part[q] = 0;
+        }
+        if (blockIdx.x == 0)
+          for (int t = threadIdx.x; t < kStatSlots * kStatFields; t += BLOCK)
+            a.ctl->acc[t / kStatFields][t % kStatFields][0] = 0ULL;
+        next[0] = MS_SEED;
+        break;
+      case MS_SEED:
+        for (long long q = gtid; q < bt.count; q += nthreads) {
+          const long long u = a.srcs[bt.offset + q];
+          const long long vi = get_vi(u, rho, SIGMA);
+          __hip_atomic_fetch_or(&a.N[vi * W + q / 64], 1ULL << (q % 64), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          a.dirty[u / SIGMA] = 1;
+        }
+        next[0] = MS_FIN0;
+        break;
+      case MS_FIN0:
+        ms_finalize<SIGMA, BLOCK>(a, bt, 0, 0, 0, 0, lds_cnt, count_sources);
+        next[0] = MS_ENGINE;
+        next[2] = 0;
+        break;
+      case MS_ENGINE: {
+        const unsigned long long* accr = &a.ctl->acc[level % kStatSlots][0][0];
+        const long long fresh = static_cast<long long>(accr[F_FRONTIER * kPad]);
+        if (fresh == 0) {
+          next[0] = MS_END;
+          break;
+        }
+        const long long qlen = static_cast<long long>(accr[F_QUEUE * kPad]);
+        const long long cumv = static_cast<long long>(accr[F_CUMV * kPad]);
+        const long long pairs_total = static_cast<long long>(bt.count) * a.n;
+        int engine;
+        switch (a.policy) {
+          case BLEST_POLICY_BVSS:
+          case BLEST_POLICY_PUSH:
+            engine = BLEST_ENGINE_BVSS;
+            break;
+          case BLEST_POLICY_BOTTOM_UP:
+            engine = BLEST_ENGINE_BOTTOM_UP;
+            break;
+          case BLEST_POLICY_RANDOM:
+            engine = (mix64_ms(a.seed + 0x9E3779B97F4A7C15ULL * static_cast<unsigned long long>(level + 1 + 977 * bi)) &
+                      1ULL)
+                         ? BLEST_ENGINE_BOTTOM_UP
+                         : BLEST_ENGINE_BVSS;
+            break;
+          default:
+            engine = (static_cast<double>(pairs_total - cumv) < static_cast<double>(a.eta) * static_cast<double>(qlen))
+                         ? BLEST_ENGINE_BOTTOM_UP
+                         : BLEST_ENGINE_BVSS;
+            break;
+        }
+        if (blockIdx.x == 0) {
+          const int nslot = (level + 1) % kStatSlots;
+          for (int t = threadIdx.x; t < kStatFields; t += BLOCK) a.ctl->acc[nslot][t][0] = 0ULL;
+        }
+        if (engine == BLEST_ENGINE_BVSS)
+          ms_engine_bvss<SIGMA, SliceT>(a, a.queue[level & 1], qlen, W, gwave, nwaves, my_f);
+        else
+          ms_engine_pull<SIGMA>(a, W, bt.count, gtid, nthreads);
+        next[0] = MS_FIN;
+        break;
+      }
+      case MS_FIN: {
+        const long long cumv = static_cast<long long>(a.ctl->acc[level % kStatSlots][F_CUMV][0]);
+        ms_finalize<SIGMA, BLOCK>(a, bt, level + 1, (level + 1) % kStatSlots, (level & 1) ^ 1, cumv, lds_cnt,
+                                  count_sources);
+        next[0] = MS_ENGINE;
+        next[2] = level + 1;
+        break;
+      }
+      default:  // MS_END
+        if (count_sources) {
+          for (long long q = gtid; q < bt.count; q += nthreads) {
+            long long su = 0, re = 0;
+            for (unsigned blk = 0; blk < gridDim.x; ++blk) {
+              const long long* part = a.part + static_cast<long long>(blk) * (2 * 64 * kWMax);
+              su += part[q];
+              re += part[64 * kWMax + q];
+            }
+            const long long row = bt.offset + q;
+            if (a.sums) a.sums[row] = su;
+            if (a.reach) a.reach[row] = re;
+            if (a.cc) a.cc[row] = su ? static_cast<double>(re - 1) / static_cast<double>(su) : 0.0;
+          }
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0 && level > a.ctl->nlevels[0]) a.ctl->nlevels[0] = level;
+        next[0] = bi + 1 < a.nbatches ? MS_INIT : MS_DONE;
+        next[1] = bi + 1;
+        next[2] = 0;
+        break;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ctl->ms_state[parity ^ 1][0] = next[0];
+    a.ctl->ms_state[parity ^ 1][1] = next[1];
+    a.ctl->ms_state[parity ^ 1][2] = next[2];
+  }
+}
+
+__global__ void k_ms_start(Ctl* ctl) {
+  if (threadIdx.x == 0) {
+    ctl->ms_state[0][0] = MS_INIT;
+    ctl->ms_state[0][1] = 0;
+    ctl->ms_state[0][2] = 0;
+    ctl->nlevels[0] = 0;
+  }
+}
+
+template <int SIGMA, class SliceT>
+const void* ms_phase_fn() {
+  return reinterpret_cast<const void*>(&k_ms_phase<SIGMA, SliceT, 512>);
+}
+
 template <int SIGMA, class SliceT, int BLOCK>
 const void* ms_fn() {
   return reinterpret_cast<const void*>(&k_ms_persistent<SIGMA, SliceT, BLOCK>);
@@ -579,7 +738,7 @@ hipError_t ensure(const DevGraph& g, MsDev* ms, int wmax, int32_t k, int nbatche
 
 hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, const int32_t* widths, int nwidths,
                   int policy, float eta, uint64_t seed, int16_t* levels16, int64_t* sums, int64_t* reach, double* cc,
-                  hipStream_t st) {
+                  hipStream_t st, int graph) {
   if (k <= 0) return hipSuccess;
   std::vector<MsBatch> plan;
   int32_t off = 0;
@@ -630,8 +789,60 @@ hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, 
   a.eta = eta;
   a.seed = seed;
   a.timeout_ticks = 3000000000ULL;  // 30 s
-  void* args[] = {static_cast<void*>(&a)};
-  return hipLaunchCooperativeKernel(ms_kernel(g), dim3(ms->grid), dim3(ms->block), args, 0, st);
+  if (!graph) {
+    void* args[] = {static_cast<void*>(&a)};
+    return hipLaunchCooperativeKernel(ms_kernel(g), dim3(ms->grid), dim3(ms->block), args, 0, st);
+  }
+  // Graph mode: capture kMsGraphKernels phase kernels plus a copy of the state
+  // and error words to pinned host memory on a stream of our own (the caller's
+  // may be the null stream, which cannot be captured), ordered after the
+  // caller's stream by an event; replay until the state says MS_DONE.
+  if (!ms->gstream) {
+    if ((e = hipStreamCreateWithFlags(&ms->gstream, hipStreamNonBlocking)) != hipSuccess) return e;
+    for (int i = 0; i < 2; ++i)
+      if ((e = hipEventCreateWithFlags(&ms->gev[i], hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  const void* fn = (g.sigma == 8 && !g.wide) ? ms_phase_fn<8, uint32_t>()
+                   : g.sigma == 8            ? ms_phase_fn<8, uint64_t>()
+                   : g.sigma == 16           ? ms_phase_fn<16, uint64_t>()
+                                             : ms_phase_fn<32, uint64_t>();
+  hipStream_t gs = ms->gstream;
+  if ((e = hipEventRecord(ms->gev[0], st)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(gs, ms->gev[0], 0)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ms_start, dim3(1), dim3(64), 0, gs, g.ctl);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  int* flags = g.host_flags;
+  hipGraph_t graph_h = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if ((e = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+  int par[kMsGraphKernels];
+  void* kargs[kMsGraphKernels][2];
+  for (int i = 0; i < kMsGraphKernels; ++i) {
+    par[i] = i & 1;
+    kargs[i][0] = static_cast<void*>(&a);
+    kargs[i][1] = static_cast<void*>(&par[i]);
+    (void)hipLaunchKernel(fn, dim3(ms->grid), dim3(kMsBlock), kargs[i], 0, gs);
+  }
+  (void)hipMemcpyAsync(flags + 2, &g.ctl->ms_state[0][0], sizeof(int), hipMemcpyDeviceToHost, gs);
+  (void)hipMemcpyAsync(flags + 3, &g.ctl->error[0], sizeof(int), hipMemcpyDeviceToHost, gs);
+  e = hipStreamEndCapture(gs, &graph_h);
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph_h, nullptr, nullptr, 0);
+  // every batch has at most 3 + 2 * 32768 + 1 phases (levels are int16)
+  const long long max_replays = static_cast<long long>(nplan) * (2LL * 32768 + 4) / kMsGraphKernels + 2;
+  for (long long r = 0; e == hipSuccess; ++r) {
+    if (r >= max_replays) {
+      e = hipErrorLaunchTimeOut;
+      break;
+    }
+    if ((e = hipGraphLaunch(exec, gs)) != hipSuccess) break;
+    if ((e = hipStreamSynchronize(gs)) != hipSuccess) break;
+    if (flags[2] == MS_DONE || flags[3] != 0) break;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph_h) (void)hipGraphDestroy(graph_h);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(ms->gev[1], gs)) != hipSuccess) return e;
+  return hipStreamWaitEvent(st, ms->gev[1], 0);
 }
 
 void ms_release(MsDev* ms) {
@@ -648,6 +859,11 @@ void ms_release(MsDev* ms) {
 
 void ms_free_all(MsDev* ms) {
   ms_release(ms);
+  if (ms->gstream) (void)hipStreamDestroy(ms->gstream);
+  for (int i = 0; i < 2; ++i)
+    if (ms->gev[i]) (void)hipEventDestroy(ms->gev[i]);
+  ms->gstream = nullptr;
+  ms->gev[0] = ms->gev[1] = nullptr;
   if (ms->srcs) (void)hipFree(ms->srcs);
   if (ms->part) (void)hipFree(ms->part);
   if (ms->batches) (void)hipFree(ms->batches);

@@ -179,3 +179,42 @@ def test_closeness_full_size(blest, which):
     assert np.array_equal(s[idx], osum)
     assert np.array_equal(r[idx], oreach)
     assert np.array_equal(c[idx], occ)
+
+
+@pytest.mark.parametrize("name", ["rmat13", "grid60", "path2000", "disconnected"])
+def test_msbfs_graph_mode(blest, name):
+    """msbfs_graph=1: per-phase kernels captured in a hipGraph and replayed
+    (many replays per call, the graph object reused across calls) give the same
+    levels and closeness as the oracle, for uneven batches and every policy."""
+    if name == "rmat13":
+        rp, col = inputs.rmat_graph(13, 61)
+    elif name == "grid60":
+        rp, col = inputs.grid_graph(60, 3)
+    elif name == "path2000":
+        rp, col = H.path(2000)
+    else:
+        rp, col = inputs.from_pairs(29, [0, 1, 2, 10, 11, 20], [1, 2, 3, 11, 12, 21])
+    n = rp.size - 1
+    srcs = np.arange(n, dtype=np.int32) if n <= 300 else inputs.sources(rp, 300, seed=4)
+    ref = oracle.msbfs16(rp, col, srcs)
+    g = blest.Graph(rp, col, msbfs_graph=1)
+    for pol in POLICIES:
+        g.set_policy(getattr(blest.Policy, pol), 10.0, 3)
+        got = g.msbfs_batched(srcs, [64, 128, 256, 512]).cpu().numpy()
+        assert np.array_equal(got, ref), (name, pol)
+    osum, oreach, occ = oracle.closeness(rp, col, srcs)
+    s, r, c = g.closeness(srcs)
+    assert np.array_equal(s.cpu().numpy(), osum)
+    assert np.array_equal(r.cpu().numpy(), oreach)
+    assert np.array_equal(c.cpu().numpy(), occ)
+    g.close()
+
+
+def test_msbfs_graph_mode_overflow(blest):
+    rp, col = H.path(33000)
+    g = blest.Graph(rp, col, msbfs_graph=1)
+    with pytest.raises(blest.BlestError) as ei:
+        g.msbfs([0, 5])
+    assert ei.value.status == blest.Status.OVERFLOW
+    assert np.array_equal(g.msbfs([16000]).cpu().numpy(), oracle.msbfs16(rp, col, [16000]))
+    g.close()
