@@ -158,6 +158,13 @@ blest_status blest_msbfs_batched(blest_graph* g, const int32_t* srcs_host, int32
 blest_status blest_closeness(blest_graph* g, const int32_t* srcs_host, int64_t k, int64_t* sums_dev,
                              int64_t* reach_dev, double* cc_dev, void* stream);
 
+/* Per-target distance sums of Eq. 4 (Closeness Centrality): far_dev[v] =
+ * sum over the k sources c that reach v of d(srcs[c], v), in input vertex ids;
+ * far_dev: int64[n] device memory, overwritten. Paper's normalisation for a
+ * connected graph with all vertices as sources: cc(v) = (n-1)/far(v) (Eq. 5).
+ * Sources may repeat (each counts). Errors as blest_closeness. */
+blest_status blest_far(blest_graph* g, const int32_t* srcs_host, int64_t k, int64_t* far_dev, void* stream);
+
 /* With opts.async = 1: waits for `stream` and reports device-side errors of the
  * calls enqueued since the last sync (TIMEOUT, OVERFLOW). */
 blest_status blest_sync(blest_graph* g, void* stream);

@@ -113,6 +113,7 @@ SIGNATURES = {
     "blest_msbfs": (_i32, [_vp, _p32, _i32, _vp, _vp]),
     "blest_msbfs_batched": (_i32, [_vp, _p32, _i32, _p32, _i32, _vp, _vp]),
     "blest_closeness": (_i32, [_vp, _p32, _i64, _vp, _vp, _vp, _vp]),
+    "blest_far": (_i32, [_vp, _p32, _i64, _vp, _vp]),
     "blest_sync": (_i32, [_vp, _vp]),
     "blest_set_policy": (_i32, [_vp, _i32, _f32, _u64]),
     "blest_graph_info": (_i32, [_vp, ctypes.POINTER(GraphStats)]),
@@ -216,6 +217,11 @@ def blest_closeness(h, srcs, sums, reach, cc, stream=None):
     s = np.ascontiguousarray(srcs, dtype=np.int32)
     _check(lib().blest_closeness(h, s.ctypes.data_as(_p32) if s.size else None, s.size, _ptr(sums), _ptr(reach),
                                  _ptr(cc), _stream(stream)))
+
+
+def blest_far(h, srcs, far, stream=None):
+    s = np.ascontiguousarray(srcs, dtype=np.int32)
+    _check(lib().blest_far(h, s.ctypes.data_as(_p32) if s.size else None, s.size, _ptr(far), _stream(stream)))
 
 
 def blest_sync(h, stream=None):
@@ -332,6 +338,12 @@ class Graph:
         cc = torch.empty(k, dtype=torch.float64, device=self.device)
         blest_closeness(self._h, srcs, sums, reach, cc, stream)
         return sums, reach, cc
+
+    def far(self, srcs, stream=None):
+        """Per-target distance sums of Eq. 4: int64[n], input vertex ids."""
+        out = torch.empty(self.n, dtype=torch.int64, device=self.device)
+        blest_far(self._h, srcs, out, stream)
+        return out
 
     def sync(self, stream=None):
         blest_sync(self._h, stream)

@@ -631,6 +631,29 @@ blest_status blest_closeness(blest_graph* g, const int32_t* srcs, int64_t k, int
   return wait_and_check(g, st);
 }
 
+blest_status blest_far(blest_graph* g, const int32_t* srcs, int64_t k, int64_t* far_dev, void* stream) {
+  if (!g) return fail(BLEST_ERR_INVALID_ARG, "NULL graph");
+  if (k < 0 || k > INT32_MAX) return fail(BLEST_ERR_INVALID_ARG, "bad source count");
+  if (!far_dev) return fail(BLEST_ERR_INVALID_ARG, "NULL output");
+  if (k > 0 && !srcs) return fail(BLEST_ERR_INVALID_ARG, "NULL sources");
+  for (int64_t c = 0; c < k; ++c)
+    if (srcs[c] < 0 || srcs[c] >= g->d.n) return fail(BLEST_ERR_OUT_OF_RANGE, "source vertex out of range");
+  CK(hipSetDevice(g->d.device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  CK(hipMemsetAsync(far_dev, 0, sizeof(int64_t) * static_cast<size_t>(g->d.n), st));
+  if (k == 0) return g->opts.async ? BLEST_OK : wait_and_check(g, st);
+  std::vector<int32_t> internal(srcs, srcs + k);
+  if (!g->perm.empty())
+    for (auto& s : internal) s = g->perm[s];
+  const int32_t w = g->opts.msbfs_width;
+  hipError_t e = blest::ms_run(g->d, &g->ms, internal.data(), static_cast<int32_t>(k), &w, 1, g->opts.policy,
+                               g->opts.eta, g->opts.random_seed, nullptr, nullptr, nullptr, nullptr, st,
+                               g->opts.msbfs_graph, far_dev);
+  if (e != hipSuccess) return hip_fail(e, "far");
+  if (g->opts.async) return BLEST_OK;
+  return wait_and_check(g, st);
+}
+
 blest_status blest_mlp_forward(const float* params, const float* x, int32_t batch, float* logits, void* stream) {
   if (batch < 0) return fail(BLEST_ERR_INVALID_ARG, "negative batch");
   if (batch == 0) return BLEST_OK;

@@ -38,13 +38,14 @@ struct MsDev {
 // the last width repeating. levels16 (k*n, source-major, input ids) and/or
 // sums/reach/cc may be NULL. Device-side errors (overflow, timeout) are left
 // in g.ctl->error. Returns after the launch is enqueued.
-// graph != 0: the same work as a hipGraph of per-phase kernels (batch set-up,
+// far (n entries, input ids, zeroed by the caller): per-target distance sums
+// of Eq. 4, added to. graph != 0: the same work as a hipGraph of per-phase kernels (batch set-up,
 // seeding, each level's engine and Stage 2, batch reduction) replayed until a
 // device-side state machine reports the last batch done; the call then
 // returns with the work finished.
 hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs_internal, int32_t k, const int32_t* widths,
                   int nwidths, int policy, float eta, uint64_t seed, int16_t* levels16, int64_t* sums,
-                  int64_t* reach, double* cc, hipStream_t st, int graph = 0);
+                  int64_t* reach, double* cc, hipStream_t st, int graph = 0, int64_t* far = nullptr);
 void ms_release(MsDev* ms);   // frees the per-vertex arrays
 void ms_free_all(MsDev* ms);  // frees everything
 void ms_reset(MsDev* ms);     // clears marks after a device-side error

@@ -62,6 +62,7 @@ struct MsArgs {
   int64_t* sums;      // k or NULL
   int64_t* reach;     // k or NULL
   double* cc;         // k or NULL
+  int64_t* far;       // n (input ids) or NULL: per-target sums of Eq. 4, accumulated
   long long* part;    // per block: kappa sums then kappa reach counts
   Ctl* ctl;
   int32_t policy;
@@ -254,6 +255,9 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
       if (mine) a.dirty[s] = 0;
       const bool wave_any = __ballot(mine) != 0ULL;
       unsigned long long A_any = 0ULL;
+      int far_cnt[SIGMA];  // per vertex of the set: traversals that reached it at this level
+#pragma unroll
+      for (int b = 0; b < SIGMA; ++b) far_cnt[b] = 0;
       if (wave_any) {
         for (int w = 0; w < W; ++w) {
           unsigned long long dw[SIGMA];
@@ -274,6 +278,7 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
               a.F[idx] = dd;
               dw[b] = dd;
               Aw |= dd;
+              far_cnt[b] += __popcll(dd);
             }
           }
           if (mine) a.act[s * W + w] = Aw;
@@ -312,6 +317,16 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
           }
           if (cnt_c) atomicAdd(&lds_cnt[w * 64 + lane], cnt_c);
         }
+      }
+      if (a.far && mine && A_any && new_level > 0) {
+        // Eq. 4: far[u] += level * (traversals reaching u at this level); the
+        // thread owns set s, so no other thread updates these vertices
+#pragma unroll
+        for (int b = 0; b < SIGMA; ++b)
+          if (far_cnt[b]) {
+            const long long u = s * SIGMA + b;
+            a.far[a.orig_id ? a.orig_id[u] : u] += static_cast<int64_t>(new_level) * far_cnt[b];
+          }
       }
       if (mine && A_any) {
         s0 = a.slice_ptr[s];
@@ -738,7 +753,7 @@ hipError_t ensure(const DevGraph& g, MsDev* ms, int wmax, int32_t k, int nbatche
 
 hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, const int32_t* widths, int nwidths,
                   int policy, float eta, uint64_t seed, int16_t* levels16, int64_t* sums, int64_t* reach, double* cc,
-                  hipStream_t st, int graph) {
+                  hipStream_t st, int graph, int64_t* far) {
   if (k <= 0) return hipSuccess;
   std::vector<MsBatch> plan;
   int32_t off = 0;
@@ -783,6 +798,7 @@ hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, 
   a.sums = sums;
   a.reach = reach;
   a.cc = cc;
+  a.far = far;
   a.part = ms->part;
   a.ctl = g.ctl;
   a.policy = policy;

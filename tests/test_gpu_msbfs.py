@@ -110,8 +110,25 @@ def test_closeness_all_sources_equals_per_target_far(blest):
     allv = np.arange(n, dtype=np.int32)
     g = blest.Graph(rp, col)
     s, _, _ = g.closeness(allv)
-    assert np.array_equal(s.cpu().numpy(), oracle.far(rp, col, allv))
+    ofar = oracle.far(rp, col, allv)
+    assert np.array_equal(s.cpu().numpy(), ofar)
+    assert np.array_equal(g.far(allv).cpu().numpy(), ofar)  # Eq. 4 on the device: equal when S = V
     g.close()
+
+
+@pytest.mark.parametrize("graph_mode", [0, 1])
+def test_per_target_far_subsets(blest, graph_mode):
+    """Eq. 4's per-target sums for source subsets (repeats count twice),
+    relabelled graphs and several batch widths."""
+    for rp, col, opts in [(*inputs.rmat_graph(12, 91), {}), (*inputs.grid_graph(40, 92), {"reorder": 1}),
+                          (*inputs.rmat_graph(12, 93), {"msbfs_width": 64}),
+                          (*inputs.from_pairs(9, [0, 1, 4], [1, 2, 5]), {})]:
+        n = rp.size - 1
+        srcs = inputs.sources(rp, min(n, 300), seed=94, nonzero_degree=False, distinct=False)
+        g = blest.Graph(rp, col, msbfs_graph=graph_mode, **opts)
+        assert np.array_equal(g.far(srcs).cpu().numpy(), oracle.far(rp, col, srcs))
+        assert np.array_equal(g.far([]).cpu().numpy(), np.zeros(n, np.int64))
+        g.close()
 
 
 def test_msbfs_full_size_rmat20_sampled_rows(blest):
