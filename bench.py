@@ -18,8 +18,10 @@ method (BVSS top-down at every level) on the same sources with its roofline,
 the 2048x2048 grid with 10% edge deletion (RCM-reordered), batched
 multi-source BFS sources/s on scale-20 R-MAT (960 sources in batches of
 64/128/256/512, one launch), exact closeness (all 262,144 sources of
-scale-18 R-MAT; 16,384 sources of scale-23 R-MAT) and the CPU oracle on a
-bounded sample.
+scale-18 R-MAT; 16,384 sources of scale-23 R-MAT) with the pairs rule and
+with the multi-source switch network (paper_2606_05081_amd/switch_model_ms.json,
+kept per graph only if a trial batch of 512 other sources was faster with it)
+and the CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -91,12 +93,34 @@ def timed_sources(g, srcs, out, torch):
     return [evs[i].elapsed_time(evs[i + 1]) for i in range(len(srcs))]
 
 
-def load_switch_model():
-    path = os.path.join(ROOT, "paper_2606_05081_amd", "switch_model.json")
+def load_switch_model(name="switch_model.json"):
+    path = os.path.join(ROOT, "paper_2606_05081_amd", name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         return json.load(f)
+
+
+def timed_call(fn, torch):
+    """Device time (ms) of one call of fn on the current stream, after a sync."""
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def ms_learned_enable(g, trial_srcs, torch, blest):
+    """Per-graph enable of the multi-source network: one trial batch of 512
+    sources per policy; the learned policy stays only if it was faster."""
+    t = {}
+    for name, pol in (("heuristic", blest.Policy.HEURISTIC), ("learned", blest.Policy.LEARNED)):
+        g.set_policy(pol)
+        g.closeness(trial_srcs)
+        t[name] = timed_call(lambda: (g.closeness(trial_srcs), g.sync()), torch)
+    return t["learned"] < t["heuristic"], t
 
 
 def cpu_baseline(rp, col, srcs, budget_s=20.0):
@@ -119,6 +143,7 @@ def cpu_baseline(rp, col, srcs, budget_s=20.0):
 # The persistent kernel and what fixes its launch (block size, panel layout):
 # a counter summary taken on other versions of these files is not reported.
 KERNEL_SOURCES = ["paper_2606_05081_amd/csrc/bfs.hip", "paper_2606_05081_amd/csrc/device_common.h",
+                  "paper_2606_05081_amd/csrc/mlp_infer.h",
                   "paper_2606_05081_amd/csrc/blest_internal.h", "paper_2606_05081_amd/csrc/api.cpp",
                   "paper_2606_05081_amd/csrc/host_build.cpp"]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_bfs_persistent_rmat22_bvss_traffic.txt")
@@ -330,6 +355,15 @@ def main():
             torch.cuda.synchronize()
             per_width[str(w)] = round(960 / e0.elapsed_time(e1) * 1e3, 1)
         extras["msbfs_sources_per_s_by_width"] = per_width
+        ms_model = load_switch_model("switch_model_ms.json")
+        if ms_model is not None:  # the same 960 sources with the multi-source switch network
+            mg.set_ms_switch_model(np.array(ms_model["params"], np.float32), np.array(ms_model["mean"], np.float32),
+                                   np.array(ms_model["std"], np.float32), ms_model.get("min_confidence", 0.5))
+            mg.set_policy(blest.Policy.LEARNED)
+            mg.msbfs_batched(msrcs, [64, 128, 256, 512], mout)
+            lms = timed_call(lambda: (mg.msbfs_batched(msrcs, [64, 128, 256, 512], mout), mg.sync()), torch)
+            extras["msbfs_learned_sources_per_s"] = round(960 / lms * 1e3, 1)
+            mg.set_policy(blest.Policy.HEURISTIC)
         mg.close()
         # the same 960 sources with the levels as a replayed hipGraph of per-phase kernels
         gmg = blest.Graph(mrp, mcol, device=0, msbfs_graph=1, **{"async": 1})
@@ -358,23 +392,33 @@ def main():
             timed_sources(sg, ss, sout, torch)
             extras[name] = round(harmonic_gteps(sedges, timed_sources(sg, ss, sout, torch)), 3)
         sg.close()
-        # exact closeness: all sources of scale-18 R-MAT, 16,384 sources of scale-23 R-MAT (512 per batch)
+        # exact closeness: all sources of scale-18 R-MAT, 16,384 sources of scale-23 R-MAT (512 per
+        # batch), with the pairs rule and with the multi-source switch network (per-graph enabled)
+        ms_model = load_switch_model("switch_model_ms.json")
         for tag, scale, gseed, k in (("closeness_rmat18_all", 18, 1050, None), ("closeness_rmat23_16k", 23, 1052, 16384)):
             crp, ccol = inputs.rmat_graph(scale, gseed)
             cs = np.arange(crp.size - 1, dtype=np.int32) if k is None else inputs.sources(crp, k, seed=gseed + 1)
             cg = blest.Graph(crp, ccol, device=0, msbfs_width=512, **{"async": 1})
-            cg.closeness(cs[:512])
-            cg.sync()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            cg.closeness(cs)
-            e1.record()
-            cg.sync()
-            torch.cuda.synchronize()
-            cms = e0.elapsed_time(e1)
-            extras[tag] = {"sources": int(cs.size), "ms": round(cms, 1), "sources_per_s": round(cs.size / cms * 1e3, 1)}
-            print(f"# {tag}: {cs.size} sources in {cms:.1f} ms", file=sys.stderr, flush=True)
+            res = {"sources": int(cs.size)}
+            pols = [("heuristic", blest.Policy.HEURISTIC)]
+            if ms_model is not None:
+                cg.set_ms_switch_model(np.array(ms_model["params"], np.float32), np.array(ms_model["mean"], np.float32),
+                                       np.array(ms_model["std"], np.float32), ms_model.get("min_confidence", 0.5))
+                enabled, trial = ms_learned_enable(cg, inputs.sources(crp, 512, seed=gseed + 7), torch, blest)
+                res["learned_enabled_by_trial"] = bool(enabled)
+                res["trial_ms"] = {k2: round(v, 2) for k2, v in trial.items()}
+                pols.append(("learned", blest.Policy.LEARNED))
+            for name, pol in pols:
+                cg.set_policy(pol)
+                cg.closeness(cs[:512])
+                cms = timed_call(lambda: (cg.closeness(cs), cg.sync()), torch)
+                res[f"ms_{name}"] = round(cms, 1)
+                print(f"# {tag} {name}: {cs.size} sources in {cms:.1f} ms", file=sys.stderr, flush=True)
+            chosen = "learned" if res.get("learned_enabled_by_trial") else "heuristic"
+            res["policy"] = chosen
+            res["ms"] = res[f"ms_{chosen}"]
+            res["sources_per_s"] = round(cs.size / res["ms"] * 1e3, 1)
+            extras[tag] = res
             cg.close()
         cpu = cpu_baseline(rp, col, srcs)
 

@@ -165,6 +165,32 @@ blest_status blest_closeness(blest_graph* g, const int32_t* srcs_host, int64_t k
  * Sources may repeat (each counts). Errors as blest_closeness. */
 blest_status blest_far(blest_graph* g, const int32_t* srcs_host, int64_t k, int64_t* far_dev, void* stream);
 
+/* Same result as blest_msbfs_batched, but every level runs both multi-source
+ * engines (BVSS and bottom-up) from the same state and times each (device
+ * clock), for switch training data (persistent launch; returns after the
+ * stream syncs). Records via blest_msbfs_last_levels. */
+blest_status blest_msbfs_probe(blest_graph* g, const int32_t* srcs_host, int32_t k, const int32_t* widths_host,
+                               int32_t nwidths, int16_t* levels_dev, void* stream);
+
+/* Per-level record of the last multi-source call (all batches in order). */
+typedef struct {
+  int32_t batch, level;
+  int32_t engine;          /* BLEST_ENGINE_BVSS or _BOTTOM_UP (-1 in probe mode) */
+  int32_t mlp_fallback;    /* learned policy: 1 if the pairs rule decided */
+  int32_t width;           /* sources in the batch */
+  int32_t live;            /* traversals whose frontier is non-empty at this level */
+  int64_t new_pairs;       /* (vertex, traversal) pairs at this level */
+  int64_t queue;           /* VSSs queued */
+  int64_t queue_slices;
+  int64_t unvisited_pairs;
+  double t_engine_us[2];   /* probe mode: BVSS, bottom-up; else -1 */
+  float feat[12];          /* the multi-source switch network's inputs */
+} blest_ms_level_stat;
+
+/* Copies up to cap records of the last multi-source call to buf (host);
+ * *nrec = records written by the call. Errors: INVALID_ARG, HIP. */
+blest_status blest_msbfs_last_levels(const blest_graph* g, blest_ms_level_stat* buf, int32_t cap, int32_t* nrec);
+
 /* With opts.async = 1: waits for `stream` and reports device-side errors of the
  * calls enqueued since the last sync (TIMEOUT, OVERFLOW). */
 blest_status blest_sync(blest_graph* g, void* stream);
@@ -248,9 +274,20 @@ blest_status blest_export_bvss(const blest_graph* g, int64_t* real_ptrs, int64_t
 blest_status blest_set_switch_model(blest_graph* g, const float* params, int32_t nparams, const float* mean,
                                     const float* std);
 
+/* Installs the multi-source switch network (same format; inputs listed at
+ * blest_ms_level_stat.feat: log(1+new pairs), log(1+queued slices), shares of
+ * new pairs, VSSs, slices and unvisited pairs, log batch width, log |Q| - log
+ * unvisited pairs, log live traversals - log batch width, three zeros). Outputs 0 (BVSS) and 2 (bottom-up) are used;
+ * any other choice falls back to the pairs rule. g = NULL: default for graphs
+ * built afterwards. Errors as blest_set_switch_model. */
+blest_status blest_set_ms_switch_model(blest_graph* g, const float* params, int32_t nparams, const float* mean,
+                                       const float* std);
+
 /* Minimum softmax probability of the network's choice for BLEST_POLICY_LEARNED
- * (default 0.5); below it, and for standardised inputs outside [-6, 6], the
- * level falls back to Eq. 3. g = NULL sets the default for later models.
+ * (default 0.5), for both networks of g (single- and multi-source); below it,
+ * and for standardised inputs outside [-6, 6], the level falls back to Eq. 3
+ * (the pairs rule for multi-source levels). A model installed later takes the
+ * default again. g = NULL sets the default for later models.
  * Errors: INVALID_ARG (min_prob outside (0, 1]). */
 blest_status blest_set_switch_confidence(blest_graph* g, float min_prob);
 

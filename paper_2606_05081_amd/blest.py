@@ -96,6 +96,14 @@ class LevelStat(ctypes.Structure):
                 ("t_count_us", ctypes.c_double)]
 
 
+class MsLevelStat(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("level", ctypes.c_int32), ("engine", ctypes.c_int32),
+                ("mlp_fallback", ctypes.c_int32), ("width", ctypes.c_int32), ("live", ctypes.c_int32),
+                ("new_pairs", ctypes.c_int64), ("queue", ctypes.c_int64), ("queue_slices", ctypes.c_int64),
+                ("unvisited_pairs", ctypes.c_int64), ("t_engine_us", ctypes.c_double * 2),
+                ("feat", ctypes.c_float * 12)]
+
+
 # Every exported symbol of the C ABI: name -> (restype, argtypes).
 _vp, _i32, _i64, _u64, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float
 _p32 = ctypes.POINTER(ctypes.c_int32)
@@ -114,6 +122,9 @@ SIGNATURES = {
     "blest_msbfs_batched": (_i32, [_vp, _p32, _i32, _p32, _i32, _vp, _vp]),
     "blest_closeness": (_i32, [_vp, _p32, _i64, _vp, _vp, _vp, _vp]),
     "blest_far": (_i32, [_vp, _p32, _i64, _vp, _vp]),
+    "blest_msbfs_probe": (_i32, [_vp, _p32, _i32, _p32, _i32, _vp, _vp]),
+    "blest_msbfs_last_levels": (_i32, [_vp, ctypes.POINTER(MsLevelStat), _i32, _p32]),
+    "blest_set_ms_switch_model": (_i32, [_vp, _pf32, _i32, _pf32, _pf32]),
     "blest_sync": (_i32, [_vp, _vp]),
     "blest_set_policy": (_i32, [_vp, _i32, _f32, _u64]),
     "blest_graph_info": (_i32, [_vp, ctypes.POINTER(GraphStats)]),
@@ -213,6 +224,13 @@ def blest_msbfs_batched(h, srcs, widths, levels: torch.Tensor, stream=None):
                                      w.size, _ptr(levels), _stream(stream)))
 
 
+def blest_msbfs_probe(h, srcs, widths, levels: torch.Tensor, stream=None):
+    s = np.ascontiguousarray(srcs, dtype=np.int32)
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    _check(lib().blest_msbfs_probe(h, s.ctypes.data_as(_p32) if s.size else None, s.size, w.ctypes.data_as(_p32),
+                                   w.size, _ptr(levels), _stream(stream)))
+
+
 def blest_closeness(h, srcs, sums, reach, cc, stream=None):
     s = np.ascontiguousarray(srcs, dtype=np.int32)
     _check(lib().blest_closeness(h, s.ctypes.data_as(_p32) if s.size else None, s.size, _ptr(sums), _ptr(reach),
@@ -238,6 +256,14 @@ def blest_set_switch_model(h, params, mean, std):
     sd = np.ascontiguousarray(std, dtype=np.float32)
     _check(lib().blest_set_switch_model(h, p.ctypes.data_as(_pf32), p.size, mu.ctypes.data_as(_pf32),
                                         sd.ctypes.data_as(_pf32)))
+
+
+def blest_set_ms_switch_model(h, params, mean, std):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    mu = np.ascontiguousarray(mean, dtype=np.float32)
+    sd = np.ascontiguousarray(std, dtype=np.float32)
+    _check(lib().blest_set_ms_switch_model(h, p.ctypes.data_as(_pf32), p.size, mu.ctypes.data_as(_pf32),
+                                           sd.ctypes.data_as(_pf32)))
 
 
 def blest_set_switch_confidence(h, min_prob: float):
@@ -330,6 +356,33 @@ class Graph:
             out = torch.empty((k, self.n), dtype=torch.int16, device=self.device)
         blest_msbfs_batched(self._h, srcs, widths, out, stream)
         return out
+
+    def msbfs_probe(self, srcs, widths, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        k = len(srcs)
+        if out is None:
+            out = torch.empty((k, self.n), dtype=torch.int16, device=self.device)
+        blest_msbfs_probe(self._h, srcs, widths, out, stream)
+        return out
+
+    def ms_level_stats(self, cap: int = 1 << 16) -> list:
+        """Per-level records of the last multi-source call (dicts; 'feat' is a list)."""
+        buf = (MsLevelStat * cap)()
+        nr = ctypes.c_int32()
+        _check(lib().blest_msbfs_last_levels(self._h, buf, cap, ctypes.byref(nr)))
+        out = []
+        for i in range(min(cap, nr.value)):
+            r = buf[i]
+            d = {k: getattr(r, k) for k, _ in MsLevelStat._fields_ if k not in ("reserved", "t_engine_us", "feat")}
+            d["t_engine_us"] = list(r.t_engine_us)
+            d["feat"] = list(r.feat)
+            out.append(d)
+        return out
+
+    def set_ms_switch_model(self, params, mean, std, min_confidence: float | None = None):
+        """Multi-source network; min_confidence (if given) applies to both networks."""
+        blest_set_ms_switch_model(self._h, params, mean, std)
+        if min_confidence is not None:
+            blest_set_switch_confidence(self._h, min_confidence)
 
     def closeness(self, srcs, stream=None):
         k = len(srcs)

@@ -53,6 +53,8 @@ std::mutex g_model_mu;
 bool g_model_set = false;
 float g_min_conf = 0.5f;
 blest::MlpDev g_model{};
+bool g_ms_model_set = false;
+blest::MlpDev g_ms_model{};
 
 hipError_t dalloc(blest_graph* g, void** p, size_t bytes) {
   *p = nullptr;
@@ -334,6 +336,7 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   TRY(dalloc_t(g, &d.part, static_cast<size_t>(d.grid) * 8));
   TRY(dalloc_t(g, &d.log, static_cast<size_t>(d.log_cap)));
   TRY(dalloc_t(g, &d.mlp, 1));
+  TRY(dalloc_t(g, &d.ms_mlp, 1));
   if (g->reordered) {
     TRY(dalloc_t(g, &d.orig_id, static_cast<size_t>(n)));
     TRY(hipMemcpy(d.orig_id, orig.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
@@ -360,9 +363,11 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   TRY(hipMemset(d.mark, 0, mark_bytes));
   TRY(hipMemset(d.ctl, 0, sizeof(blest::Ctl)));
   TRY(hipMemset(d.mlp, 0, sizeof(blest::MlpDev)));
+  TRY(hipMemset(d.ms_mlp, 0, sizeof(blest::MlpDev)));
   {
     std::lock_guard<std::mutex> lk(g_model_mu);
     if (g_model_set) TRY(hipMemcpy(d.mlp, &g_model, sizeof(g_model), hipMemcpyHostToDevice));
+    if (g_ms_model_set) TRY(hipMemcpy(d.ms_mlp, &g_ms_model, sizeof(g_ms_model), hipMemcpyHostToDevice));
   }
   TRY(hipDeviceSynchronize());
 #undef TRY
@@ -515,8 +520,11 @@ blest_status blest_export_bvss(const blest_graph* g, int64_t* real_ptrs, int64_t
   return BLEST_OK;
 }
 
-blest_status blest_set_switch_model(blest_graph* g, const float* params, int32_t nparams, const float* mean,
-                                    const float* std_) {
+namespace {
+
+// Validates and packs switch-network weights (the same format for both networks).
+blest_status make_model(const float* params, int32_t nparams, const float* mean, const float* std_,
+                        blest::MlpDev* out) {
   if (!params || !mean || !std_) return fail(BLEST_ERR_INVALID_ARG, "NULL argument");
   if (nparams != BLEST_MLP_NPARAMS) return fail(BLEST_ERR_INVALID_ARG, "wrong parameter count");
   blest::MlpDev m{};
@@ -534,6 +542,33 @@ blest_status blest_set_switch_model(blest_graph* g, const float* params, int32_t
     m.max_ratio = 1.0f / g_min_conf;
   }
   m.valid = 1;
+  *out = m;
+  return BLEST_OK;
+}
+
+}  // namespace
+
+blest_status blest_set_ms_switch_model(blest_graph* g, const float* params, int32_t nparams, const float* mean,
+                                       const float* std_) {
+  blest::MlpDev m{};
+  const blest_status s = make_model(params, nparams, mean, std_, &m);
+  if (s != BLEST_OK) return s;
+  if (!g) {
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    g_ms_model = m;
+    g_ms_model_set = true;
+    return BLEST_OK;
+  }
+  CK(hipSetDevice(g->d.device));
+  CK(hipMemcpy(g->d.ms_mlp, &m, sizeof(m), hipMemcpyHostToDevice));
+  return BLEST_OK;
+}
+
+blest_status blest_set_switch_model(blest_graph* g, const float* params, int32_t nparams, const float* mean,
+                                    const float* std_) {
+  blest::MlpDev m{};
+  const blest_status s = make_model(params, nparams, mean, std_, &m);
+  if (s != BLEST_OK) return s;
   if (!g) {
     std::lock_guard<std::mutex> lk(g_model_mu);
     g_model = m;
@@ -552,10 +587,13 @@ blest_status blest_set_switch_confidence(blest_graph* g, float min_prob) {
     std::lock_guard<std::mutex> lk(g_model_mu);
     g_min_conf = min_prob;
     g_model.max_ratio = r;
+    g_ms_model.max_ratio = r;
     return BLEST_OK;
   }
   CK(hipSetDevice(g->d.device));
   CK(hipMemcpy(reinterpret_cast<char*>(g->d.mlp) + offsetof(blest::MlpDev, max_ratio), &r, sizeof(float),
+               hipMemcpyHostToDevice));
+  CK(hipMemcpy(reinterpret_cast<char*>(g->d.ms_mlp) + offsetof(blest::MlpDev, max_ratio), &r, sizeof(float),
                hipMemcpyHostToDevice));
   return BLEST_OK;
 }
@@ -607,6 +645,59 @@ blest_status blest_msbfs_batched(blest_graph* g, const int32_t* srcs, int32_t k,
   if (e != hipSuccess) return hip_fail(e, "msbfs");
   if (g->opts.async) return BLEST_OK;
   return wait_and_check(g, st);
+}
+
+blest_status blest_msbfs_probe(blest_graph* g, const int32_t* srcs, int32_t k, const int32_t* widths, int32_t nwidths,
+                               int16_t* levels_dev, void* stream) {
+  if (!g) return fail(BLEST_ERR_INVALID_ARG, "NULL graph");
+  if (k < 0 || nwidths < 1 || !widths) return fail(BLEST_ERR_INVALID_ARG, "bad source count or widths");
+  for (int32_t i = 0; i < nwidths; ++i)
+    if (widths[i] != 64 && widths[i] != 128 && widths[i] != 256 && widths[i] != 512)
+      return fail(BLEST_ERR_UNSUPPORTED, "batch widths must be 64, 128, 256 or 512");
+  if (k == 0) return BLEST_OK;
+  if (!srcs || !levels_dev) return fail(BLEST_ERR_INVALID_ARG, "NULL sources or output");
+  for (int32_t c = 0; c < k; ++c)
+    if (srcs[c] < 0 || srcs[c] >= g->d.n) return fail(BLEST_ERR_OUT_OF_RANGE, "source vertex out of range");
+  CK(hipSetDevice(g->d.device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<int32_t> internal(srcs, srcs + k);
+  if (!g->perm.empty())
+    for (auto& s : internal) s = g->perm[s];
+  hipError_t e = blest::ms_run(g->d, &g->ms, internal.data(), k, widths, nwidths, g->opts.policy, g->opts.eta,
+                               g->opts.random_seed, levels_dev, nullptr, nullptr, nullptr, st, 0, nullptr, 1);
+  if (e != hipSuccess) return hip_fail(e, "msbfs probe");
+  return wait_and_check(g, st);
+}
+
+blest_status blest_msbfs_last_levels(const blest_graph* g, blest_ms_level_stat* buf, int32_t cap, int32_t* nrec) {
+  if (!g || !nrec || (cap > 0 && !buf)) return fail(BLEST_ERR_INVALID_ARG, "NULL argument");
+  CK(hipSetDevice(g->d.device));
+  int n = 0;
+  CK(hipMemcpy(&n, &g->d.ctl->ms_nrec[0], sizeof(int), hipMemcpyDeviceToHost));
+  n = std::min(n, g->ms.log_cap);
+  *nrec = n;
+  const int k = std::min(cap, n);
+  if (k <= 0 || !g->ms.log) return BLEST_OK;
+  std::vector<blest::MsLevelRec> rec(static_cast<size_t>(k));
+  CK(hipMemcpy(rec.data(), g->ms.log, sizeof(blest::MsLevelRec) * k, hipMemcpyDeviceToHost));
+  for (int i = 0; i < k; ++i) {
+    const blest::MsLevelRec& r = rec[i];
+    blest_ms_level_stat& o = buf[i];
+    std::memset(&o, 0, sizeof(o));
+    o.batch = r.batch;
+    o.level = r.level;
+    o.engine = r.engine;
+    o.mlp_fallback = r.fallback;
+    o.width = r.width;
+    o.live = r.live;
+    o.new_pairs = r.fresh;
+    o.queue = r.queue;
+    o.queue_slices = r.qslices;
+    o.unvisited_pairs = r.unvisited;
+    for (int e = 0; e < 2; ++e) o.t_engine_us[e] = r.t_engine[e] ? r.t_engine[e] * g->d.tick_us : -1.0;
+    std::memcpy(o.feat, r.feat, sizeof(o.feat));
+  }
+  return BLEST_OK;
 }
 
 blest_status blest_closeness(blest_graph* g, const int32_t* srcs, int64_t k, int64_t* sums_dev, int64_t* reach_dev,

@@ -39,6 +39,7 @@ enum StatField : int {
   F_CUMV = 8,      // vertices visited through this level
   F_CUME = 9,      // sum of degrees of those vertices
   F_WORK = 10,     // adjacency entries (slices or CSR edges) read by the engine that left this level
+  F_LIVE = 11,     // multi-source: one 64-bit word per batch word, bit c set iff traversal c gained a vertex
 };
 
 // Push-engine work split: vertices of degree <= kLightMax are walked by one
@@ -63,6 +64,15 @@ struct alignas(256) Ctl {
   unsigned int single_gen[kPad];   // number of finished single-workgroup episodes
   int nlevels[kPad * 2]; // frontier levels of the last traversal
   int ms_state[2][kPad];   // multi-source graph mode: {phase, batch, level} read by even/odd kernels
+  int ms_nrec[kPad];       // multi-source level records written by the last call
+};
+
+// One record per level of a multi-source call (all batches in order).
+struct MsLevelRec {
+  int batch, level, engine, fallback, width, live;  // live: traversals with a non-empty frontier
+  long long fresh, queue, qslices, unvisited;  // new pairs, VSSs, slices, unvisited pairs
+  unsigned long long t_engine[2];              // probe mode: device ticks of BVSS and bottom-up
+  float feat[kMaxSwitchFeatures];
 };
 
 // One record per frontier level, written by workgroup 0 of the persistent kernel.
@@ -150,6 +160,7 @@ struct DevGraph {
   int32_t* flight[2] = {nullptr, nullptr};
   unsigned long long* fheavy[2] = {nullptr, nullptr};
   Ctl* ctl = nullptr;
+  MlpDev* ms_mlp = nullptr;  // switch network of the multi-source kernels
   long long* part = nullptr;
   LevelRec* log = nullptr;
   int log_cap = 0;

@@ -29,6 +29,8 @@ struct MsDev {
   void* batches = nullptr;           // batch descriptors
   int batches_cap = 0;
   int grid = 0, block = 512;
+  MsLevelRec* log = nullptr;       // per-level records of the last call
+  int log_cap = 0;
   hipStream_t gstream = nullptr;  // graph mode: capture/replay stream (non-blocking)
   hipEvent_t gev[2] = {nullptr, nullptr};
 };
@@ -38,6 +40,8 @@ struct MsDev {
 // the last width repeating. levels16 (k*n, source-major, input ids) and/or
 // sums/reach/cc may be NULL. Device-side errors (overflow, timeout) are left
 // in g.ctl->error. Returns after the launch is enqueued.
+// probe != 0: every level runs both engines from the same state and times
+// each (persistent launch). Level records go to ms->log (ms_nrec in ctl).
 // far (n entries, input ids, zeroed by the caller): per-target distance sums
 // of Eq. 4, added to. graph != 0: the same work as a hipGraph of per-phase kernels (batch set-up,
 // seeding, each level's engine and Stage 2, batch reduction) replayed until a
@@ -45,7 +49,8 @@ struct MsDev {
 // returns with the work finished.
 hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs_internal, int32_t k, const int32_t* widths,
                   int nwidths, int policy, float eta, uint64_t seed, int16_t* levels16, int64_t* sums,
-                  int64_t* reach, double* cc, hipStream_t st, int graph = 0, int64_t* far = nullptr);
+                  int64_t* reach, double* cc, hipStream_t st, int graph = 0, int64_t* far = nullptr,
+                  int probe = 0);
 void ms_release(MsDev* ms);   // frees the per-vertex arrays
 void ms_free_all(MsDev* ms);  // frees everything
 void ms_reset(MsDev* ms);     // clears marks after a device-side error

@@ -17,7 +17,11 @@
 // one no-return 64-bit atomic per word, and the row's set is marked dirty.
 // Stage 1, bottom-up (E2): a lane owns a vertex with unvisited traversals and
 // ORs its neighbours' frontier words until every unvisited bit is covered;
-// it alone writes N[u], so no atomics.
+// it alone writes N[u], so no atomics. Only live traversals count (those
+// whose frontier is non-empty, from Stage 2's OR of all new words): a
+// traversal with an empty frontier can reach nothing more, and waiting for
+// its bit (a source in a small component, or one that has finished) would
+// turn every early exit into a full adjacency scan.
 // Stage 2 visits dirty slice sets only: new = N & ~V, V |= new, F = new,
 // activeSets[s] = OR of the set's new words, the set's VSSs are enqueued when
 // nonzero, int16 levels are written, and per-source counts of newly reached
@@ -26,6 +30,7 @@
 #include <vector>
 
 #include "device_common.h"
+#include "mlp_infer.h"
 #include "msbfs.h"
 
 namespace blest {
@@ -68,6 +73,11 @@ struct MsArgs {
   int32_t policy;
   float eta;
   uint64_t seed;
+  int64_t nvss, nslices;  // BVSS totals (switch features)
+  const MlpDev* mlp;      // multi-source switch network (policy LEARNED), or NULL
+  int32_t probe;          // 1: every level runs both engines from the same state and times each
+  MsLevelRec* log;        // one record per level of the call, or NULL
+  int32_t log_cap;
   unsigned long long timeout_ticks;
 };
 
@@ -90,6 +100,92 @@ __device__ __forceinline__ unsigned long long mix64_ms(unsigned long long z) {
 
 // Sets count int16 values to -1: elementwise up to 16-byte alignment, then
 // 16-byte stores, then the tail.
+// Switch inputs of a multi-source level, counted in (vertex, traversal) pairs
+// (base-2 logarithms): new pairs and queued slices (absolute), then shares:
+// new pairs / all pairs, VSSs / N_v, queued slices / all slices, unvisited
+// pairs / all pairs, the batch width, the ratio of the pairs rule
+// (log |Q| - log unvisited pairs), live traversals / batch width; three
+// reserved zeros.
+__device__ __forceinline__ void ms_features(float (&f)[kMaxSwitchFeatures], const MsArgs& a, long long fresh,
+                                            long long qlen, long long qslices, long long unv, int count,
+                                            int live) {
+  const float pairs = log2f(static_cast<float>(count) * static_cast<float>(a.n));
+  const float lu = log2f(1.0f + static_cast<float>(unv));
+  f[0] = log2f(1.0f + static_cast<float>(fresh));
+  f[1] = log2f(1.0f + static_cast<float>(qslices));
+  f[2] = f[0] - pairs;
+  f[3] = log2f(1.0f + static_cast<float>(qlen)) - log2f(1.0f + static_cast<float>(a.nvss));
+  f[4] = f[1] - log2f(1.0f + static_cast<float>(a.nslices));
+  f[5] = lu - pairs;
+  f[6] = log2f(static_cast<float>(count));
+  f[7] = log2f(1.0f + static_cast<float>(qlen)) - lu;
+  f[8] = log2f(static_cast<float>(max(live, 1))) - f[6];
+#pragma unroll
+  for (int k = 9; k < kMaxSwitchFeatures; ++k) f[k] = 0.0f;
+}
+
+// Live traversals of a stat slot (Stage 2 ORs the new words into F_LIVE;
+// words beyond the batch width stay zero). One 64-byte read, no dependent loads.
+__device__ __forceinline__ int ms_live_count(const Ctl* ctl, int slot) {
+  const unsigned long long* p = &ctl->acc[slot][F_LIVE][0];
+  int c = 0;
+#pragma unroll
+  for (int w = 0; w < kWMax; ++w) c += __popcll(p[w]);
+  return c;
+}
+
+// Block 0 clears one stat slot: element 0 of every field and the F_LIVE words.
+__device__ __forceinline__ void ms_clear_slot(Ctl* ctl, int slot) {
+  for (int t = threadIdx.x; t < kStatFields + kWMax; t += blockDim.x) {
+    if (t < kStatFields)
+      ctl->acc[slot][t][0] = 0ULL;
+    else
+      ctl->acc[slot][F_LIVE][t - kStatFields] = 0ULL;
+  }
+}
+
+// Engine of a multi-source level (uniform across the grid: every input is).
+// Eq. 3 counted in (vertex, traversal) pairs: the bottom-up engine reads W
+// frontier words per scanned edge and rarely stops early while many
+// traversals are open, so it is chosen only once fewer than eta * |Q| pairs
+// remain unvisited. LEARNED: the switch network (output 0 = BVSS, 2 =
+// bottom-up; anything else, or low confidence, falls back to the pairs rule).
+// Contains __syncthreads() when s_mlp is set.
+__device__ int ms_choose(const MsArgs& a, const float (&feat)[kMaxSwitchFeatures], long long qlen, long long unv,
+                         int level, int bi, const float* s_mlp, int* fallback) {
+  __shared__ int s_choice;
+  *fallback = 0;
+  const int rule = (static_cast<double>(unv) < static_cast<double>(a.eta) * static_cast<double>(qlen))
+                       ? BLEST_ENGINE_BOTTOM_UP
+                       : BLEST_ENGINE_BVSS;
+  switch (a.policy) {
+    case BLEST_POLICY_BVSS:
+    case BLEST_POLICY_PUSH:
+      return BLEST_ENGINE_BVSS;
+    case BLEST_POLICY_BOTTOM_UP:
+      return BLEST_ENGINE_BOTTOM_UP;
+    case BLEST_POLICY_RANDOM:
+      return (mix64_ms(a.seed + 0x9E3779B97F4A7C15ULL * static_cast<unsigned long long>(level + 1 + 977 * bi)) & 1ULL)
+                 ? BLEST_ENGINE_BOTTOM_UP
+                 : BLEST_ENGINE_BVSS;
+    case BLEST_POLICY_LEARNED:
+      if (s_mlp != nullptr) {
+        if (threadIdx.x < 64) {
+          const int c = mlp_choose_wave(s_mlp, feat);
+          if (threadIdx.x == 0) s_choice = c;
+        }
+        __syncthreads();
+        const int c = s_choice;
+        __syncthreads();
+        if (c == BLEST_ENGINE_BVSS || c == BLEST_ENGINE_BOTTOM_UP) return c;
+      }
+      *fallback = 1;
+      return rule;
+    default:
+      return rule;
+  }
+}
+
 __device__ void fill_minus_one(int16_t* p, long long count, long long gtid, long long nthreads) {
   const long long mis = (16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15;
   const long long head = min(count, mis / 2);
@@ -176,11 +272,12 @@ __device__ void ms_engine_bvss(const MsArgs& a, const uint4* q, long long qlen, 
 }
 
 template <int SIGMA>
-__device__ void ms_engine_pull(const MsArgs& a, int W, int count, long long gtid, long long nthreads) {
+__device__ void ms_engine_pull(const MsArgs& a, int W, int count, const unsigned long long* live, long long gtid,
+                               long long nthreads) {
   const long long rho = a.nsets;
   unsigned long long bm[kWMax];
 #pragma unroll
-  for (int w = 0; w < kWMax; ++w) bm[w] = (w < W) ? batch_mask(count, w) : 0ULL;
+  for (int w = 0; w < kWMax; ++w) bm[w] = (w < W) ? (batch_mask(count, w) & live[w]) : 0ULL;
   for (long long u = gtid; u < a.n; u += nthreads) {
     const int p0 = a.rp[u], p1 = a.rp[u + 1];
     if (p0 == p1) continue;
@@ -236,7 +333,9 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
   __shared__ unsigned long long qbase;
   __shared__ MsExpandRec rec[kMsMaxExpand];
   __shared__ int nrec;
+  __shared__ unsigned long long lds_live[kWMax];  // OR of this block's new words
   if (threadIdx.x == 0) nrec = 0;
+  if (threadIdx.x < kWMax) lds_live[threadIdx.x] = 0ULL;
   const int W = bt.W;
   const long long rho = a.nsets;
   const uint32_t tau = static_cast<uint32_t>(a.tau);
@@ -283,6 +382,8 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
           }
           if (mine) a.act[s * W + w] = Aw;
           A_any |= Aw;
+          if (Aw & ~lds_live[w])
+            __hip_atomic_fetch_or(&lds_live[w], Aw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           // int16 levels: for each traversal c with new vertices in this set,
           // write the set's vertices (8 contiguous int16 when not reordered).
           if (a.levels16 && Aw && !overflow) {
@@ -367,6 +468,11 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
     }
   }
   block_sum64<BLOCK, 3>(st, lds64);
+  __syncthreads();
+  if (threadIdx.x < W) {
+    const unsigned long long v = lds_live[threadIdx.x];
+    if (v) __hip_atomic_fetch_or(acc + F_LIVE * kPad + threadIdx.x, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   if (threadIdx.x == 0) {
     if (st[0]) {
       add_u64(acc + F_FRONTIER * kPad, st[0]);
@@ -395,8 +501,11 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
 
 template <int SIGMA, class SliceT, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
+  extern __shared__ float s_mlp[];
   __shared__ unsigned long long lds_f[(BLOCK / 64) * SIGMA * kWMax];
   __shared__ int lds_cnt[64 * kWMax];
+  const bool learned = a.policy == BLEST_POLICY_LEARNED && a.mlp != nullptr && a.mlp->valid;
+  if (learned) mlp_to_lds(a.mlp, s_mlp);
   const long long nthreads = static_cast<long long>(gridDim.x) * BLOCK;
   const long long gtid = static_cast<long long>(blockIdx.x) * BLOCK + threadIdx.x;
   const int wave = wave_in_block();
@@ -410,6 +519,7 @@ __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
   BarrierCtx bc;
   if (!barrier_register(a.ctl, &bc, a.timeout_ticks)) return;
   int total_levels = 0;
+  int nrec = 0;  // level records written so far (the same count in every workgroup)
   for (int bi = 0; bi < a.nbatches; ++bi) {
     const MsBatch bt = a.batches[bi];
     const int W = bt.W;
@@ -425,8 +535,7 @@ __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
       for (int c = threadIdx.x; c < 2 * 64 * kWMax; c += BLOCK) part[c] = 0;
     }
     if (blockIdx.x == 0)
-      for (int t = threadIdx.x; t < kStatSlots * kStatFields; t += BLOCK)
-        a.ctl->acc[t / kStatFields][t % kStatFields][0] = 0ULL;
+      for (int t = 0; t < kStatSlots; ++t) ms_clear_slot(a.ctl, t);
     if (!grid_barrier(a.ctl, bc)) return;
     // seed: mark each source in its own traversal's bit
     for (long long c = gtid; c < bt.count; c += nthreads) {
@@ -445,40 +554,50 @@ __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
       const long long fresh = static_cast<long long>(accr[F_FRONTIER * kPad]);
       if (fresh == 0) break;
       const long long qlen = static_cast<long long>(accr[F_QUEUE * kPad]);
+      const long long qslices = static_cast<long long>(accr[F_QSLICES * kPad]);
       const long long cumv = static_cast<long long>(accr[F_CUMV * kPad]);
-      int engine;
-      switch (a.policy) {
-        case BLEST_POLICY_BVSS:
-        case BLEST_POLICY_PUSH:
-          engine = BLEST_ENGINE_BVSS;
-          break;
-        case BLEST_POLICY_BOTTOM_UP:
-          engine = BLEST_ENGINE_BOTTOM_UP;
-          break;
-        case BLEST_POLICY_RANDOM:
-          engine = (mix64_ms(a.seed + 0x9E3779B97F4A7C15ULL * static_cast<unsigned long long>(level + 1 + 977 * bi)) & 1ULL)
-                       ? BLEST_ENGINE_BOTTOM_UP
-                       : BLEST_ENGINE_BVSS;
-          break;
-        default:
-          // Eq. 3 counted in (vertex, traversal) pairs: the bottom-up engine
-          // reads W frontier words per scanned edge and rarely stops early
-          // while many traversals are open, so it is chosen only once fewer
-          // than eta * |Q| pairs remain unvisited.
-          engine = (static_cast<double>(pairs_total - cumv) < static_cast<double>(a.eta) * static_cast<double>(qlen))
-                       ? BLEST_ENGINE_BOTTOM_UP
-                       : BLEST_ENGINE_BVSS;
-          break;
+      const int live = ms_live_count(a.ctl, slot);
+      const unsigned long long* live_w = accr + F_LIVE * kPad;
+      float feat[kMaxSwitchFeatures];
+      ms_features(feat, a, fresh, qlen, qslices, pairs_total - cumv, bt.count, live);
+      int fallback = 0;
+      const int engine = ms_choose(a, feat, qlen, pairs_total - cumv, level, bi, learned ? s_mlp : nullptr, &fallback);
+      if (blockIdx.x == 0) ms_clear_slot(a.ctl, (level + 1) % kStatSlots);
+      MsLevelRec* rec = (a.log && nrec < a.log_cap) ? a.log + nrec : nullptr;
+      if (blockIdx.x == 0 && threadIdx.x == 0 && rec) {
+        rec->batch = bi;
+        rec->level = level;
+        rec->engine = a.probe ? -1 : engine;
+        rec->fallback = fallback;
+        rec->width = bt.count;
+        rec->live = live;
+        rec->fresh = fresh;
+        rec->queue = qlen;
+        rec->qslices = qslices;
+        rec->unvisited = pairs_total - cumv;
+        rec->t_engine[0] = rec->t_engine[1] = 0ULL;
+        for (int k = 0; k < kMaxSwitchFeatures; ++k) rec->feat[k] = feat[k];
       }
-      if (blockIdx.x == 0) {
-        const int nslot = (level + 1) % kStatSlots;
-        for (int t = threadIdx.x; t < kStatFields; t += BLOCK) a.ctl->acc[nslot][t][0] = 0ULL;
-      }
-      if (engine == BLEST_ENGINE_BVSS)
+      ++nrec;
+      if (a.probe) {
+        // both engines from the same state: their marks are the same set
+        const unsigned long long t0 = dev_ticks();
         ms_engine_bvss<SIGMA, SliceT>(a, a.queue[level & 1], qlen, W, gwave, nwaves, my_f);
-      else
-        ms_engine_pull<SIGMA>(a, W, bt.count, gtid, nthreads);
-      if (!grid_barrier(a.ctl, bc)) return;
+        if (!grid_barrier(a.ctl, bc)) return;
+        const unsigned long long t1 = dev_ticks();
+        ms_engine_pull<SIGMA>(a, W, bt.count, live_w, gtid, nthreads);
+        if (!grid_barrier(a.ctl, bc)) return;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && rec) {
+          rec->t_engine[0] = t1 - t0;
+          rec->t_engine[1] = dev_ticks() - t1;
+        }
+      } else {
+        if (engine == BLEST_ENGINE_BVSS)
+          ms_engine_bvss<SIGMA, SliceT>(a, a.queue[level & 1], qlen, W, gwave, nwaves, my_f);
+        else
+          ms_engine_pull<SIGMA>(a, W, bt.count, live_w, gtid, nthreads);
+        if (!grid_barrier(a.ctl, bc)) return;
+      }
       ms_finalize<SIGMA, BLOCK>(a, bt, level + 1, (level + 1) % kStatSlots, (level & 1) ^ 1, cumv, lds_cnt,
                                 count_sources);
       if (!grid_barrier(a.ctl, bc)) return;
@@ -505,6 +624,7 @@ __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
     if (threadIdx.x < 8) a.ctl->xcd_blocks[threadIdx.x][0] = 0u;
     if (threadIdx.x == 8) a.ctl->xcd_active[0] = 0u;
     if (threadIdx.x == 0) a.ctl->nlevels[0] = total_levels;
+    if (threadIdx.x == 0) a.ctl->ms_nrec[0] = nrec;
   }
 }
 
@@ -523,12 +643,14 @@ constexpr int kMsGraphKernels = 32;  // kernels per captured graph (even)
 
 template <int SIGMA, class SliceT, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_ms_phase(MsArgs a, int parity) {
+  extern __shared__ float s_mlp[];
   __shared__ unsigned long long lds_f[(BLOCK / 64) * SIGMA * kWMax];
   __shared__ int lds_cnt[64 * kWMax];
   const int phase = a.ctl->ms_state[parity][0];
   const int bi = a.ctl->ms_state[parity][1];
   const int level = a.ctl->ms_state[parity][2];
-  int next[3] = {MS_DONE, bi, level};
+  const int nrec = a.ctl->ms_state[parity][3];
+  int next[4] = {MS_DONE, bi, level, nrec};
   if (phase != MS_DONE) {
     const long long nthreads = static_cast<long long>(gridDim.x) * BLOCK;
     const long long gtid = static_cast<long long>(blockIdx.x) * BLOCK + threadIdx.x;
@@ -556,8 +678,7 @@ __global__ void __launch_bounds__(BLOCK) k_ms_phase(MsArgs a, int parity) {
           for (int q = threadIdx.x; q < 2 * 64 * kWMax; q += BLOCK) part[q] = 0;
         }
         if (blockIdx.x == 0)
-          for (int t = threadIdx.x; t < kStatSlots * kStatFields; t += BLOCK)
-            a.ctl->acc[t / kStatFields][t % kStatFields][0] = 0ULL;
+          for (int t = 0; t < kStatSlots; ++t) ms_clear_slot(a.ctl, t);
         next[0] = MS_SEED;
         break;
       case MS_SEED:
@@ -582,37 +703,42 @@ __global__ void __launch_bounds__(BLOCK) k_ms_phase(MsArgs a, int parity) {
           break;
         }
         const long long qlen = static_cast<long long>(accr[F_QUEUE * kPad]);
+        const long long qslices = static_cast<long long>(accr[F_QSLICES * kPad]);
         const long long cumv = static_cast<long long>(accr[F_CUMV * kPad]);
-        const long long pairs_total = static_cast<long long>(bt.count) * a.n;
-        int engine;
-        switch (a.policy) {
-          case BLEST_POLICY_BVSS:
-          case BLEST_POLICY_PUSH:
-            engine = BLEST_ENGINE_BVSS;
-            break;
-          case BLEST_POLICY_BOTTOM_UP:
-            engine = BLEST_ENGINE_BOTTOM_UP;
-            break;
-          case BLEST_POLICY_RANDOM:
-            engine = (mix64_ms(a.seed + 0x9E3779B97F4A7C15ULL * static_cast<unsigned long long>(level + 1 + 977 * bi)) &
-                      1ULL)
-                         ? BLEST_ENGINE_BOTTOM_UP
-                         : BLEST_ENGINE_BVSS;
-            break;
-          default:
-            engine = (static_cast<double>(pairs_total - cumv) < static_cast<double>(a.eta) * static_cast<double>(qlen))
-                         ? BLEST_ENGINE_BOTTOM_UP
-                         : BLEST_ENGINE_BVSS;
-            break;
+        const long long unv = static_cast<long long>(bt.count) * a.n - cumv;
+        const bool learned = a.policy == BLEST_POLICY_LEARNED && a.mlp != nullptr && a.mlp->valid;
+        if (learned) {
+          mlp_to_lds(a.mlp, s_mlp);
+          __syncthreads();
         }
+        const int live = ms_live_count(a.ctl, level % kStatSlots);
+        float feat[kMaxSwitchFeatures];
+        ms_features(feat, a, fresh, qlen, qslices, unv, bt.count, live);
+        int fallback = 0;
+        const int engine = ms_choose(a, feat, qlen, unv, level, bi, learned ? s_mlp : nullptr, &fallback);
         if (blockIdx.x == 0) {
-          const int nslot = (level + 1) % kStatSlots;
-          for (int t = threadIdx.x; t < kStatFields; t += BLOCK) a.ctl->acc[nslot][t][0] = 0ULL;
+          ms_clear_slot(a.ctl, (level + 1) % kStatSlots);
+          if (threadIdx.x == 0 && a.log && nrec < a.log_cap) {
+            MsLevelRec* rec = a.log + nrec;
+            rec->batch = bi;
+            rec->level = level;
+            rec->engine = engine;
+            rec->fallback = fallback;
+            rec->width = bt.count;
+            rec->live = live;
+            rec->fresh = fresh;
+            rec->queue = qlen;
+            rec->qslices = qslices;
+            rec->unvisited = unv;
+            rec->t_engine[0] = rec->t_engine[1] = 0ULL;
+            for (int k = 0; k < kMaxSwitchFeatures; ++k) rec->feat[k] = feat[k];
+          }
         }
+        next[3] = nrec + 1;
         if (engine == BLEST_ENGINE_BVSS)
           ms_engine_bvss<SIGMA, SliceT>(a, a.queue[level & 1], qlen, W, gwave, nwaves, my_f);
         else
-          ms_engine_pull<SIGMA>(a, W, bt.count, gtid, nthreads);
+          ms_engine_pull<SIGMA>(a, W, bt.count, accr + F_LIVE * kPad, gtid, nthreads);
         next[0] = MS_FIN;
         break;
       }
@@ -639,18 +765,18 @@ __global__ void __launch_bounds__(BLOCK) k_ms_phase(MsArgs a, int parity) {
             if (a.cc) a.cc[row] = su ? static_cast<double>(re - 1) / static_cast<double>(su) : 0.0;
           }
         }
-        if (blockIdx.x == 0 && threadIdx.x == 0 && level > a.ctl->nlevels[0]) a.ctl->nlevels[0] = level;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          if (level > a.ctl->nlevels[0]) a.ctl->nlevels[0] = level;
+          a.ctl->ms_nrec[0] = nrec;
+        }
         next[0] = bi + 1 < a.nbatches ? MS_INIT : MS_DONE;
         next[1] = bi + 1;
         next[2] = 0;
         break;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.ctl->ms_state[parity ^ 1][0] = next[0];
-    a.ctl->ms_state[parity ^ 1][1] = next[1];
-    a.ctl->ms_state[parity ^ 1][2] = next[2];
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    for (int i = 0; i < 4; ++i) a.ctl->ms_state[parity ^ 1][i] = next[i];
 }
 
 __global__ void k_ms_start(Ctl* ctl) {
@@ -658,7 +784,9 @@ __global__ void k_ms_start(Ctl* ctl) {
     ctl->ms_state[0][0] = MS_INIT;
     ctl->ms_state[0][1] = 0;
     ctl->ms_state[0][2] = 0;
+    ctl->ms_state[0][3] = 0;
     ctl->nlevels[0] = 0;
+    ctl->ms_nrec[0] = 0;
   }
 }
 
@@ -687,6 +815,7 @@ const void* ms_fn_block(int block) {
 // The multi-source kernel keeps sigma words per slice set live in Stage 2;
 // 512-thread blocks leave it enough registers to avoid spilling at sigma 8.
 constexpr int kMsBlock = 512;
+constexpr int kMsLogCap = 1 << 16;  // level records per call
 
 const void* ms_kernel(const DevGraph& g) {
   if (g.sigma == 8 && !g.wide) return ms_fn_block<8, uint32_t>(kMsBlock);
@@ -732,12 +861,18 @@ hipError_t ensure(const DevGraph& g, MsDev* ms, int wmax, int32_t k, int nbatche
   }
   if (ms->grid == 0) {
     int nb = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ms_kernel(g), kMsBlock, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ms_kernel(g), kMsBlock,
+                                                                 kLdsMlpFloats * sizeof(float));
     if (e != hipSuccess) return e;
     if (nb < 1) return hipErrorInvalidConfiguration;
     nb = std::min(nb, 2);
     ms->grid = nb * g.num_cu;
     ms->block = kMsBlock;
+  }
+  if (!ms->log) {
+    hipError_t e = hipMalloc(&ms->log, sizeof(MsLevelRec) * static_cast<size_t>(kMsLogCap));
+    if (e != hipSuccess) return e;
+    ms->log_cap = kMsLogCap;
   }
   if (ms->part_blocks < ms->grid) {
     if (ms->part) (void)hipFree(ms->part);
@@ -753,7 +888,7 @@ hipError_t ensure(const DevGraph& g, MsDev* ms, int wmax, int32_t k, int nbatche
 
 hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, const int32_t* widths, int nwidths,
                   int policy, float eta, uint64_t seed, int16_t* levels16, int64_t* sums, int64_t* reach, double* cc,
-                  hipStream_t st, int graph, int64_t* far) {
+                  hipStream_t st, int graph, int64_t* far, int probe) {
   if (k <= 0) return hipSuccess;
   std::vector<MsBatch> plan;
   int32_t off = 0;
@@ -799,15 +934,22 @@ hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, 
   a.reach = reach;
   a.cc = cc;
   a.far = far;
+  a.nvss = g.nvss;
+  a.nslices = g.nslices;
+  a.mlp = g.ms_mlp;
+  a.probe = probe;
+  a.log = ms->log;
+  a.log_cap = ms->log_cap;
   a.part = ms->part;
   a.ctl = g.ctl;
   a.policy = policy;
   a.eta = eta;
   a.seed = seed;
   a.timeout_ticks = 3000000000ULL;  // 30 s
-  if (!graph) {
+  const unsigned shmem = policy == BLEST_POLICY_LEARNED ? kLdsMlpFloats * sizeof(float) : 0u;
+  if (!graph || probe) {
     void* args[] = {static_cast<void*>(&a)};
-    return hipLaunchCooperativeKernel(ms_kernel(g), dim3(ms->grid), dim3(ms->block), args, 0, st);
+    return hipLaunchCooperativeKernel(ms_kernel(g), dim3(ms->grid), dim3(ms->block), args, shmem, st);
   }
   // Graph mode: capture kMsGraphKernels phase kernels plus a copy of the state
   // and error words to pinned host memory on a stream of our own (the caller's
@@ -837,7 +979,7 @@ hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, 
     par[i] = i & 1;
     kargs[i][0] = static_cast<void*>(&a);
     kargs[i][1] = static_cast<void*>(&par[i]);
-    (void)hipLaunchKernel(fn, dim3(ms->grid), dim3(kMsBlock), kargs[i], 0, gs);
+    (void)hipLaunchKernel(fn, dim3(ms->grid), dim3(kMsBlock), kargs[i], shmem, gs);
   }
   (void)hipMemcpyAsync(flags + 2, &g.ctl->ms_state[0][0], sizeof(int), hipMemcpyDeviceToHost, gs);
   (void)hipMemcpyAsync(flags + 3, &g.ctl->error[0], sizeof(int), hipMemcpyDeviceToHost, gs);
@@ -883,6 +1025,9 @@ void ms_free_all(MsDev* ms) {
   if (ms->srcs) (void)hipFree(ms->srcs);
   if (ms->part) (void)hipFree(ms->part);
   if (ms->batches) (void)hipFree(ms->batches);
+  if (ms->log) (void)hipFree(ms->log);
+  ms->log = nullptr;
+  ms->log_cap = 0;
   ms->srcs = nullptr;
   ms->part = nullptr;
   ms->batches = nullptr;

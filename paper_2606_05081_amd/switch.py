@@ -285,6 +285,163 @@ def evaluate_graph(kind, size, seed, params, mean, std, n_sources=16, log=print)
     return res
 
 
+# ---------------------------------------------------------------- multi-source
+# The same network type decides each level of each multi-source batch (Alg. 5)
+# between the BVSS top-down engine (output 0) and the bottom-up engine
+# (output 2); the fallback is the pairs form of Eq. 3 (bottom-up iff fewer than
+# eta * |Q| (vertex, traversal) pairs are unvisited). Its 12 inputs are the
+# ones blest_ms_level_stat.feat documents; probe-mode multi-source calls time
+# both engines from the same state at every level of every batch.
+MS_MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "switch_model_ms.json")
+MS_FEATURES = ["log(1+new pairs)", "log(1+queued slices)", "log new pairs/all pairs", "log |Q|/N_v",
+               "log queued slices/all slices", "log unvisited pairs/all pairs", "log batch width",
+               "log |Q|/unvisited pairs", "log live traversals/batch width", "reserved", "reserved", "reserved"]
+MS_ENGINES = ["bvss", "bottom_up"]
+MS_WIDTHS = (64, 128, 256, 512)
+MS_TRAIN_SPECS = ([("rmat", s, 3000 + s) for s in (16, 17, 18, 19, 20, 21)] +
+                  [("grid", side, 3100 + i) for i, side in enumerate((256, 384, 512))])
+MS_EVAL_SPECS = [("rmat", 22, 3040), ("er", 20, 3042), ("grid", 768, 3044)]
+
+
+def ms_rule(rec, eta=10.0):
+    """Pairs rule as an index into MS_ENGINES."""
+    return 1 if rec["unvisited_pairs"] < eta * rec["queue"] else 0
+
+
+def probe_ms(g, srcs, widths, max_rows=None, rng=None):
+    """Probe-mode multi-source rows: (features[12], times[2] (BVSS, bottom-up),
+    pairs-rule index, batch width)."""
+    g.msbfs_probe(srcs, widths)
+    recs = [r for r in g.ms_level_stats() if min(r["t_engine_us"]) > 0]
+    if max_rows is not None and len(recs) > max_rows:
+        keep = np.sort((rng or np.random.default_rng(0)).choice(len(recs), max_rows, replace=False))
+        recs = [recs[i] for i in keep]
+    X = np.array([r["feat"] for r in recs], np.float32).reshape(-1, 12)
+    T = np.array([r["t_engine_us"] for r in recs], np.float32).reshape(-1, 2)
+    H = np.array([ms_rule(r) for r in recs], np.int32)
+    W = np.array([r["width"] for r in recs], np.int32)
+    return X, T, H, W
+
+
+def ms_width_plan(cycles):
+    """Sources and batch widths that visit every width `cycles` times."""
+    widths = list(MS_WIDTHS) * cycles
+    return sum(widths), widths
+
+
+def ms_predict(params, mean, std, X, min_confidence=MIN_CONFIDENCE):
+    """Network choices as MS_ENGINES indices; -1 where the kernel uses the pairs rule."""
+    ch = predict(params, mean, std, X, min_confidence)
+    return np.where(ch == 0, 0, np.where(ch == 2, 1, -1)).astype(np.int32)
+
+
+def build_ms_dataset(specs=MS_TRAIN_SPECS, cycles=3, grid_rows=800, log=print):
+    from . import blest, inputs
+    Xs, Ts, Hs, fam = [], [], [], []
+    k, widths = ms_width_plan(cycles)
+    for kind, size, seed in specs:
+        t0 = time.time()
+        rp, col = make_graph(kind, size, seed)
+        g = blest.Graph(rp, col)
+        srcs = inputs.sources(rp, k, seed=seed + 500)
+        X, T, Hc, _ = probe_ms(g, srcs, widths, grid_rows if kind == "grid" else None, np.random.default_rng(seed))
+        g.close()
+        Xs.append(X)
+        Ts.append(T)
+        Hs.append(Hc)
+        fam += [kind] * len(X)
+        log(f"[ms-dataset] {kind} {size} seed {seed}: {len(X)} levels in {time.time() - t0:.1f}s", flush=True)
+    return np.concatenate(Xs), np.concatenate(Ts), np.concatenate(Hs), np.array(fam)
+
+
+def train_ms(X, T, Hc, fam, steps=4000, seed=1):
+    """Labels (0 = BVSS, 2 = bottom-up) and cost weights as for the single-source
+    network, then the same GPU training."""
+    y2 = labels_from_times(T, Hc)
+    w = cost_weights(T, fam)
+    return train(X, (2 * y2).astype(np.int32), w, steps=steps, seed=seed), y2
+
+
+def ms_time(g, srcs, widths, policy, reps=1):
+    """Device time (ms) of blest_msbfs_batched over srcs with the given policy."""
+    import torch
+    from . import blest
+    g.set_policy(policy)
+    out = torch.empty(len(srcs) * g.n, dtype=torch.int16, device="cuda")
+    g.msbfs_batched(srcs, widths, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.msbfs_batched(srcs, widths, out)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def ms_per_graph_enable(g, srcs, width=512, trials=1):
+    """Trial batches decide per graph, as for single-source BFS: the learned
+    policy stays on only if its trial batches take less device time."""
+    from . import blest
+    srcs = np.asarray(srcs)[: width * trials]
+    t = {name: ms_time(g, srcs, [width], pol)
+         for name, pol in (("heuristic", blest.Policy.HEURISTIC), ("learned", blest.Policy.LEARNED))}
+    return t["learned"] < t["heuristic"], t
+
+
+def evaluate_ms_graph(kind, size, seed, params, mean, std, cycles=2, n_timed=2048, log=print):
+    """Probe regret of both choices and end-to-end sources/s of both policies."""
+    from . import blest, inputs
+    rp, col = make_graph(kind, size, seed)
+    g = blest.Graph(rp, col)
+    g.set_ms_switch_model(params, mean, std, MIN_CONFIDENCE)
+    k, widths = ms_width_plan(cycles)
+    X, T, Hc, _ = probe_ms(g, inputs.sources(rp, k, seed=seed + 1), widths)
+    ch = ms_predict(params, mean, std, X)
+    ch = np.where(ch < 0, Hc, ch)
+    res = {"graph": f"{kind}{size}", "levels": int(len(X)), "regret_learned": regret(T, ch),
+           "regret_heuristic": regret(T, Hc), "misclassified_learned": float((ch != T.argmin(1)).mean()),
+           "misclassified_heuristic": float((Hc != T.argmin(1)).mean())}
+    srcs = inputs.sources(rp, n_timed, seed=seed + 2)
+    for name, pol in (("heuristic", blest.Policy.HEURISTIC), ("learned", blest.Policy.LEARNED)):
+        res[f"sources_per_s_{name}"] = len(srcs) / (ms_time(g, srcs, [512], pol) * 1e-3)
+    res["learned_over_heuristic"] = res["sources_per_s_learned"] / res["sources_per_s_heuristic"]
+    enabled, trial_ms = ms_per_graph_enable(g, inputs.sources(rp, 512, seed=seed + 3))
+    res["learned_enabled"] = bool(enabled)
+    res["trial_ms"] = trial_ms
+    g.close()
+    log(f"[ms-eval] {res}", flush=True)
+    res["probe"] = {"X": X, "T": T, "H": Hc}
+    return res
+
+
+def main_ms(args):
+    X, T, Hc, fam = build_ms_dataset(cycles=args.ms_cycles)
+    t0 = time.time()
+    (params, mean, std, losses), y2 = train_ms(X, T, Hc, fam, steps=args.steps)
+    ch = ms_predict(params, mean, std, X)
+    ch = np.where(ch < 0, Hc, ch)
+    meta = {"levels": int(len(y2)), "label_counts": np.bincount(y2, minlength=2).tolist(),
+            "train_loss_first": float(losses[:50].mean()), "train_loss_last": float(losses[-50:].mean()),
+            "train_regret_learned": regret(T, ch), "train_regret_heuristic": regret(T, Hc),
+            "steps": args.steps, "specs": MS_TRAIN_SPECS, "widths": list(MS_WIDTHS)}
+    print(f"[ms-train] {time.time() - t0:.1f}s {meta}", flush=True)
+    with open(args.out, "w") as f:
+        json.dump({"params": [float(x) for x in params], "mean": [float(x) for x in mean],
+                   "std": [float(x) for x in std], "min_confidence": MIN_CONFIDENCE, "features": MS_FEATURES,
+                   "engines": ["bvss", "push (unused)", "bottom_up"], "meta": meta}, f)
+    if args.dataset_out:
+        np.savez(args.dataset_out, X=X, T=T, H=Hc, fam=fam)
+    if args.eval:
+        probes = {}
+        for kind, size, seed in MS_EVAL_SPECS:
+            r = evaluate_ms_graph(kind, size, seed, params, mean, std)
+            for k, v in r.pop("probe").items():
+                probes[f"{r['graph']}_{k}"] = v
+        if args.dataset_out:
+            np.savez(args.dataset_out.replace(".npz", "_eval.npz"), **probes)
+
+
 def main(argv=None):
     import argparse
     ap = argparse.ArgumentParser(description="train and evaluate the learned engine switch (GPU)")
@@ -293,7 +450,13 @@ def main(argv=None):
     ap.add_argument("--out", default=MODEL_PATH)
     ap.add_argument("--dataset-out", default=None)
     ap.add_argument("--eval", action="store_true")
+    ap.add_argument("--ms", action="store_true", help="the multi-source network (switch_model_ms.json)")
+    ap.add_argument("--ms-cycles", type=int, default=3)
     args = ap.parse_args(argv)
+    if args.ms:
+        if args.out == MODEL_PATH:
+            args.out = MS_MODEL_PATH
+        return main_ms(args)
     X, T, Hc, fam = build_dataset(runs_per_graph=args.runs_per_graph)
     y = labels_from_times(T, Hc)
     w = cost_weights(T, fam)

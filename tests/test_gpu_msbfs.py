@@ -235,3 +235,110 @@ def test_msbfs_graph_mode_overflow(blest):
     assert ei.value.status == blest.Status.OVERFLOW
     assert np.array_equal(g.msbfs([16000]).cpu().numpy(), oracle.msbfs16(rp, col, [16000]))
     g.close()
+
+
+def _random_model(seed):
+    """Untrained weights scaled so the network is often confident; std 8 keeps
+    every standardised feature of these graphs inside [-6, 6]."""
+    from paper_2606_05081_amd import switch
+    params = (switch.init_params(seed) * 4.0).astype(np.float32)
+    return params, np.zeros(12, np.float32), np.full(12, 8.0, np.float32)
+
+
+def test_msbfs_probe_levels_and_records(blest):
+    rp, col = inputs.rmat_graph(13, 61)
+    srcs = inputs.sources(rp, 300, seed=62)
+    ref = oracle.msbfs16(rp, col, srcs)
+    g = blest.Graph(rp, col)
+    got = g.msbfs_probe(srcs, [64, 128, 256]).cpu().numpy()
+    assert np.array_equal(got, ref)
+    recs = g.ms_level_stats()
+    # one record per level of every batch (64, 128, then the last 108 sources)
+    nb = [64, 128, 108]
+    per_batch = [int(ref[sum(nb[:b]):sum(nb[:b + 1])].max()) + 1 for b in range(3)]
+    assert [sum(1 for r in recs if r["batch"] == b) for b in range(3)] == per_batch
+    assert all(min(r["t_engine_us"]) > 0 for r in recs)
+    assert all(np.isfinite(r["feat"]).all() for r in recs)
+    assert [r["width"] for r in recs if r["level"] == 0] == nb
+    # new pairs per level equal the oracle's level counts; live traversals are
+    # those with a vertex at that level
+    for b in range(3):
+        rows = ref[sum(nb[:b]):sum(nb[:b + 1])]
+        rb = [r for r in recs if r["batch"] == b]
+        assert [r["new_pairs"] for r in rb] == [int((rows == l).sum()) for l in range(per_batch[b])]
+        assert [r["live"] for r in rb] == [int((rows == l).any(axis=1).sum()) for l in range(per_batch[b])]
+    g.close()
+
+
+@pytest.mark.parametrize("graph_mode", [0, 1])
+def test_msbfs_dead_traversals(blest, graph_mode):
+    """Sources in small components (isolated vertices, short paths) finish
+    after a level or two; the bottom-up engine then ignores their bits. Every
+    policy must still match the oracle, and the live counts must drop."""
+    rp0, col0 = inputs.rmat_graph(12, 81)
+    n0 = rp0.size - 1
+    src = np.repeat(np.arange(n0), np.diff(rp0))
+    keep = src < col0
+    extra_u = [n0, n0 + 1, n0 + 3]
+    extra_v = [n0 + 1, n0 + 2, n0 + 4]
+    rp, col = inputs.from_pairs(n0 + 6, np.concatenate([src[keep], extra_u]),
+                                np.concatenate([col0[keep], extra_v]))
+    assert np.array_equal(np.diff(rp)[:n0], np.diff(rp0))
+    big = inputs.sources(rp0, 120, seed=82)
+    small = np.array([n0, n0 + 2, n0 + 3, n0 + 5], np.int32)  # path ends, an edge, an isolated vertex
+    srcs = np.concatenate([small[:2], big[:60], small[2:], big[60:]]).astype(np.int32)
+    ref = oracle.msbfs16(rp, col, srcs)
+    g = blest.Graph(rp, col, msbfs_graph=graph_mode)
+    for pol in POLICIES:
+        g.set_policy(getattr(blest.Policy, pol), 10.0, 5)
+        got = g.msbfs_batched(srcs, [64]).cpu().numpy()
+        assert np.array_equal(got, ref), (pol, np.argwhere(got != ref)[:5])
+        recs = [r for r in g.ms_level_stats() if r["batch"] == 0]
+        rows = ref[:64]
+        assert [r["live"] for r in recs] == [int((rows == l).any(axis=1).sum()) for l in range(len(recs))]
+        assert recs[0]["live"] == 64 and recs[2]["live"] <= 62
+    g.close()
+
+
+@pytest.mark.parametrize("graph_mode", [0, 1])
+def test_msbfs_learned_policy_exact_and_inference(blest, graph_mode):
+    """Policy LEARNED with arbitrary weights changes only the engines, never
+    the results; the engine recorded per level is the oracle network's choice
+    (pairs rule where the network declines: confidence or non-BVSS/BU output)."""
+    from oracle import mlp as omlp
+    rp, col = inputs.rmat_graph(13, 71)
+    srcs = inputs.sources(rp, 400, seed=72)
+    ref = oracle.msbfs16(rp, col, srcs)
+    osum, oreach, occ = oracle.closeness(rp, col, srcs)
+    blest.blest_set_switch_confidence(None, 0.5)
+    used = {0: 0, 1: 0}
+    for seed in (1, 2, 3):
+        params, mean, std = _random_model(seed)
+        g = blest.Graph(rp, col, msbfs_graph=graph_mode)
+        g.set_ms_switch_model(params, mean, std)
+        g.set_policy(blest.Policy.LEARNED)
+        got = g.msbfs_batched(srcs, [64, 256, 512]).cpu().numpy()
+        assert np.array_equal(got, ref), seed
+        recs = g.ms_level_stats()
+        for r in recs:
+            z = (np.asarray(r["feat"], np.float64) - mean) / std
+            logits, _ = omlp.forward(params.astype(np.float64), z[None, :])
+            lg = logits[0]
+            p = np.exp(lg - lg.max())
+            p /= p.sum()
+            c = int(np.argmax(lg))
+            rule = 2 if r["unvisited_pairs"] < 10.0 * r["queue"] else 0
+            ood = (np.abs(z) > 6).any()
+            sure = p.max() >= 0.5 + 1e-4
+            if not ood and sure and c in (0, 2) and abs(np.sort(lg)[-1] - np.sort(lg)[-2]) > 1e-4:
+                assert r["engine"] == c and r["mlp_fallback"] == 0, r
+                used[0] += 1
+            elif ood or p.max() < 0.5 - 1e-4 or c == 1:
+                assert r["engine"] == rule and r["mlp_fallback"] == 1, r
+                used[1] += 1
+        s, rr, cc = g.closeness(srcs)
+        assert np.array_equal(s.cpu().numpy(), osum)
+        assert np.array_equal(rr.cpu().numpy(), oreach)
+        assert np.array_equal(cc.cpu().numpy(), occ)
+        g.close()
+    assert used[0] > 0 and used[1] > 0, used

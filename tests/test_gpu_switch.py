@@ -74,3 +74,38 @@ def test_committed_model_on_held_out_graphs(env, capsys):
         s = int(inputs.sources(rp, 1, seed=seed + 2)[0])
         assert np.array_equal(g.bfs(s).cpu().numpy(), oracle.bfs(rp, col, s))
         g.close()
+
+
+def test_multi_source_committed_model_on_held_out_graphs(env, capsys):
+    """The multi-source network (switch_model_ms.json) against the pairs rule
+    on graphs outside its training set: probe regret from the same timings,
+    end-to-end device time of both policies, and exact closeness with it."""
+    blest, switch = env
+    if not os.path.exists(switch.MS_MODEL_PATH):
+        pytest.skip("no multi-source model committed yet (python -m paper_2606_05081_amd.switch --ms)")
+    params, mean, std, meta = switch.load_model(switch.MS_MODEL_PATH)
+    conf = meta.get("min_confidence", 0.5)
+    for kind, size, seed in [("rmat", 20, 4930), ("grid", 640, 4931)]:
+        rp, col = switch.make_graph(kind, size, seed)
+        g = blest.Graph(rp, col)
+        g.set_ms_switch_model(params, mean, std, conf)
+        k, widths = switch.ms_width_plan(1)
+        X, T, H, _ = switch.probe_ms(g, inputs.sources(rp, k, seed=seed + 1), widths)
+        ch = switch.ms_predict(params, mean, std, X, conf)
+        ch = np.where(ch < 0, H, ch)
+        r_l, r_h = switch.regret(T, ch), switch.regret(T, H)
+        srcs = inputs.sources(rp, 1024, seed=seed + 2)
+        t_h = min(switch.ms_time(g, srcs, [512], blest.Policy.HEURISTIC) for _ in range(2))
+        t_l = min(switch.ms_time(g, srcs, [512], blest.Policy.LEARNED) for _ in range(2))
+        with capsys.disabled():
+            print(f"\n[ms-switch] {kind}{size}: regret learned {r_l:.4f} vs pairs rule {r_h:.4f}; "
+                  f"1024 sources {t_l:.2f} ms learned vs {t_h:.2f} ms pairs rule")
+        assert r_l <= r_h + 0.02
+        assert t_l <= t_h * 1.02
+        cs = inputs.sources(rp, 96, seed=seed + 3)
+        osum, oreach, occ = oracle.closeness(rp, col, cs)
+        g.set_policy(blest.Policy.LEARNED)
+        s_, r_, c_ = g.closeness(cs)
+        assert np.array_equal(s_.cpu().numpy(), osum) and np.array_equal(r_.cpu().numpy(), oreach)
+        assert np.array_equal(c_.cpu().numpy(), occ)
+        g.close()
