@@ -301,11 +301,13 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   } while (0)
   // rp is padded to N_s*sigma + 1 entries (tail = m) so a slice set's row
   // pointers can be read with aligned 16-byte loads.
+  // The fused panel step also reads whole 32-row groups (33 entries) and the
+  // 5 slice pointers of their 4 sets, hence the extra padding of both.
   const size_t rp_len = static_cast<size_t>(b.nsets) * o.sigma + 1;
-  TRY(dalloc_t(g, &d.rp, rp_len + 4));
+  TRY(dalloc_t(g, &d.rp, rp_len + 32));
   // col is padded by 4 entries: the bottom-up engine reads 4 neighbours at a time
   TRY(dalloc_t(g, &d.col, static_cast<size_t>(m) + 4));
-  TRY(dalloc_t(g, &d.slice_ptr, ns + 1));
+  TRY(dalloc_t(g, &d.slice_ptr, ns + 8));
   TRY(dalloc(g, &d.slices, static_cast<size_t>(std::max<int64_t>(b.nslices, 1)) * (wide ? 8 : 4)));
   TRY(dalloc(g, &d.degmask, ns * mb));
   // The panel engine reads visited words and writes mark bytes in whole
@@ -315,8 +317,14 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   // words starting at its first set (rounded down to 8).
   const size_t state_bytes = std::max(ns * mb, prow / 8) + 512;
   const size_t mark_bytes = std::max(ns * static_cast<size_t>(o.sigma), prow);
+  // the frontier is double-buffered by level parity: level l reads buffer
+  // l & 1 while Stage 2 (or the fused panel step) writes the other
+  const size_t fstride = (state_bytes + 255) / 256 * 256;
   TRY(dalloc(g, &d.vis, state_bytes));
-  TRY(dalloc(g, &d.front, state_bytes));
+  TRY(dalloc(g, &d.front, 2 * fstride));
+  TRY(hipMemset(d.vis, 0, state_bytes));
+  TRY(hipMemset(d.front, 0, 2 * fstride));
+  d.fstride = fstride;
   TRY(dalloc_t(g, &d.mark, mark_bytes));
   d.mark_bytes = mark_bytes;
   if (pn.npanels > 0) {

@@ -26,6 +26,34 @@
 
 namespace blest {
 
+// Frontier buffer of a level parity (level l reads buffer l & 1; its Stage 2
+// writes the other one, so an engine never reads words being rewritten).
+__device__ __forceinline__ void* front_buf(const BfsArgs& a, int sel) {
+  return static_cast<char*>(a.front) + (sel ? a.fstride : 0LL);
+}
+
+// Per-workgroup Stage 2 partial counters: frontier, queued slices, frontier
+// edges, deg >= 32, deg >= 1024, light, heavy and queue entries.
+constexpr int kParts = 8;
+
+// Row pointers rp[s*SIGMA .. s*SIGMA + SIGMA] of a slice set's vertices with
+// 16-byte loads. rp is padded on the device to N_s*SIGMA + 1 entries (the
+// tail repeats m), and s*SIGMA*4 is a multiple of 16, so the loads are aligned
+// and in bounds.
+template <int SIGMA>
+__device__ __forceinline__ void load_set_rp(gptr<const int32_t> rp, long long s, int (&r)[SIGMA + 1]) {
+  const gptr<const int4> p = (gptr<const int4>)(rp + s * SIGMA);
+#pragma unroll
+  for (int i = 0; i < SIGMA / 4; ++i) {
+    const int4 q = p[i];
+    r[4 * i + 0] = q.x;
+    r[4 * i + 1] = q.y;
+    r[4 * i + 2] = q.z;
+    r[4 * i + 3] = q.w;
+  }
+  r[SIGMA] = rp[s * SIGMA + SIGMA];
+}
+
 // ------------------------------------------------------------- decisions
 
 struct LevelView {
@@ -263,9 +291,14 @@ __device__ long long engine_bvss(const BfsArgs& a, const uint4* __restrict__ q, 
 // byte in an LDS byte map is set with a plain store (lazy marking is
 // idempotent, so no atomic is needed). Loads of the next batch of chunks are
 // issued before the current batch is tested. After the panel, the byte map
-// minus the visited words is written to the mark bytes, 32 rows per pair of
-// 16-byte stores; the workgroup owns those rows, so each new vertex is
-// written once and no visited word is read per hit.
+// minus the visited words gives the panel's new vertices; the workgroup owns
+// those rows, so each new vertex is handled once and no visited word is read
+// per hit. Either they are written to the mark bytes (32 rows per pair of
+// 16-byte stores) for Stage 2, or (fused, new_level >= 0) the workgroup does
+// Stage 2 for its rows itself: it updates the visited words, writes every
+// next-frontier word of the panel (buffer sel ^ 1), writes the levels and
+// stores its Stage 2 partial counters, so the grid needs no separate Stage 2
+// sweep and no second barrier for the level.
 // pm: LDS scratch of at least 2^rb bytes, left filled with ones (the
 // single-workgroup hash set shares it).
 constexpr int kPanelChunk = 256;      // slices per chunk (host layout)
@@ -315,8 +348,58 @@ __device__ __forceinline__ void panel_test4(const uint4& w, uint32_t b7, const u
   }
 }
 
+// Stage 2 for one 32-row group (four slice sets, sigma = 8) whose new
+// vertices are x: level writes and the counters of finalize_count. The 33
+// row pointers and 5 slice pointers of the group are loaded at once (rp and
+// slice_ptr are padded on the device so these loads stay in bounds).
+__device__ __forceinline__ void panel_count_group(const BfsArgs& a, long long g, uint32_t x, int new_level,
+                                                  long long (&st)[kParts]) {
+  const gptr<const int32_t> rp = to_global(a.rp);
+  const gptr<const uint32_t> sp = to_global(a.slice_ptr);
+  const gptr<int32_t> levels = to_global(a.levels);
+  const gptr<const int32_t> orig_id = to_global(a.orig_id);
+  const uint32_t tau = static_cast<uint32_t>(a.tau);
+  const gptr<const int4> r4 = (gptr<const int4>)(rp + 32 * g);
+  int r[33];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int4 q = r4[i];
+    r[4 * i + 0] = q.x;
+    r[4 * i + 1] = q.y;
+    r[4 * i + 2] = q.z;
+    r[4 * i + 3] = q.w;
+  }
+  r[32] = rp[32 * g + 32];
+  const uint4 s4 = *(gptr<const uint4>)(sp + 4 * g);
+  const uint32_t spt[5] = {s4.x, s4.y, s4.z, s4.w, sp[4 * g + 4]};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t xb = (x >> (8 * k)) & 0xffu;
+    if (!xb) continue;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      if (!((xb >> b) & 1u)) continue;
+      const long long u = 32 * g + 8 * k + b;
+      const int d = r[8 * k + b + 1] - r[8 * k + b];
+      st[0] += 1;
+      st[2] += d;
+      st[3] += d >= 32;
+      st[4] += d >= 1024;
+      if (d > kLightMax)
+        st[6] += (d + kHeavyChunk - 1) / kHeavyChunk;
+      else
+        st[5] += 1;
+      levels[orig_id ? orig_id[u] : u] = new_level;
+    }
+    const uint32_t ns = spt[k + 1] - spt[k];
+    st[1] += ns;
+    st[7] += (ns + tau - 1) / tau;
+  }
+}
+
 template <int BLOCK>
-__device__ __attribute__((noinline)) long long engine_panel(const BfsArgs& a, lptr<uint32_t> pm) {
+__device__ __attribute__((noinline)) long long engine_panel(const BfsArgs& a, lptr<uint32_t> pm, int sel,
+                                                            int new_level) {
   constexpr int U = kPanelUnroll;
   constexpr uint32_t NW = BLOCK / 64;
   constexpr uint32_t STEP = NW * U;
@@ -329,11 +412,17 @@ __device__ __attribute__((noinline)) long long engine_panel(const BfsArgs& a, lp
   const int rshift = 32 - rb;
   PanelPtrs pp;
   pp.words = to_global(reinterpret_cast<const uint4*>(a.pwords));
-  pp.front8 = to_global(static_cast<const uint2*>(a.front));
+  pp.front8 = to_global(static_cast<const uint2*>(front_buf(a, sel)));
   pp.base = to_global(static_cast<const uint32_t*>(a.pbase));
   const gptr<const uint32_t> pptr = to_global(static_cast<const uint32_t*>(a.pptr));
-  const gptr<const uint32_t> vis32 = to_global(static_cast<const uint32_t*>(a.vis));
+  const gptr<uint32_t> vis32 = to_global(static_cast<uint32_t*>(a.vis));
+  const gptr<uint32_t> next32 = to_global(static_cast<uint32_t*>(front_buf(a, sel ^ 1)));
   const gptr<uint4> mark16 = to_global(reinterpret_cast<uint4*>(a.mark));
+  const bool fused = new_level >= 0;
+  // fused: the workgroup's Stage 2 counters, summed per panel (kept out of
+  // registers during the chunk loop)
+  __shared__ unsigned long long s_part[kParts];
+  if (threadIdx.x < kParts) s_part[threadIdx.x] = 0ULL;
   const uint32_t lane = static_cast<uint32_t>(lane_id());
   const uint32_t wv = static_cast<uint32_t>(wave_in_block());
   long long work = 0;
@@ -389,9 +478,21 @@ __device__ __attribute__((noinline)) long long engine_panel(const BfsArgs& a, lp
     }
     __syncthreads();
     const size_t wb = static_cast<size_t>(p) * W;
+    long long st[kParts] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t j = threadIdx.x; j < W; j += BLOCK) {
       const uint32_t m = gather8(pm64[4 * j]) | (gather8(pm64[4 * j + 1]) << 8) | (gather8(pm64[4 * j + 2]) << 16) |
                          (gather8(pm64[4 * j + 3]) << 24);
+      if (fused) {
+        uint32_t x = 0;
+        if (m) {
+          const uint32_t old = vis32[wb + j];
+          x = m & ~old;
+          if (x) vis32[wb + j] = old | x;
+        }
+        next32[wb + j] = x;
+        if (x) panel_count_group(a, static_cast<long long>(wb + j), x, new_level, st);
+        continue;
+      }
       if (!m) continue;
       const uint32_t x = m & ~vis32[wb + j];
       if (!x) continue;
@@ -404,9 +505,25 @@ __device__ __attribute__((noinline)) long long engine_panel(const BfsArgs& a, lp
       mark16[2 * (wb + j)] = make_uint4(q[0], q[1], q[2], q[3]);
       mark16[2 * (wb + j) + 1] = make_uint4(q[4], q[5], q[6], q[7]);
     }
+    if (fused) {
+#pragma unroll
+      for (int f = 0; f < kParts; ++f) {
+        const long long t = wave_sum(st[f]);
+        if (lane == 0 && t)
+          __hip_atomic_fetch_add(&s_part[f], static_cast<unsigned long long>(t), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
     __syncthreads();
   }
   for (uint32_t j = threadIdx.x; j < 8 * W; j += BLOCK) pm[j] = 0xffffffffu;
+  if (fused) {
+    // every workgroup stores its partials (zero if it owns no panel)
+    __syncthreads();
+    if (threadIdx.x < kParts)
+      to_global(a.part)[static_cast<long long>(blockIdx.x) * kParts + threadIdx.x] =
+          static_cast<long long>(s_part[threadIdx.x]);
+  }
   return lane == 0 ? work : 0;
 }
 
@@ -482,11 +599,12 @@ __device__ __attribute__((noinline)) long long engine_push(const BfsArgs& a, int
 constexpr int kPullLight = 32;
 
 template <int SIGMA>
-__device__ __attribute__((noinline)) long long engine_pull(const BfsArgs& a, long long gtid, long long nthreads) {
+__device__ __attribute__((noinline)) long long engine_pull(const BfsArgs& a, int sel, long long gtid,
+                                                           long long nthreads) {
   long long work = 0;
   using M = typename MaskOf<SIGMA>::T;
   gptr<const M> __restrict__ vis = to_global(static_cast<const M*>(a.vis));
-  gptr<const M> __restrict__ front = to_global(static_cast<const M*>(a.front));
+  gptr<const M> __restrict__ front = to_global(static_cast<const M*>(front_buf(a, sel)));
   gptr<const M> __restrict__ degm = to_global(static_cast<const M*>(a.degmask));
   gptr<const int32_t> __restrict__ rp = to_global(a.rp);
   gptr<const int32_t> __restrict__ col = to_global(a.col);
@@ -554,15 +672,16 @@ __device__ __attribute__((noinline)) long long engine_pull(const BfsArgs& a, lon
 // hs != nullptr: single-workgroup level, marked slice sets are recorded in hs
 // (only the BVSS and push engines run there). pm: LDS scratch for the
 // panel-blocked BVSS step (nullptr: that step is not available).
+// fuse_level >= 0: a panel step also does Stage 2 for that new level.
 template <int SIGMA, class SliceT, int BLOCK>
 __device__ __forceinline__ void run_engine(const BfsArgs& a, int engine, int sel, int slot, const LevelView& v,
                                            long long gtid, long long nthreads, long long gwave, long long nwaves,
-                                           lptr<int> hs, lptr<uint32_t> pm) {
+                                           lptr<int> hs, lptr<uint32_t> pm, int fuse_level = -1) {
   __shared__ long long lds_work[BLOCK / 64];
   long long work[1];
   constexpr bool kPanelFmt = SIGMA == 8 && sizeof(SliceT) == 4;
   if (kPanelFmt && engine == BLEST_ENGINE_BVSS && !hs && pm && use_panel(a, v))
-    work[0] = engine_panel<BLOCK>(a, pm);
+    work[0] = engine_panel<BLOCK>(a, pm, sel, fuse_level);
   else if (engine == BLEST_ENGINE_BVSS)
     work[0] = hs ? engine_bvss<SIGMA, SliceT, true>(a, a.queue[sel], v.queue, gwave, nwaves, hs)
                  : engine_bvss<SIGMA, SliceT, false>(a, a.queue[sel], v.queue, gwave, nwaves, nullptr);
@@ -570,7 +689,7 @@ __device__ __forceinline__ void run_engine(const BfsArgs& a, int engine, int sel
     work[0] = hs ? engine_push<SIGMA, true>(a, sel, v.light, v.heavy, gtid, nthreads, gwave, nwaves, hs)
                  : engine_push<SIGMA, false>(a, sel, v.light, v.heavy, gtid, nthreads, gwave, nwaves, nullptr);
   else
-    work[0] = engine_pull<SIGMA>(a, gtid, nthreads);
+    work[0] = engine_pull<SIGMA>(a, sel, gtid, nthreads);
   if (a.count_work || a.probe) {
     block_sum64<BLOCK, 1>(work, lds_work);
     if (threadIdx.x == 0 && work[0]) add_u64(&a.ctl->acc[slot][F_WORK][0], static_cast<unsigned long long>(work[0]));
@@ -579,23 +698,7 @@ __device__ __forceinline__ void run_engine(const BfsArgs& a, int engine, int sel
 
 // ------------------------------------------------------------ Stage 2
 
-// Row pointers rp[s*SIGMA .. s*SIGMA + SIGMA] of a slice set's vertices with
-// 16-byte loads. rp is padded on the device to N_s*SIGMA + 1 entries (the
-// tail repeats m), and s*SIGMA*4 is a multiple of 16, so the loads are aligned
-// and in bounds.
-template <int SIGMA>
-__device__ __forceinline__ void load_set_rp(gptr<const int32_t> rp, long long s, int (&r)[SIGMA + 1]) {
-  const gptr<const int4> p = (gptr<const int4>)(rp + s * SIGMA);
-#pragma unroll
-  for (int i = 0; i < SIGMA / 4; ++i) {
-    const int4 q = p[i];
-    r[4 * i + 0] = q.x;
-    r[4 * i + 1] = q.y;
-    r[4 * i + 2] = q.z;
-    r[4 * i + 3] = q.w;
-  }
-  r[SIGMA] = rp[s * SIGMA + SIGMA];
-}
+
 
 
 // Stage 2 over windows of 2*BLOCK slice sets; set_at(win, k) gives the set
@@ -628,7 +731,7 @@ __device__ void finalize_windows(const BfsArgs& a, int new_level, gptr<unsigned 
   __shared__ int lds32[3 * (BLOCK / 64)];
   __shared__ unsigned long long bases[3];
   gptr<M> __restrict__ vis = to_global(static_cast<M*>(a.vis));
-  gptr<M> __restrict__ front = to_global(static_cast<M*>(a.front));
+  gptr<M> __restrict__ front = to_global(static_cast<M*>(front_buf(a, sel_out)));
   gptr<uint8_t> __restrict__ mark = to_global(a.mark);
   gptr<const int32_t> __restrict__ rp = to_global(a.rp);
   gptr<const uint32_t> __restrict__ sp = to_global(a.slice_ptr);
@@ -857,7 +960,6 @@ __device__ void finalize(const BfsArgs& a, int new_level, int slot_out, int sel_
 // over the queue, the vertex lists for push; all lists in probe mode) do the
 // workgroups sweep again and write it at those offsets, behind one more
 // barrier. Bottom-up and panel levels skip the emit phase.
-constexpr int kParts = 8;  // frontier, queued slices, frontier edges, deg>=32, deg>=1024, light, heavy, queue
 
 // MODE = FIN_COUNT (counts only) or FIN_ATOMIC (lists too, output space
 // reserved with one device atomic per window and list on the cursors of
@@ -916,9 +1018,13 @@ __device__ void reduce_parts(const BfsArgs& a, long long (&tot)[kParts], long lo
   __syncthreads();
 }
 
+// panel_part: the counts came from the fused panel step, so each workgroup
+// emits the lists of the slice sets of its own panels (the partition its
+// partial counters, and hence its offsets, were computed over); otherwise
+// the window partition of finalize_count.
 template <int SIGMA, int BLOCK>
 __device__ void finalize_emit(const BfsArgs& a, int sel_out, const long long (&before)[3], bool want_push,
-                              bool want_queue) {
+                              bool want_queue, bool panel_part) {
   constexpr long long WIN = static_cast<long long>(BLOCK) * 2;
   __shared__ unsigned long long cursor[3];
   if (threadIdx.x < 3) cursor[threadIdx.x] = static_cast<unsigned long long>(before[threadIdx.x]);
@@ -926,8 +1032,28 @@ __device__ void finalize_emit(const BfsArgs& a, int sel_out, const long long (&b
   long long st[kParts] = {0, 0, 0, 0, 0, 0, 0, 0};
   const long long nsets = a.nsets;
   const long long tid = threadIdx.x;
-  finalize_windows<SIGMA, BLOCK, FIN_EMIT>(a, 0, to_global(&a.ctl->acc[0][0][0]), sel_out, blockIdx.x,
-                                           (nsets + WIN - 1) / WIN, gridDim.x,
+  const gptr<unsigned long long> acc0 = to_global(&a.ctl->acc[0][0][0]);
+  if (panel_part) {
+    // panel p holds sets [p * sp, (p + 1) * sp); this workgroup owns panels
+    // blockIdx.x, blockIdx.x + G, ...; window w is window w % wpp of its
+    // (w / wpp)-th panel
+    const long long sp = 1LL << (a.panel_rb - 3);
+    const long long wpp = (sp + WIN - 1) / WIN;
+    const long long mine = a.npanels > static_cast<int>(blockIdx.x)
+                               ? (a.npanels - 1 - static_cast<long long>(blockIdx.x)) / gridDim.x + 1
+                               : 0;
+    const long long b = blockIdx.x, G = gridDim.x;
+    finalize_windows<SIGMA, BLOCK, FIN_EMIT>(a, 0, acc0, sel_out, 0, mine * wpp, 1,
+                                             [=](long long win, int k) -> long long {
+                                               const long long p = b + (win / wpp) * G;
+                                               const long long end = min((p + 1) * sp, nsets);
+                                               const long long s = p * sp + (win % wpp) * WIN + k * BLOCK + tid;
+                                               return s < end ? s : -1;
+                                             },
+                                             st, cursor, want_push, want_queue);
+    return;
+  }
+  finalize_windows<SIGMA, BLOCK, FIN_EMIT>(a, 0, acc0, sel_out, blockIdx.x, (nsets + WIN - 1) / WIN, gridDim.x,
                                            [=](long long win, int k) -> long long {
                                              const long long s = win * WIN + k * BLOCK + tid;
                                              return s < nsets ? s : -1;
@@ -1000,11 +1126,13 @@ template <int SIGMA>
 __device__ void clear_state(const BfsArgs& a, long long gtid, long long nthreads) {
   using M = typename MaskOf<SIGMA>::T;
   M* vis = static_cast<M*>(a.vis);
-  M* front = static_cast<M*>(a.front);
+  M* front0 = static_cast<M*>(front_buf(a, 0));
+  M* front1 = static_cast<M*>(front_buf(a, 1));
   for (long long i = gtid; i < a.n; i += nthreads) a.levels[i] = -1;
   for (long long s = gtid; s < a.nsets; s += nthreads) {
     vis[s] = 0;
-    front[s] = 0;
+    front0[s] = 0;
+    front1[s] = 0;
   }
   if (blockIdx.x == 0)
     for (int t = threadIdx.x; t < kStatSlots * kStatFields; t += blockDim.x)
@@ -1029,7 +1157,7 @@ __device__ void seed_source(const BfsArgs& a) {
     a.fheavy[0][c] = (static_cast<unsigned long long>(src) << 32) | static_cast<unsigned long long>(c * kHeavyChunk);
   if (threadIdx.x == 0) {
     static_cast<M*>(a.vis)[s] = bit;
-    static_cast<M*>(a.front)[s] = bit;
+    static_cast<M*>(front_buf(a, 0))[s] = bit;
     a.levels[a.orig_id ? a.orig_id[src] : src] = 0;
     if (nh == 0) a.flight[0][0] = static_cast<int32_t>(src);
     unsigned long long* acc = &a.ctl->acc[0][0][0];
@@ -1198,6 +1326,9 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
       for (int t = threadIdx.x; t < kStatFields; t += BLOCK) a.ctl->acc[nslot][t][0] = 0ULL;
     }
     const int sel = level & 1;
+    // A BVSS step over the panel copy does Stage 2 itself (two-phase modes):
+    // its partial counters are ready after the Stage 1 barrier.
+    const bool fused = !a.probe && a.count_first != 0 && engine == BLEST_ENGINE_BVSS && kPanelFmt && use_panel(a, v);
     if (a.probe) {
       for (int e = 0; e < 3; ++e) {
         const unsigned long long t0 = dev_ticks();
@@ -1208,7 +1339,7 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
       }
     } else {
       run_engine<SIGMA, SliceT, BLOCK>(a, engine, sel, slot, v, gtid, nthreads, gwave, nwaves, nullptr,
-                                       to_lds(reinterpret_cast<uint32_t*>(hs)));
+                                       to_lds(reinterpret_cast<uint32_t*>(hs)), fused ? level + 1 : -1);
       if (!grid_barrier(a.ctl, bc)) return;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_mid = dev_ticks();
@@ -1222,16 +1353,18 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
     const bool dense_next = engine == BLEST_ENGINE_BOTTOM_UP ||
                             (engine == BLEST_ENGINE_BVSS && kPanelFmt && use_panel(a, v)) ||
                             v.fedges >= 8 * v.frontier;
-    const bool two_phase = !a.probe && (a.count_first == 2 || (a.count_first == 1 && dense_next));
+    const bool two_phase = fused || (!a.probe && (a.count_first == 2 || (a.count_first == 1 && dense_next)));
     LevelView nv;
     bool emitted = false;
     long long before[3] = {0, 0, 0};
     {
-      if (two_phase)
-        finalize_count<SIGMA, BLOCK, FIN_COUNT>(a, level + 1, (level + 1) % kStatSlots, sel ^ 1);
-      else
-        finalize_count<SIGMA, BLOCK, FIN_ATOMIC>(a, level + 1, (level + 1) % kStatSlots, sel ^ 1);
-      if (!grid_barrier(a.ctl, bc)) return;
+      if (!fused) {
+        if (two_phase)
+          finalize_count<SIGMA, BLOCK, FIN_COUNT>(a, level + 1, (level + 1) % kStatSlots, sel ^ 1);
+        else
+          finalize_count<SIGMA, BLOCK, FIN_ATOMIC>(a, level + 1, (level + 1) % kStatSlots, sel ^ 1);
+        if (!grid_barrier(a.ctl, bc)) return;
+      }
       long long tot[kParts];
       reduce_parts<BLOCK>(a, tot, before);
       nv.frontier = tot[0];
@@ -1264,7 +1397,7 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
         const bool want_queue = engine == BLEST_ENGINE_BVSS && !(kPanelFmt && use_panel(a, nv));
         const bool want_push = engine == BLEST_ENGINE_PUSH;
         if (want_queue || want_push) {
-          finalize_emit<SIGMA, BLOCK>(a, sel ^ 1, before, want_push, want_queue);
+          finalize_emit<SIGMA, BLOCK>(a, sel ^ 1, before, want_push, want_queue, fused);
           emitted = true;
         }
       }
@@ -1432,6 +1565,7 @@ BfsArgs bfs_args(const DevGraph& g) {
   a.tau = g.tau;
   a.vis = g.vis;
   a.front = g.front;
+  a.fstride = static_cast<long long>(g.fstride);
   a.mark = g.mark;
   for (int i = 0; i < 2; ++i) {
     a.queue[i] = g.queue[i];

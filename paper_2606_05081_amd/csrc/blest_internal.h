@@ -111,7 +111,8 @@ struct BfsArgs {
   int32_t tau;
   // working state
   void* vis;       // sigma-bit visited word per slice set (V_curr)
-  void* front;     // sigma-bit frontier word per slice set (F_curr)
+  void* front;     // two sigma-bit frontier words per slice set: F_curr of even levels, then of odd levels
+  long long fstride;  // bytes from the first frontier buffer to the second
   uint8_t* mark;   // one byte per vertex: lazily marked in Stage 1 (V_next)
   uint4* queue[2]; // VSS descriptors {first slice, count, frontier bits, set}
   int32_t* flight[2];             // light frontier vertices
@@ -154,7 +155,8 @@ struct DevGraph {
   void* degmask = nullptr;
   int32_t* orig_id = nullptr;
   void* vis = nullptr;
-  void* front = nullptr;
+  void* front = nullptr;  // two buffers, fstride bytes apart
+  size_t fstride = 0;
   uint8_t* mark = nullptr;
   uint4* queue[2] = {nullptr, nullptr};
   int32_t* flight[2] = {nullptr, nullptr};
