@@ -78,6 +78,7 @@ typedef struct {
 #define BLEST_REORDER_NONE 0
 #define BLEST_REORDER_RCM 1  /* Reverse Cuthill-McKee (Section "Boosting Cache Locality") */
 #define BLEST_REORDER_AUTO 2 /* RCM unless the degree distribution is scale-free-like (footnote of that section) */
+#define BLEST_REORDER_JACCARD 3 /* JaccardWithWindows (Section "Increasing Compression Ratio") */
 
 typedef struct {
   int32_t sigma;        /* slice-set width in columns: 8 (default), 16 or 32 */
@@ -110,7 +111,9 @@ typedef struct {
   int32_t msbfs_graph;  /* 1: multi-source BFS and closeness run as a hipGraph of per-phase kernels
                            (batch set-up, each level's engine and Stage 2, batch reduction),
                            replayed until done, instead of one persistent launch (default 0) */
-  int32_t reserved[2];
+  int32_t jaccard_window; /* window width W of BLEST_REORDER_JACCARD: a multiple of sigma greater
+                             than sigma; 0 (default) = 1024 */
+  int32_t reserved;
 } blest_opts;
 
 /* Fills *opts with the defaults listed above. */
@@ -207,7 +210,7 @@ typedef struct {
   int64_t n, m;
   int32_t sigma, tau;
   int32_t slice_bytes;   /* 4 (packed row<<8 | mask) or 8 (row<<32 | mask) */
-  int32_t reordered;     /* 1 if RCM was applied */
+  int32_t reordered;     /* 1 if RCM was applied, 3 if JaccardWithWindows, 0 if neither */
   int64_t n_slice_sets;  /* N_s = ceil(n / sigma) */
   int64_t n_vss;         /* N_v */
   int64_t n_slices;
@@ -223,6 +226,21 @@ typedef struct {
 
 /* Fills *out with structure sizes. Errors: INVALID_ARG. */
 blest_status blest_graph_info(const blest_graph* g, blest_graph_stats* out);
+
+/* JaccardWithWindows on the host (Alg. "JaccardWithWindows", Section
+ * "Increasing Compression Ratio"): the relabelling BLEST_REORDER_JACCARD
+ * applies before building the BVSS. Columns are grouped, window by window
+ * (ids [wW, wW + W)), into slice sets of sigma columns: each set starts from
+ * the window's highest-degree unassigned column and grows by the unassigned
+ * column j sharing rows with the set's row union R that maximises
+ * inter(j) / (|R| + deg(j) - inter(j)), or by the highest-degree one when no
+ * column shares a row. Ties go to the smaller id; a last window narrower than
+ * a multiple of sigma ends with a partial set. csr must be undirected and
+ * simple (as for blest_build). new_of_old (host, n int32): the new id of every
+ * vertex; each id stays inside its window. No device is used.
+ * Errors: INVALID_ARG (NULL, sigma < 1, window not a multiple of sigma or not
+ * greater than it), INVALID_GRAPH, OOM. */
+blest_status blest_reorder_jaccard(const blest_csr* csr, int32_t sigma, int32_t window, int32_t* new_of_old);
 
 /* Per-level record of the last single-source BFS (Alg. 3, Stage 2 statistics). */
 typedef struct {

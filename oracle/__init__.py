@@ -18,6 +18,8 @@ Contents, each following the passage cited beside it:
   get_vi         -- the multi-source index remap (Multi-Source BFS)
   switch_replay  -- Eq. 3 decisions replayed from oracle levels
   mlp            -- float64 MLP forward/backward/Adam (oracle/mlp.py)
+  jaccard        -- JaccardWithWindows over Python sets (oracle/jaccard.py,
+                    Section "Increasing Compression Ratio")
 """
 from __future__ import annotations
 

@@ -50,6 +50,7 @@ class Reorder(IntEnum):
     NONE = 0
     RCM = 1
     AUTO = 2
+    JACCARD = 3
 
 
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_NPARAMS = 12, 64, 3, 5187
@@ -74,7 +75,7 @@ class Opts(ctypes.Structure):
                 ("random_seed", ctypes.c_uint64), ("device", ctypes.c_int32), ("single_block", ctypes.c_int32),
                 ("panel", ctypes.c_int32), ("panel_log2_rows", ctypes.c_int32),
                 ("stage2_count_first", ctypes.c_int32), ("msbfs_graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("jaccard_window", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class GraphStats(ctypes.Structure):
@@ -128,6 +129,7 @@ SIGNATURES = {
     "blest_sync": (_i32, [_vp, _vp]),
     "blest_set_policy": (_i32, [_vp, _i32, _f32, _u64]),
     "blest_graph_info": (_i32, [_vp, ctypes.POINTER(GraphStats)]),
+    "blest_reorder_jaccard": (_i32, [ctypes.POINTER(CSR), _i32, _i32, _p32]),
     "blest_last_level_stats": (_i32, [_vp, ctypes.POINTER(LevelStat), _i32, _p32]),
     "blest_last_level_features": (_i32, [_vp, _pf32, _i32, _p32]),
     "blest_export_bvss": (_i32, [_vp, _p64, _p64, _p64, _p32, _pu64, _p32]),
@@ -198,6 +200,19 @@ def blest_build(row_ptr, col, opts: Opts | None = None):
     h = ctypes.c_void_p()
     _check(lib().blest_build(ctypes.byref(csr), ctypes.byref(opts) if opts is not None else None, ctypes.byref(h)))
     return h
+
+
+def blest_reorder_jaccard(row_ptr, col, sigma: int = 8, window: int = 1024) -> np.ndarray:
+    """JaccardWithWindows on the host: the new id of every vertex (int32[n])."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    if cl.size == 0:
+        cl = np.zeros(1, dtype=np.int32)
+    n = rp.size - 1
+    out = np.empty(max(n, 1), dtype=np.int32)
+    csr = CSR(n, int(rp[-1]) if rp.size else 0, rp.ctypes.data_as(_p32), cl.ctypes.data_as(_p32))
+    _check(lib().blest_reorder_jaccard(ctypes.byref(csr), int(sigma), int(window), out.ctypes.data_as(_p32)))
+    return out[:n]
 
 
 def blest_free(h):

@@ -195,8 +195,10 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
     return fail(BLEST_ERR_UNSUPPORTED, "block_size must be 256, 512 or 1024");
   if (o.policy < BLEST_POLICY_HEURISTIC || o.policy > BLEST_POLICY_RANDOM)
     return fail(BLEST_ERR_INVALID_ARG, "unknown policy");
-  if (o.reorder < BLEST_REORDER_NONE || o.reorder > BLEST_REORDER_AUTO)
+  if (o.reorder < BLEST_REORDER_NONE || o.reorder > BLEST_REORDER_JACCARD)
     return fail(BLEST_ERR_INVALID_ARG, "unknown reorder mode");
+  if (o.jaccard_window < 0 || (o.jaccard_window != 0 && (o.jaccard_window <= o.sigma || o.jaccard_window % o.sigma)))
+    return fail(BLEST_ERR_INVALID_ARG, "jaccard_window must be 0 or a multiple of sigma greater than sigma");
   if (!(o.eta >= 0.0f)) return fail(BLEST_ERR_INVALID_ARG, "eta must be >= 0");
   if (o.msbfs_width != 64 && o.msbfs_width != 128 && o.msbfs_width != 256 && o.msbfs_width != 512)
     return fail(BLEST_ERR_UNSUPPORTED, "msbfs_width must be 64, 128, 256 or 512");
@@ -220,11 +222,19 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   const int32_t* rp = csr->row_ptr;
   const int32_t* col = csr->col_idx;
   std::vector<int32_t> rp2, col2, orig;
-  bool reorder = o.reorder == BLEST_REORDER_RCM ||
-                 (o.reorder == BLEST_REORDER_AUTO && !blest::is_scale_free_like(n, rp));
-  if (reorder && n > 1) {
+  const bool rcm = o.reorder == BLEST_REORDER_RCM ||
+                   (o.reorder == BLEST_REORDER_AUTO && !blest::is_scale_free_like(n, rp));
+  const bool jac = o.reorder == BLEST_REORDER_JACCARD;
+  if ((rcm || jac) && n > 1) {
     try {
-      orig = blest::rcm_order(n, rp, col);
+      if (rcm) {
+        orig = blest::rcm_order(n, rp, col);
+      } else {
+        const std::vector<int32_t> nof =
+            blest::jaccard_order(n, rp, col, o.sigma, o.jaccard_window ? o.jaccard_window : 1024);
+        orig.assign(static_cast<size_t>(n), 0);
+        for (int64_t i = 0; i < n; ++i) orig[nof[i]] = static_cast<int32_t>(i);
+      }
       blest::permute_csr(n, rp, col, orig, g->perm, rp2, col2);
     } catch (...) {
       delete g;
@@ -232,7 +242,7 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
     }
     rp = rp2.data();
     col = col2.data();
-    g->reordered = 1;
+    g->reordered = rcm ? 1 : 3;
   }
   const bool wide = o.sigma != 8 || o.wide_slices || n > (int64_t(1) << 24);
   blest::Bvss b;
@@ -442,6 +452,22 @@ blest_status blest_graph_info(const blest_graph* g, blest_graph_stats* out) {
   out->block_size = g->d.block;
   out->device = g->d.device;
   out->panel_log2_rows = g->d.npanels > 0 ? g->d.panel_rb : 0;
+  return BLEST_OK;
+}
+
+blest_status blest_reorder_jaccard(const blest_csr* csr, int32_t sigma, int32_t window, int32_t* new_of_old) {
+  if (!csr || !new_of_old) return fail(BLEST_ERR_INVALID_ARG, "NULL argument");
+  if (sigma < 1 || window <= sigma || window % sigma != 0)
+    return fail(BLEST_ERR_INVALID_ARG, "window must be a multiple of sigma greater than sigma");
+  std::string why;
+  if (!blest::validate_csr(csr->n, csr->m, csr->row_ptr, csr->col_idx, &why))
+    return fail(BLEST_ERR_INVALID_GRAPH, why);
+  try {
+    const std::vector<int32_t> nof = blest::jaccard_order(csr->n, csr->row_ptr, csr->col_idx, sigma, window);
+    std::memcpy(new_of_old, nof.data(), sizeof(int32_t) * nof.size());
+  } catch (...) {
+    return fail(BLEST_ERR_OOM, "host allocation during reordering");
+  }
   return BLEST_OK;
 }
 

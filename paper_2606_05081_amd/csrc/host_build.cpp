@@ -201,6 +201,100 @@ std::vector<int32_t> rcm_order(int64_t n, const int32_t* rp, const int32_t* col)
   return order;  // order[new id] = old id
 }
 
+std::vector<int32_t> jaccard_order(int64_t n, const int32_t* rp, const int32_t* col, int sigma, int64_t window) {
+  std::vector<int32_t> new_of_old(static_cast<size_t>(n), 0);
+  if (n <= 0) return new_of_old;
+  const int64_t nwin = (n + window - 1) / window;
+  const int t = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(host_threads(), nwin)));
+  std::vector<std::thread> pool;
+  for (int ti = 0; ti < t; ++ti) {
+    pool.emplace_back([&, ti] {
+      // per-thread scratch: membership stamps of R over all rows, and the
+      // window-local candidate state
+      std::vector<uint32_t> in_r(static_cast<size_t>(n), 0u);
+      uint32_t stamp = 0;
+      std::vector<int32_t> inter(static_cast<size_t>(window), 0);
+      std::vector<char> assigned(static_cast<size_t>(window), 0), in_q(static_cast<size_t>(window), 0);
+      std::vector<int32_t> q, touched, by_deg;
+      auto deg = [&](int64_t j) { return static_cast<int64_t>(rp[j + 1] - rp[j]); };
+      for (int64_t w = ti; w < nwin; w += t) {
+        const int64_t ws = w * window, we = std::min(ws + window, n), wn = we - ws;
+        std::fill(assigned.begin(), assigned.begin() + wn, 0);
+        by_deg.resize(static_cast<size_t>(wn));
+        for (int64_t j = 0; j < wn; ++j) by_deg[j] = static_cast<int32_t>(j);
+        std::stable_sort(by_deg.begin(), by_deg.end(),
+                         [&](int32_t x, int32_t y) { return deg(ws + x) > deg(ws + y); });
+        size_t next_deg = 0;
+        auto highest = [&]() {
+          while (assigned[by_deg[next_deg]]) ++next_deg;
+          return by_deg[next_deg];
+        };
+        int64_t rsize = 0;
+        // adds row i to R and updates inter/Q of the window's unassigned columns
+        auto add_row = [&](int32_t i) {
+          in_r[i] = stamp;
+          ++rsize;
+          const int32_t* b = col + rp[i];
+          const int32_t* e = col + rp[i + 1];
+          for (const int32_t* p = std::lower_bound(b, e, static_cast<int32_t>(ws)); p < e && *p < we; ++p) {
+            const int32_t j = static_cast<int32_t>(*p - ws);
+            if (assigned[j]) continue;
+            if (inter[j] == 0) {
+              touched.push_back(j);
+              if (!in_q[j]) {
+                in_q[j] = 1;
+                q.push_back(j);
+              }
+            }
+            ++inter[j];
+          }
+        };
+        auto take = [&](int32_t j, int64_t pos) {
+          assigned[j] = 1;
+          new_of_old[ws + j] = static_cast<int32_t>(pos);
+          for (int32_t p = rp[ws + j]; p < rp[ws + j + 1]; ++p)
+            if (in_r[col[p]] != stamp) add_row(col[p]);
+        };
+        for (int64_t ss = ws; ss < we; ss += sigma) {
+          const int64_t se = std::min<int64_t>(ss + sigma, we);
+          ++stamp;
+          rsize = 0;
+          take(highest(), ss);
+          for (int64_t pos = ss + 1; pos < se; ++pos) {
+            // best candidate of Q: largest inter / (|R| + deg - inter), ties to the smaller id
+            int32_t best = -1;
+            int64_t bn = 0, bd = 1;
+            size_t keep = 0;
+            for (size_t k = 0; k < q.size(); ++k) {
+              const int32_t j = q[k];
+              if (assigned[j]) {
+                in_q[j] = 0;
+                continue;
+              }
+              q[keep++] = j;
+              const int64_t num = inter[j], den = rsize + deg(ws + j) - inter[j];
+              if (best < 0 || num * bd > bn * den || (num * bd == bn * den && j < best)) {
+                best = j;
+                bn = num;
+                bd = den;
+              }
+            }
+            q.resize(keep);
+            take(best >= 0 ? best : highest(), pos);
+          }
+          // reset the candidate state of this slice set
+          for (int32_t j : touched) inter[j] = 0;
+          for (int32_t j : q) in_q[j] = 0;
+          touched.clear();
+          q.clear();
+        }
+      }
+    });
+  }
+  for (auto& th : pool) th.join();
+  return new_of_old;
+}
+
 void permute_csr(int64_t n, const int32_t* rp, const int32_t* col, const std::vector<int32_t>& old_of_new,
                  std::vector<int32_t>& new_of_old, std::vector<int32_t>& rp2, std::vector<int32_t>& col2) {
   new_of_old.assign(n, 0);

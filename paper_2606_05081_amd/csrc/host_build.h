@@ -26,6 +26,15 @@ bool is_scale_free_like(int64_t n, const int32_t* rp);
 // Reverse Cuthill-McKee order: result[new id] = old id.
 std::vector<int32_t> rcm_order(int64_t n, const int32_t* rp, const int32_t* col);
 
+// JaccardWithWindows (Alg. "JaccardWithWindows", Section "Increasing
+// Compression Ratio"): within each window of `window` consecutive ids, slice
+// sets of sigma columns are filled greedily, each seeded by the
+// highest-degree unassigned column and grown by the candidate maximising
+// inter / (|R| + deg - inter). Result: new_of_old (the algorithm's inverse
+// permutation), every id staying inside its window. Ties go to the smaller
+// id; a window whose width is not a multiple of sigma ends with a partial set.
+std::vector<int32_t> jaccard_order(int64_t n, const int32_t* rp, const int32_t* col, int sigma, int64_t window);
+
 // Relabels a CSR: vertex old_of_new[i] becomes i.
 void permute_csr(int64_t n, const int32_t* rp, const int32_t* col, const std::vector<int32_t>& old_of_new,
                  std::vector<int32_t>& new_of_old, std::vector<int32_t>& rp2, std::vector<int32_t>& col2);

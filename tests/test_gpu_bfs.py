@@ -76,6 +76,7 @@ def test_rmat_s16_all_policies(blest):
     dict(panel=0), dict(panel=2), dict(panel=2, block_size=256), dict(panel=2, persistent=0),
     dict(panel=2, blocks_per_cu=1, single_block=0),
     dict(stage2_count_first=0), dict(stage2_count_first=2), dict(stage2_count_first=2, single_block=0, panel=0),
+    dict(reorder=3), dict(reorder=3, jaccard_window=64, panel=2),
 ])
 def test_option_matrix(blest, opt):
     for rp, col in [inputs.rmat_graph(13, 77), inputs.grid_graph(70, 78)]:
@@ -263,4 +264,27 @@ def test_full_size_sampled_sources(blest, which):
             if which == "rmat22" and pol == "BVSS":
                 # the dense levels of the plain method read the panel-blocked copy
                 assert any(r["bvss_panel"] for r in g.level_stats()[:-1])
+    g.close()
+
+
+def test_jaccard_reordering_exact_and_compresses(blest):
+    """JaccardWithWindows relabelling (Section "Increasing Compression
+    Ratio"): fewer slices than the input order on R-MAT, and every output is
+    still in input ids and exact (the relabelling only changes the BVSS)."""
+    import oracle.jaccard as J
+    rp, col = inputs.rmat_graph(13, 91)
+    base = blest.Graph(rp, col, reorder=0)
+    g = blest.Graph(rp, col, reorder=3, jaccard_window=256)
+    sb, sj = base.info(), g.info()
+    assert sj["reordered"] == 3 and sb["reordered"] == 0
+    nof = blest.blest_reorder_jaccard(rp, col, 8, 256)
+    assert sj["n_slices"] == J.count_slices(rp, col, nof, 8) < sb["n_slices"]
+    for s in inputs.sources(rp, 3, seed=92):
+        run_all_policies(blest, g, int(s), oracle.bfs(rp, col, int(s)), seeds=(2,))
+    srcs = inputs.sources(rp, 130, seed=93)
+    assert np.array_equal(g.msbfs(srcs).cpu().numpy(), oracle.msbfs16(rp, col, srcs))
+    osum, oreach, occ = oracle.closeness(rp, col, srcs)
+    s_, r_, c_ = g.closeness(srcs)
+    assert np.array_equal(s_.cpu().numpy(), osum) and np.array_equal(c_.cpu().numpy(), occ)
+    base.close()
     g.close()

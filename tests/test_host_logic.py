@@ -55,3 +55,34 @@ def test_autotune_cache_roundtrip(tmp_path):
     assert autotune.lookup("rmat", 1 << 20, 31 << 20, device_name="gfx950", path=path)["tau"] == 64
     assert json.load(open(path))[key]["bfs"]["tau"] == 64
     assert not autotune._valid({**autotune.DEFAULTS, "sigma": 16, "wide_slices": 0})
+
+
+def test_jaccard_host_order_equals_oracle():
+    """The library's JaccardWithWindows (host code, no device) against the
+    set-based oracle, on graphs of several shapes and (sigma, window) pairs."""
+    import oracle.jaccard as J
+    from paper_2606_05081_amd import blest, inputs
+    from tests import helpers as H
+    cases = [(inputs.rmat_graph(9, 5), 8, 64), (inputs.rmat_graph(10, 6), 8, 128), (inputs.rmat_graph(9, 7), 16, 96),
+             (inputs.er_graph(9, 8), 8, 64), (inputs.grid_graph(20, 9), 8, 40), (H.path(37), 4, 12),
+             (inputs.rmat_graph(8, 10), 2, 6)]
+    for (rp, col), sigma, window in cases:
+        got = blest.blest_reorder_jaccard(rp, col, sigma, window)
+        ref = J.jaccard_with_windows(rp, col, sigma, window)
+        assert np.array_equal(got, ref), (sigma, window, np.nonzero(got != ref)[0][:5])
+    rp, col = inputs.rmat_graph(11, 11)
+    nof = blest.blest_reorder_jaccard(rp, col, 8, 1024)
+    assert J.count_slices(rp, col, nof, 8) < J.count_slices(rp, col, np.arange(rp.size - 1), 8)
+
+
+def test_jaccard_host_rejects_bad_arguments():
+    import pytest
+    from paper_2606_05081_amd import blest, inputs
+    rp, col = inputs.rmat_graph(6, 1)
+    for sigma, window in [(8, 8), (8, 12), (0, 16)]:
+        with pytest.raises(blest.BlestError) as ei:
+            blest.blest_reorder_jaccard(rp, col, sigma, window)
+        assert ei.value.status == blest.Status.INVALID_ARG
+    with pytest.raises(blest.BlestError) as ei:
+        blest.blest_reorder_jaccard(np.array([0, 1, 1], np.int32), np.array([1], np.int32), 8, 16)
+    assert ei.value.status == blest.Status.INVALID_GRAPH

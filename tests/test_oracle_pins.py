@@ -358,3 +358,75 @@ def test_adam_first_step_closed_form():
     t1, m1, v1 = mlp.adam_step(theta, g, np.zeros_like(g), np.zeros_like(g), 1, lr=lr, eps=eps)
     assert np.allclose(t1, theta - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-15)
     assert np.allclose(m1, 0.1 * g) and np.allclose(v1, 0.001 * g * g)
+
+
+# ---- JaccardWithWindows (Section "Increasing Compression Ratio") ----------
+
+def _planted_blocks(sizes, rows_per_group, seed):
+    """Columns 0..sum(sizes)-1 in groups; the columns of a group share the same
+    private row set (identical neighbourhoods, so their Jaccard similarity is 1
+    and 0 across groups). Column labels are shuffled."""
+    rng = np.random.default_rng(seed)
+    ncol = sum(sizes)
+    perm = rng.permutation(ncol)
+    us, vs, groups, nxt = [], [], [], ncol
+    start = 0
+    for size, nr in zip(sizes, rows_per_group):
+        cols = perm[start:start + size]
+        start += size
+        rows = list(range(nxt, nxt + nr))
+        nxt += nr
+        groups.append(set(int(c) for c in cols))
+        for c in cols:
+            for r in rows:
+                us.append(int(c))
+                vs.append(r)
+    rp, col = inputs.from_pairs(nxt, us, vs)
+    return rp, col, groups
+
+
+def test_jaccard_recovers_planted_slice_sets():
+    from oracle import jaccard as J
+    # window 16 = four slice sets of 4; group sizes 4, row sets of distinct sizes
+    rp, col, groups = _planted_blocks([4, 4, 4, 4], [5, 9, 3, 7], seed=3)
+    nof = J.jaccard_with_windows(rp, col, sigma=4, window=16)
+    sets = [set(np.nonzero(nof[:16] // 4 == k)[0].tolist()) for k in range(4)]
+    assert sorted(map(sorted, sets)) == sorted(map(sorted, groups))
+    # seeds go by degree: the first slice set is the group with the largest row set
+    assert sets[0] == groups[1] and sets[1] == groups[3]
+    # the window's four slice sets then hold one slice per (group, row): the
+    # minimum, 5 + 9 + 3 + 7; the shuffled order needs more
+    def window_slices(order):
+        src = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+        sel = src < 16
+        return len(set(zip((np.asarray(order)[src[sel]] // 4).tolist(), col[sel].tolist())))
+    assert window_slices(nof) == 24
+    assert window_slices(np.arange(rp.size - 1)) > 24
+
+
+def test_jaccard_is_a_windowwise_permutation_seeded_by_degree():
+    from oracle import jaccard as J
+    rp, col = inputs.rmat_graph(8, 17)
+    n = rp.size - 1
+    deg = np.diff(rp)
+    for sigma, window in [(8, 32), (8, 64), (4, 12), (2, 6)]:
+        nof = J.jaccard_with_windows(rp, col, sigma, window)
+        assert np.array_equal(np.sort(nof), np.arange(n))
+        for ws in range(0, n, window):
+            we = min(ws + window, n)
+            assert nof[ws:we].min() == ws and nof[ws:we].max() == we - 1
+            first = int(np.nonzero(nof == ws)[0][0])
+            best = ws + int(np.argmax(deg[ws:we]))  # argmax returns the smallest id among ties
+            assert first == best
+
+
+def test_jaccard_without_edges_keeps_the_order_and_handles_a_ragged_window():
+    from oracle import jaccard as J
+    rp = np.zeros(21, dtype=np.int32)
+    col = np.zeros(0, dtype=np.int32)
+    assert np.array_equal(J.jaccard_with_windows(rp, col, 8, 16), np.arange(20))
+    # a path: degrees 1, 2, ..., 2, 1 -- ties resolved to the smaller id
+    rp, col = H.path(10)
+    nof = J.jaccard_with_windows(rp, col, 2, 4)
+    assert np.array_equal(np.sort(nof), np.arange(10))
+    assert nof[1] == 0  # vertex 1 (degree 2, smallest such id) seeds the first window
