@@ -1343,14 +1343,16 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
       if (!grid_barrier(a.ctl, bc)) return;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) a.log[level].t_mid = dev_ticks();
-    // Stage 2. When the next level is likely dense (this step was bottom-up
-    // or BVSS over the panel copy, or the frontier's mean degree is at least
-    // 8, so the next frontier will be much larger) it will likely read no
-    // list: the two-phase form counts first and writes lists only if the
-    // chosen engine needs them. Otherwise the lists are built in the same
-    // pass (one device atomic per window and list), which saves a barrier.
+    // Stage 2. When the next level is likely dense (this step was BVSS over
+    // the panel copy, or bottom-up on a frontier that did not shrink, or the
+    // frontier's mean degree is at least 8, so the next frontier will be much
+    // larger) it will likely read no list: the two-phase form counts first
+    // and writes lists only if the chosen engine needs them. Otherwise (a
+    // shrinking bottom-up tail is usually followed by a small queue step)
+    // the lists are built in the same pass (one device atomic per window and
+    // list), which saves a barrier.
     // The level statistics come from the per-workgroup partials either way.
-    const bool dense_next = engine == BLEST_ENGINE_BOTTOM_UP ||
+    const bool dense_next = (engine == BLEST_ENGINE_BOTTOM_UP && v.frontier >= prev_frontier) ||
                             (engine == BLEST_ENGINE_BVSS && kPanelFmt && use_panel(a, v)) ||
                             v.fedges >= 8 * v.frontier;
     const bool two_phase = fused || (!a.probe && (a.count_first == 2 || (a.count_first == 1 && dense_next)));
