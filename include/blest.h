@@ -77,7 +77,8 @@ typedef struct {
 
 #define BLEST_REORDER_NONE 0
 #define BLEST_REORDER_RCM 1  /* Reverse Cuthill-McKee (Section "Boosting Cache Locality") */
-#define BLEST_REORDER_AUTO 2 /* RCM unless the degree distribution is scale-free-like (footnote of that section) */
+#define BLEST_REORDER_AUTO 2 /* JaccardWithWindows if the degree distribution is scale-free-like (footnote
+                                of that section), RCM otherwise (Section "Reordering the Graph") */
 #define BLEST_REORDER_JACCARD 3 /* JaccardWithWindows (Section "Increasing Compression Ratio") */
 
 typedef struct {

@@ -222,9 +222,11 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   const int32_t* rp = csr->row_ptr;
   const int32_t* col = csr->col_idx;
   std::vector<int32_t> rp2, col2, orig;
-  const bool rcm = o.reorder == BLEST_REORDER_RCM ||
-                   (o.reorder == BLEST_REORDER_AUTO && !blest::is_scale_free_like(n, rp));
-  const bool jac = o.reorder == BLEST_REORDER_JACCARD;
+  // AUTO follows the section "Reordering the Graph": JaccardWithWindows for
+  // scale-free-like degree distributions, RCM for the others.
+  const bool scale_free = o.reorder == BLEST_REORDER_AUTO && blest::is_scale_free_like(n, rp);
+  const bool rcm = o.reorder == BLEST_REORDER_RCM || (o.reorder == BLEST_REORDER_AUTO && !scale_free);
+  const bool jac = o.reorder == BLEST_REORDER_JACCARD || scale_free;
   if ((rcm || jac) && n > 1) {
     try {
       if (rcm) {

@@ -611,7 +611,15 @@ __device__ __attribute__((noinline)) long long engine_pull(const BfsArgs& a, int
   gptr<uint8_t> __restrict__ mark = to_global(a.mark);
   const long long nv = a.nsets * SIGMA;
   const int lane = lane_id();
-  for (long long ubase = gtid - lane; ubase < nv; ubase += nthreads) {
+  // 64-vertex chunks: round k gives the waves chunks k*nw .. k*nw + nw - 1,
+  // rotated by k, so chunks with heavy rows that recur with a fixed stride
+  // (a relabelling that puts each window's hubs first) spread over all waves
+  const long long nw = nthreads / 64, gw = (gtid - lane) / 64;
+  const long long nchunks = (nv + 63) / 64;
+  for (long long k = 0; k * nw < nchunks; ++k) {
+    const long long chunk = k * nw + (gw + k) % nw;
+    if (chunk >= nchunks) continue;
+    const long long ubase = chunk * 64;
     const long long u = ubase + lane;
     bool cand = false;
     int p = 0, e = 0;
