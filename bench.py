@@ -280,12 +280,18 @@ def main():
     g.set_log_work(True)  # per-level adjacency counts for the byte accounting (not timed)
     nb = []
     deg = np.diff(rp).astype(np.int64)
+    pan_b, pan_us = [], []  # the panel steps alone: bytes read and Stage 1 time (fused Stage 2 and barrier included)
     for s in srcs[:8]:
         g.bfs(int(s), out)
         g.sync()
         lev = out.cpu().numpy()
-        nb.append(algorithmic_bytes(g.level_stats(), info["n"], info["n_slice_sets"], info["sigma"],
+        st = g.level_stats()
+        nb.append(algorithmic_bytes(st, info["n"], info["n_slice_sets"], info["sigma"],
                                     info["slice_bytes"], deg, lev))
+        for r in st[:-1]:
+            if r["engine"] == 0 and r.get("bvss_panel"):
+                pan_b.append(4 * r["work"] + 4 * (r["work"] // 256) + info["n"] // 8)
+                pan_us.append(r["t_stage1_us"])
     bytes_per_launch = float(np.mean(nb))
     launch_ms = float(np.mean(td_t[:8]))
     achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
@@ -310,7 +316,11 @@ def main():
               round(learned_gteps / heur_gteps, 4), "learned_enabled_by_trials": enabled,
               "trial_ms_per_source": None if trial_ms is None else {k: round(v, 4) for k, v in trial_ms.items()},
               "plain_method_gteps": round(td_gteps, 3),
-              "ms_per_source": round(float(np.mean(heur_t)), 4), "switched_achieved_GBs": round(sw_ach, 1)}
+              "ms_per_source": round(float(np.mean(heur_t)), 4), "switched_achieved_GBs": round(sw_ach, 1),
+              "panel_step": None if not pan_b else {
+                  "levels": len(pan_b), "GB_per_level": round(float(np.mean(pan_b)) / 1e9, 4),
+                  "us_per_level": round(float(np.mean(pan_us)), 1),
+                  "GBs": round(float(np.sum(pan_b)) / (float(np.sum(pan_us)) * 1e-6) / 1e9, 1)}}
     g.close()
 
     cpu = None

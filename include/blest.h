@@ -46,6 +46,7 @@ typedef int32_t blest_status;
 #define BLEST_ERR_UNSUPPORTED (-7)   /* option not supported (e.g. sigma) */
 #define BLEST_ERR_TIMEOUT (-8)       /* a device-wide barrier exceeded its spin bound */
 #define BLEST_ERR_NO_DEVICE (-9)     /* no usable gfx950 device */
+#define BLEST_ERR_IO (-10)           /* a checkpoint file could not be read or written */
 
 /* Short name of a status code (static string). */
 const char* blest_status_str(blest_status s);
@@ -161,6 +162,24 @@ blest_status blest_msbfs_batched(blest_graph* g, const int32_t* srcs_host, int32
  * Any of the three output pointers may be NULL. */
 blest_status blest_closeness(blest_graph* g, const int32_t* srcs_host, int64_t k, int64_t* sums_dev,
                              int64_t* reach_dev, double* cc_dev, void* stream);
+
+/* Closeness with a checkpoint file, for runs long enough to be interrupted
+ * (all sources of a large graph). Same outputs as blest_closeness. Sources
+ * are processed in order, in chunks of up to 64 batches; after each chunk the
+ * per-source sums and reach counts finished so far are written to `path`
+ * (host file: a header with n, m, k and a hash of the source list, then the
+ * finished sources' sums and reach; replaced atomically by rename). A call
+ * that finds a matching file resumes after its finished sources and copies
+ * their results to the outputs (cc recomputed as (reach-1)/sum). max_sources
+ * > 0 stops after about that many new sources (whole chunks of at most that
+ * size); 0 runs to the end. *done = sources finished in total (k when
+ * complete); outputs are valid for [0, *done). The call waits for `stream`.
+ * Errors: as blest_closeness; INVALID_ARG (NULL path or done, or a file
+ * written for another graph or source list); IO (file cannot be read or
+ * written). */
+blest_status blest_closeness_resumable(blest_graph* g, const int32_t* srcs_host, int64_t k, int64_t* sums_dev,
+                                       int64_t* reach_dev, double* cc_dev, const char* path, int64_t max_sources,
+                                       int64_t* done, void* stream);
 
 /* Per-target distance sums of Eq. 4 (Closeness Centrality): far_dev[v] =
  * sum over the k sources c that reach v of d(srcs[c], v), in input vertex ids;

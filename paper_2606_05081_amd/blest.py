@@ -29,6 +29,7 @@ class Status(IntEnum):
     UNSUPPORTED = -7
     TIMEOUT = -8
     NO_DEVICE = -9
+    IO = -10
 
 
 class Policy(IntEnum):
@@ -129,6 +130,7 @@ SIGNATURES = {
     "blest_sync": (_i32, [_vp, _vp]),
     "blest_set_policy": (_i32, [_vp, _i32, _f32, _u64]),
     "blest_graph_info": (_i32, [_vp, ctypes.POINTER(GraphStats)]),
+    "blest_closeness_resumable": (_i32, [_vp, _p32, _i64, _vp, _vp, _vp, ctypes.c_char_p, _i64, _p64, _vp]),
     "blest_reorder_jaccard": (_i32, [ctypes.POINTER(CSR), _i32, _i32, _p32]),
     "blest_last_level_stats": (_i32, [_vp, ctypes.POINTER(LevelStat), _i32, _p32]),
     "blest_last_level_features": (_i32, [_vp, _pf32, _i32, _p32]),
@@ -200,6 +202,15 @@ def blest_build(row_ptr, col, opts: Opts | None = None):
     h = ctypes.c_void_p()
     _check(lib().blest_build(ctypes.byref(csr), ctypes.byref(opts) if opts is not None else None, ctypes.byref(h)))
     return h
+
+
+def blest_closeness_resumable(h, srcs, sums, reach, cc, path: str, max_sources: int = 0, stream=None) -> int:
+    s = np.ascontiguousarray(srcs, dtype=np.int32)
+    done = ctypes.c_int64(0)
+    _check(lib().blest_closeness_resumable(h, s.ctypes.data_as(_p32) if s.size else None, s.size, _ptr(sums),
+                                           _ptr(reach), _ptr(cc), os.fsencode(path), int(max_sources),
+                                           ctypes.byref(done), _stream(stream)))
+    return done.value
 
 
 def blest_reorder_jaccard(row_ptr, col, sigma: int = 8, window: int = 1024) -> np.ndarray:
@@ -406,6 +417,16 @@ class Graph:
         cc = torch.empty(k, dtype=torch.float64, device=self.device)
         blest_closeness(self._h, srcs, sums, reach, cc, stream)
         return sums, reach, cc
+
+    def closeness_resumable(self, srcs, path: str, max_sources: int = 0, stream=None):
+        """Closeness with a checkpoint file (blest_closeness_resumable).
+        Returns (sums, reach, cc, done); outputs are valid for the first done sources."""
+        k = len(srcs)
+        sums = torch.zeros(max(k, 1), dtype=torch.int64, device=self.device)
+        reach = torch.zeros(max(k, 1), dtype=torch.int64, device=self.device)
+        cc = torch.zeros(max(k, 1), dtype=torch.float64, device=self.device)
+        done = blest_closeness_resumable(self._h, srcs, sums, reach, cc, path, max_sources, stream)
+        return sums[:k], reach[:k], cc[:k], done
 
     def far(self, srcs, stream=None):
         """Per-target distance sums of Eq. 4: int64[n], input vertex ids."""

@@ -154,6 +154,7 @@ const char* blest_status_str(blest_status s) {
     case BLEST_ERR_UNSUPPORTED: return "UNSUPPORTED";
     case BLEST_ERR_TIMEOUT: return "TIMEOUT";
     case BLEST_ERR_NO_DEVICE: return "NO_DEVICE";
+    case BLEST_ERR_IO: return "IO";
     default: return "UNKNOWN";
   }
 }
@@ -756,6 +757,130 @@ blest_status blest_closeness(blest_graph* g, const int32_t* srcs, int64_t k, int
   if (e != hipSuccess) return hip_fail(e, "closeness");
   if (g->opts.async) return BLEST_OK;
   return wait_and_check(g, st);
+}
+
+namespace {
+
+// Checkpoint of a resumable closeness run: header, then sums[done], reach[done].
+struct CcHeader {
+  char magic[8];
+  int64_t n, m, k;
+  uint64_t src_hash;  // FNV-1a over the source list
+  int64_t done;
+};
+
+uint64_t fnv1a(const int32_t* p, int64_t k) {
+  uint64_t h = 1469598103934665603ULL;
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(p);
+  for (int64_t i = 0; i < k * 4; ++i) h = (h ^ b[i]) * 1099511628211ULL;
+  return h;
+}
+
+bool write_checkpoint(const std::string& path, const CcHeader& h, const std::vector<int64_t>& sums,
+                      const std::vector<int64_t>& reach) {
+  const std::string tmp = path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return false;
+  bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1;
+  if (h.done > 0) {
+    ok = ok && std::fwrite(sums.data(), sizeof(int64_t), h.done, f) == static_cast<size_t>(h.done);
+    ok = ok && std::fwrite(reach.data(), sizeof(int64_t), h.done, f) == static_cast<size_t>(h.done);
+  }
+  ok = (std::fclose(f) == 0) && ok;
+  return ok && std::rename(tmp.c_str(), path.c_str()) == 0;
+}
+
+}  // namespace
+
+blest_status blest_closeness_resumable(blest_graph* g, const int32_t* srcs, int64_t k, int64_t* sums_dev,
+                                       int64_t* reach_dev, double* cc_dev, const char* path, int64_t max_sources,
+                                       int64_t* done, void* stream) {
+  if (!g || !path || !done) return fail(BLEST_ERR_INVALID_ARG, "NULL graph, path or done");
+  if (k < 0 || k > INT32_MAX || max_sources < 0) return fail(BLEST_ERR_INVALID_ARG, "bad source count");
+  *done = 0;
+  if (k > 0 && !srcs) return fail(BLEST_ERR_INVALID_ARG, "NULL sources");
+  for (int64_t c = 0; c < k; ++c)
+    if (srcs[c] < 0 || srcs[c] >= g->d.n) return fail(BLEST_ERR_OUT_OF_RANGE, "source vertex out of range");
+  CcHeader h{};
+  std::memcpy(h.magic, "BLESTCC1", 8);
+  h.n = g->d.n;
+  h.m = g->d.m;
+  h.k = k;
+  h.src_hash = fnv1a(srcs, k);
+  std::vector<int64_t> sums, reach;
+  if (FILE* f = std::fopen(path, "rb")) {
+    CcHeader r{};
+    bool ok = std::fread(&r, sizeof(r), 1, f) == 1;
+    if (ok && (std::memcmp(r.magic, h.magic, 8) != 0 || r.n != h.n || r.m != h.m || r.k != h.k ||
+               r.src_hash != h.src_hash || r.done < 0 || r.done > k)) {
+      std::fclose(f);
+      return fail(BLEST_ERR_INVALID_ARG, "checkpoint file belongs to another graph or source list");
+    }
+    if (ok && r.done > 0) {
+      sums.resize(r.done);
+      reach.resize(r.done);
+      ok = std::fread(sums.data(), sizeof(int64_t), r.done, f) == static_cast<size_t>(r.done) &&
+           std::fread(reach.data(), sizeof(int64_t), r.done, f) == static_cast<size_t>(r.done);
+    }
+    std::fclose(f);
+    if (!ok) return fail(BLEST_ERR_IO, "checkpoint file is truncated");
+    h.done = r.done;
+  }
+  CK(hipSetDevice(g->d.device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (h.done > 0) {
+    // results of the finished sources, cc as the kernels compute it
+    std::vector<double> cc(h.done);
+    for (int64_t c = 0; c < h.done; ++c)
+      cc[c] = sums[c] ? static_cast<double>(reach[c] - 1) / static_cast<double>(sums[c]) : 0.0;
+    if (sums_dev) CK(hipMemcpyAsync(sums_dev, sums.data(), sizeof(int64_t) * h.done, hipMemcpyHostToDevice, st));
+    if (reach_dev) CK(hipMemcpyAsync(reach_dev, reach.data(), sizeof(int64_t) * h.done, hipMemcpyHostToDevice, st));
+    if (cc_dev) CK(hipMemcpyAsync(cc_dev, cc.data(), sizeof(double) * h.done, hipMemcpyHostToDevice, st));
+    CK(hipStreamSynchronize(st));
+  }
+  const int64_t chunk = static_cast<int64_t>(g->opts.msbfs_width) * 64;
+  int64_t budget = max_sources > 0 ? max_sources : k;
+  // device scratch for one chunk's sums and reach, so they can be saved
+  int64_t* dsum = nullptr;
+  int64_t* dreach = nullptr;
+  const int64_t cap = std::min(chunk, std::max<int64_t>(k - h.done, 1));
+  CK(hipMalloc(&dsum, sizeof(int64_t) * cap));
+  if (hipMalloc(&dreach, sizeof(int64_t) * cap) != hipSuccess) {
+    (void)hipFree(dsum);
+    return fail(BLEST_ERR_OOM, "device scratch");
+  }
+  blest_status s = BLEST_OK;
+  const int32_t saved_async = g->opts.async;
+  g->opts.async = 0;
+  while (h.done < k && budget > 0) {
+    const int64_t c = std::min({chunk, k - h.done, budget});
+    s = blest_closeness(g, srcs + h.done, c, dsum, dreach, cc_dev ? cc_dev + h.done : nullptr, stream);
+    if (s != BLEST_OK) break;
+    sums.resize(h.done + c);
+    reach.resize(h.done + c);
+    if (hipMemcpy(sums.data() + h.done, dsum, sizeof(int64_t) * c, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(reach.data() + h.done, dreach, sizeof(int64_t) * c, hipMemcpyDeviceToHost) != hipSuccess) {
+      s = fail(BLEST_ERR_HIP, "copy of closeness results");
+      break;
+    }
+    if ((sums_dev && hipMemcpy(sums_dev + h.done, dsum, sizeof(int64_t) * c, hipMemcpyDeviceToDevice) != hipSuccess) ||
+        (reach_dev &&
+         hipMemcpy(reach_dev + h.done, dreach, sizeof(int64_t) * c, hipMemcpyDeviceToDevice) != hipSuccess)) {
+      s = fail(BLEST_ERR_HIP, "copy of closeness results");
+      break;
+    }
+    h.done += c;
+    budget -= c;
+    if (!write_checkpoint(path, h, sums, reach)) {
+      s = fail(BLEST_ERR_IO, std::string("cannot write checkpoint ") + path);
+      break;
+    }
+  }
+  g->opts.async = saved_async;
+  (void)hipFree(dsum);
+  (void)hipFree(dreach);
+  *done = h.done;
+  return s;
 }
 
 blest_status blest_far(blest_graph* g, const int32_t* srcs, int64_t k, int64_t* far_dev, void* stream) {

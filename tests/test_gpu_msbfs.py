@@ -342,3 +342,30 @@ def test_msbfs_learned_policy_exact_and_inference(blest, graph_mode):
         assert np.array_equal(cc.cpu().numpy(), occ)
         g.close()
     assert used[0] > 0 and used[1] > 0, used
+
+
+def test_closeness_resumable_checkpoint(blest, tmp_path):
+    """A closeness run cut into pieces by max_sources resumes from its
+    checkpoint file and ends with the oracle's results; a file written for
+    another source list is refused."""
+    rp, col = inputs.rmat_graph(12, 101)
+    srcs = inputs.sources(rp, 700, seed=102)
+    osum, oreach, occ = oracle.closeness(rp, col, srcs)
+    g = blest.Graph(rp, col, msbfs_width=64)  # chunks of 64 batches = 4096 sources
+    path = str(tmp_path / "cc.ckpt")
+    s, r, c, done = g.closeness_resumable(srcs, path, max_sources=300)
+    assert done == 300
+    assert np.array_equal(s.cpu().numpy()[:300], osum[:300]) and np.array_equal(r.cpu().numpy()[:300], oreach[:300])
+    s, r, c, done = g.closeness_resumable(srcs, path, max_sources=250)
+    assert done == 550
+    s, r, c, done = g.closeness_resumable(srcs, path)
+    assert done == 700
+    assert np.array_equal(s.cpu().numpy(), osum) and np.array_equal(r.cpu().numpy(), oreach)
+    assert np.array_equal(c.cpu().numpy(), occ)
+    # a finished file gives the results without new work
+    s, r, c, done = g.closeness_resumable(srcs, path, max_sources=1)
+    assert done == 700 and np.array_equal(c.cpu().numpy(), occ)
+    with pytest.raises(blest.BlestError) as ei:
+        g.closeness_resumable(srcs[::-1].copy(), path)
+    assert ei.value.status == blest.Status.INVALID_ARG
+    g.close()
