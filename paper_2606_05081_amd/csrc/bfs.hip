@@ -1131,15 +1131,21 @@ __device__ void finalize_list(const BfsArgs& a, int new_level, int slot_out, int
 // ------------------------------------------------------- init and seeding
 
 template <int SIGMA>
-__device__ void clear_state(const BfsArgs& a, long long gtid, long long nthreads) {
+// seeded: the threads that clear the source's visited/frontier word and
+// level write the source's values instead (level 0), so no barrier is needed
+// between the clear and those writes.
+__device__ void clear_state(const BfsArgs& a, long long gtid, long long nthreads, bool seeded = false) {
   using M = typename MaskOf<SIGMA>::T;
   M* vis = static_cast<M*>(a.vis);
   M* front0 = static_cast<M*>(front_buf(a, 0));
   M* front1 = static_cast<M*>(front_buf(a, 1));
-  for (long long i = gtid; i < a.n; i += nthreads) a.levels[i] = -1;
+  const long long src_set = seeded ? a.src / SIGMA : -1;
+  const M src_bit = static_cast<M>(M(1) << (a.src % SIGMA));
+  const long long src_in = seeded ? (a.orig_id ? a.orig_id[a.src] : a.src) : -1;
+  for (long long i = gtid; i < a.n; i += nthreads) a.levels[i] = i == src_in ? 0 : -1;
   for (long long s = gtid; s < a.nsets; s += nthreads) {
-    vis[s] = 0;
-    front0[s] = 0;
+    vis[s] = s == src_set ? src_bit : M(0);
+    front0[s] = s == src_set ? src_bit : M(0);
     front1[s] = 0;
   }
   if (blockIdx.x == 0)
@@ -1149,7 +1155,8 @@ __device__ void clear_state(const BfsArgs& a, long long gtid, long long nthreads
 
 // Level 0: frontier = {src}, queue = the VSSs of src's slice set. One block.
 template <int SIGMA>
-__device__ void seed_source(const BfsArgs& a) {
+// lists_only: clear_state(seeded) already wrote the visited/frontier bit and level.
+__device__ void seed_source(const BfsArgs& a, bool lists_only = false) {
   using M = typename MaskOf<SIGMA>::T;
   const long long src = a.src;
   const long long s = src / SIGMA;
@@ -1164,9 +1171,11 @@ __device__ void seed_source(const BfsArgs& a) {
   for (int c = threadIdx.x; c < nh; c += blockDim.x)
     a.fheavy[0][c] = (static_cast<unsigned long long>(src) << 32) | static_cast<unsigned long long>(c * kHeavyChunk);
   if (threadIdx.x == 0) {
-    static_cast<M*>(a.vis)[s] = bit;
-    static_cast<M*>(front_buf(a, 0))[s] = bit;
-    a.levels[a.orig_id ? a.orig_id[src] : src] = 0;
+    if (!lists_only) {
+      static_cast<M*>(a.vis)[s] = bit;
+      static_cast<M*>(front_buf(a, 0))[s] = bit;
+      a.levels[a.orig_id ? a.orig_id[src] : src] = 0;
+    }
     if (nh == 0) a.flight[0][0] = static_cast<int32_t>(src);
     unsigned long long* acc = &a.ctl->acc[0][0][0];
     acc[F_FRONTIER * kPad] = 1;
@@ -1263,12 +1272,16 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
   const bool learned = a.policy == BLEST_POLICY_LEARNED && a.mlp != nullptr && a.mlp->valid;
   if (learned) mlp_to_lds(a.mlp, s_mlp);
   for (int i = threadIdx.x; i < kSingleHash + 1; i += BLOCK) hs[i] = (i == kSingleHash) ? 0 : -1;
-  clear_state<SIGMA>(a, gtid, nthreads);
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->single_gen[0] = 0u;
+  // state clear and level-0 seed before the registration barrier, which also
+  // publishes them (one device-wide barrier at kernel start)
+  clear_state<SIGMA>(a, gtid, nthreads, true);
+  if (blockIdx.x == 0) {
+    __syncthreads();  // block 0's counter clear before its seed counters
+    seed_source<SIGMA>(a, true);
+    if (threadIdx.x == 0) a.ctl->single_gen[0] = 0u;
+  }
   BarrierCtx bc;
   if (!barrier_register(a.ctl, &bc, a.timeout_ticks)) return;
-  if (blockIdx.x == 0) seed_source<SIGMA>(a);
-  if (!grid_barrier(a.ctl, bc)) return;
   unsigned episodes = 0;
   int level = 0;
   constexpr bool kPanelFmt = SIGMA == 8 && sizeof(SliceT) == 4;

@@ -249,6 +249,9 @@ __device__ __forceinline__ bool barrier_register(Ctl* ctl_in, BarrierCtx* bc, un
   const gptr<Ctl> ctl = to_global(ctl_in);
   __shared__ unsigned s_xcc, s_nlocal, s_nxcd;
   __shared__ int ok_flag;
+  // every wave's stores are performed before workgroup 0's release, so the
+  // registration also publishes what the workgroups wrote before it
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned x = xcc_id();
