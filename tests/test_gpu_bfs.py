@@ -288,3 +288,13 @@ def test_jaccard_reordering_exact_and_compresses(blest):
     assert np.array_equal(s_.cpu().numpy(), osum) and np.array_equal(c_.cpu().numpy(), occ)
     base.close()
     g.close()
+    # AUTO (Section "Reordering the Graph"): JaccardWithWindows for the
+    # scale-free-like R-MAT, RCM for the grid
+    auto = blest.Graph(rp, col)
+    nof_auto = blest.blest_reorder_jaccard(rp, col, 8, 1024)
+    assert auto.info()["reordered"] == 3 and auto.info()["n_slices"] == J.count_slices(rp, col, nof_auto, 8)
+    auto.close()
+    grp, gcol = inputs.grid_graph(40, 94)
+    auto = blest.Graph(grp, gcol)
+    assert auto.info()["reordered"] == 1
+    auto.close()
