@@ -88,12 +88,12 @@ def test_struct_layout_matches_c_compiler(tmp_path):
         ' offsetof(blest_opts, random_seed), offsetof(blest_opts, device), sizeof(blest_level_stat),'
         ' offsetof(blest_level_stat, t_step_us), sizeof(blest_graph_stats), sizeof(blest_csr),'
         ' sizeof(blest_ms_level_stat), offsetof(blest_ms_level_stat, t_engine_us),'
-        ' offsetof(blest_ms_level_stat, feat)); return 0;}\n')
+        ' offsetof(blest_ms_level_stat, feat)); printf("%zu\\n", offsetof(blest_opts, jaccard_window)); return 0;}\n')
     exe = tmp_path / "probe"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     exp = [ctypes.sizeof(blest.Opts), blest.Opts.random_seed.offset, blest.Opts.device.offset,
            ctypes.sizeof(blest.LevelStat), blest.LevelStat.t_step_us.offset, ctypes.sizeof(blest.GraphStats),
            ctypes.sizeof(blest.CSR), ctypes.sizeof(blest.MsLevelStat), blest.MsLevelStat.t_engine_us.offset,
-           blest.MsLevelStat.feat.offset]
+           blest.MsLevelStat.feat.offset, blest.Opts.jaccard_window.offset]
     assert got == exp
