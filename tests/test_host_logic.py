@@ -70,6 +70,12 @@ def test_jaccard_host_order_equals_oracle():
         got = blest.blest_reorder_jaccard(rp, col, sigma, window)
         ref = J.jaccard_with_windows(rp, col, sigma, window)
         assert np.array_equal(got, ref), (sigma, window, np.nonzero(got != ref)[0][:5])
+    # the hand-built cases where the Jaccard ratio and the plain overlap (or
+    # overlap / degree) choose different columns
+    from tests.test_oracle_pins import _jaccard_case
+    for cand in ([(3, 9), (2, 0)], [(4, 4), (3, 0)]):
+        rp, col = _jaccard_case(13, cand)
+        assert np.array_equal(blest.blest_reorder_jaccard(rp, col, 2, 4), J.jaccard_with_windows(rp, col, 2, 4))
     rp, col = inputs.rmat_graph(11, 11)
     nof = blest.blest_reorder_jaccard(rp, col, 8, 1024)
     assert J.count_slices(rp, col, nof, 8) < J.count_slices(rp, col, np.arange(rp.size - 1), 8)

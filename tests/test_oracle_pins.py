@@ -177,6 +177,33 @@ def test_far_equals_sums_when_all_sources_and_total_identity():
     assert oracle.far(rp, col, sub).sum() == s2.sum()
 
 
+def test_far_source_subsets_closed_forms():
+    """Eq. 4 over a proper subset S of the vertices: far[u] adds d(s, u) for
+    the sources s only, at the target u (not at the source)."""
+    n = 11
+    rp, col = H.path(n)
+    u = np.arange(n)
+    assert np.array_equal(oracle.far(rp, col, [0]), u)  # one end of a path: far[u] = u
+    assert np.array_equal(oracle.far(rp, col, [0, n - 1]), np.full(n, n - 1))  # both ends: u + (n-1-u)
+    assert np.array_equal(oracle.far(rp, col, [3, 3]), 2 * np.abs(u - 3))  # a repeated source counts twice
+    k = 9
+    rp, col = H.star(k + 1)  # centre 0, leaves 1..k
+    f = oracle.far(rp, col, np.arange(1, k + 1))
+    assert f[0] == k  # every leaf is one hop from the centre
+    assert (f[1:] == 2 * (k - 1)).all()  # two hops from the other k-1 leaves, 0 from itself
+    f = oracle.far(rp, col, [0])
+    assert f[0] == 0 and (f[1:] == 1).all()
+    d = 7
+    rp, col = H.hypercube(d)
+    v = np.arange(1 << d)
+    pc = np.array([bin(x).count("1") for x in v])
+    assert np.array_equal(oracle.far(rp, col, [0]), pc)  # Hamming distance to 0
+    assert np.array_equal(oracle.far(rp, col, [0, (1 << d) - 1]), np.full(1 << d, d))
+    # unreachable pairs add nothing: path 0-1-2 and edge 3-4, sources 0 and 3
+    rp, col = inputs.from_pairs(5, [0, 1, 3], [1, 2, 4])
+    assert oracle.far(rp, col, [0, 3]).tolist() == [0, 1, 2, 0, 1]
+
+
 # --------------------------------------------------------------------- BVSS
 
 def fig1_graph():
@@ -430,3 +457,49 @@ def test_jaccard_without_edges_keeps_the_order_and_handles_a_ragged_window():
     nof = J.jaccard_with_windows(rp, col, 2, 4)
     assert np.array_equal(np.sort(nof), np.arange(10))
     assert nof[1] == 0  # vertex 1 (degree 2, smallest such id) seeds the first window
+
+
+def _jaccard_case(seed_deg, cand):
+    """Window 0 = vertices 0..3 with sigma = 2: vertex 3 is the seed column
+    (the highest degree), vertex 0 a filler column with one private row, and
+    vertices 1, 2 the candidates, each given as (rows shared with the seed,
+    private rows). Every row is a vertex of id >= 4 adjacent to its columns only."""
+    us, vs = [], []
+    nxt = 4
+    seed_rows = list(range(nxt, nxt + seed_deg))
+    nxt += seed_deg
+    for r in seed_rows:
+        us.append(3)
+        vs.append(r)
+    for c, (shared, private) in zip((1, 2), cand):
+        for r in seed_rows[:shared]:
+            us.append(c)
+            vs.append(r)
+        for r in range(nxt, nxt + private):
+            us.append(c)
+            vs.append(r)
+        nxt += private
+    us.append(0)
+    vs.append(nxt)
+    nxt += 1
+    return inputs.from_pairs(nxt, us, vs)
+
+
+def test_jaccard_score_is_the_ratio_not_the_overlap():
+    """The second column of a slice set maximises inter / (|R| + deg - inter)
+    (the Jaccard similarity of Section "Increasing Compression Ratio"), which
+    differs from maximising the overlap inter or inter / deg. Values by hand,
+    seed column 3 of degree 13, so |R| = 13:
+      case 1: vertex 1 has inter 3, deg 12 -> 3/22; vertex 2 inter 2, deg 2 -> 2/13.
+              2/13 > 3/22, so vertex 2 joins the seed (overlap alone picks 1).
+      case 2: vertex 1 has inter 4, deg 8 -> 4/17; vertex 2 inter 3, deg 3 -> 3/13.
+              4/17 > 3/13, so vertex 1 joins the seed (inter / deg picks 2).
+    The second slice set is seeded by the higher-degree remaining column; the
+    filler (vertex 0) shares no row with it and comes last."""
+    from oracle import jaccard as J
+    rp, col = _jaccard_case(13, [(3, 9), (2, 0)])
+    nof = J.jaccard_with_windows(rp, col, sigma=2, window=4)
+    assert nof[:4].tolist() == [3, 2, 1, 0]
+    rp, col = _jaccard_case(13, [(4, 4), (3, 0)])
+    nof = J.jaccard_with_windows(rp, col, sigma=2, window=4)
+    assert nof[:4].tolist() == [3, 1, 2, 0]
