@@ -190,9 +190,12 @@ def profile_leg(policy_name, n_sources=8):
     c = torch.empty_like(a)
     c.copy_(a)
     torch.cuda.synchronize()
-    g.set_policy(getattr(blest.Policy, policy_name.upper()))
-    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
-    ts = timed_sources(g, srcs, out, torch)
+    try:
+        g.set_policy(getattr(blest.Policy, policy_name.upper()))
+        out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        ts = timed_sources(g, srcs, out, torch)
+    finally:
+        g.close()  # release device memory before the profiler's own exit handlers run
     print(json.dumps({"profile_leg": policy_name, "sources": n_sources, "ms_per_source": float(np.mean(ts)),
                       "calibration_copy_bytes": 2 * a.numel() * 4, "kernel_source_sha256_16": kernel_source_hash()}),
           flush=True)

@@ -7,8 +7,11 @@ there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 from enum import IntEnum
 
 import numpy as np
@@ -321,13 +324,32 @@ def blest_mlp_train(params, m, v, x, y, w, batch, steps, lr, seed, loss_log=None
 
 # ---- convenience wrapper ---------------------------------------------------
 
+# Graphs still open; closed by an exit handler while the HIP runtime is intact.
+_live_graphs = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_graphs():
+    for g in list(_live_graphs):
+        try:
+            g.close()
+        except Exception:
+            pass
+
+
 class Graph:
-    """A device-resident BVSS graph. Methods allocate outputs with torch."""
+    """A device-resident BVSS graph. Methods allocate outputs with torch.
+
+    Call close() (or use the graph as a context manager) to release its device
+    memory. Graphs left open are closed by an exit handler that runs before the
+    interpreter finalises; a graph collected during finalisation is not freed
+    (the process is ending and the HIP runtime may already be torn down)."""
 
     def __init__(self, row_ptr, col, **opts):
         self._h = None
         self.opts = default_opts(**opts)
         self._h = blest_build(row_ptr, col, self.opts)
+        _live_graphs.add(self)
         st = GraphStats()
         _check(lib().blest_graph_info(self._h, ctypes.byref(st)))
         self.n = st.n
@@ -336,10 +358,20 @@ class Graph:
 
     def close(self):
         if self._h is not None:
-            blest_free(self._h)
-            self._h = None
+            h, self._h = self._h, None
+            _live_graphs.discard(self)
+            blest_free(h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
