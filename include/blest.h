@@ -148,6 +148,26 @@ blest_status blest_bfs_probe(blest_graph* g, int32_t src, int32_t* levels_dev, v
  * INVALID_ARG, TIMEOUT, HIP. */
 blest_status blest_msbfs(blest_graph* g, const int32_t* srcs_host, int32_t k, int16_t* levels_dev, void* stream);
 
+/* blest_msbfs for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): same
+ * arguments, same result, and no hipMalloc/hipFree or allocating library call.
+ * The source list and the batch plan go to a static device array of
+ * BLEST_MSBFS_NOALLOC_MAX_SOURCES + BLEST_MSBFS_NOALLOC_MAX_SOURCES / 16 int32
+ * (278,528 bytes) that each device holds until the process ends; the graph's
+ * multi-source working buffers must already exist, i.e. an earlier
+ * blest_msbfs, blest_msbfs_batched, blest_closeness or blest_far call on this
+ * graph used a batch width of at least opts.msbfs_width. Always one
+ * persistent launch (opts.msbfs_graph is ignored); the call waits for the
+ * stream twice while staging the sources and the plan (host memory is read
+ * through a fixed buffer). Calls that overlap on one device race on that array
+ * (as calls on one graph race on the graph): serialise them.
+ * Errors: INVALID_ARG (k > BLEST_MSBFS_NOALLOC_MAX_SOURCES, NULL pointers),
+ * UNSUPPORTED (the graph's multi-source buffers are not allocated yet), and
+ * those of blest_msbfs. */
+#define BLEST_MSBFS_NOALLOC_MAX_SOURCES 65536
+blest_status blest_msbfs_noalloc(blest_graph* g, const int32_t* srcs_host, int32_t k, int16_t* levels_dev,
+                                 void* stream);
+
 /* Multi-source BFS with an explicit batch plan: the k sources are split, in
  * order, into consecutive batches of widths[0], widths[1], ... sources (each
  * 64, 128, 256 or 512; the last width repeats), all run in one persistent

@@ -125,6 +125,7 @@ SIGNATURES = {
     "blest_bfs_probe": (_i32, [_vp, _i32, _vp, _vp]),
     "blest_msbfs": (_i32, [_vp, _p32, _i32, _vp, _vp]),
     "blest_msbfs_batched": (_i32, [_vp, _p32, _i32, _p32, _i32, _vp, _vp]),
+    "blest_msbfs_noalloc": (_i32, [_vp, _p32, _i32, _vp, _vp]),
     "blest_closeness": (_i32, [_vp, _p32, _i64, _vp, _vp, _vp, _vp]),
     "blest_far": (_i32, [_vp, _p32, _i64, _vp, _vp]),
     "blest_msbfs_probe": (_i32, [_vp, _p32, _i32, _p32, _i32, _vp, _vp]),
@@ -244,6 +245,12 @@ def blest_bfs_probe(h, src: int, levels: torch.Tensor, stream=None):
 def blest_msbfs(h, srcs, levels: torch.Tensor, stream=None):
     s = np.ascontiguousarray(srcs, dtype=np.int32)
     _check(lib().blest_msbfs(h, s.ctypes.data_as(_p32) if s.size else None, s.size, _ptr(levels), _stream(stream)))
+
+
+def blest_msbfs_noalloc(h, srcs, levels: torch.Tensor, stream=None):
+    s = np.ascontiguousarray(srcs, dtype=np.int32)
+    _check(lib().blest_msbfs_noalloc(h, s.ctypes.data_as(_p32) if s.size else None, s.size, _ptr(levels),
+                                     _stream(stream)))
 
 
 def blest_msbfs_batched(h, srcs, widths, levels: torch.Tensor, stream=None):
@@ -406,6 +413,11 @@ class Graph:
         if out is None:
             out = torch.empty((k, self.n), dtype=torch.int16, device=self.device)
         blest_msbfs(self._h, srcs, out, stream)
+        return out
+
+    def msbfs_noalloc(self, srcs, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """blest_msbfs_noalloc: the caller passes the (k, n) int16 output."""
+        blest_msbfs_noalloc(self._h, srcs, out, stream)
         return out
 
     def msbfs_batched(self, srcs, widths, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:

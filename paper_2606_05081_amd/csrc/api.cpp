@@ -661,6 +661,30 @@ blest_status blest_msbfs(blest_graph* g, const int32_t* srcs, int32_t k, int16_t
   return wait_and_check(g, st);
 }
 
+blest_status blest_msbfs_noalloc(blest_graph* g, const int32_t* srcs, int32_t k, int16_t* levels_dev, void* stream) {
+  if (!g) return fail(BLEST_ERR_INVALID_ARG, "NULL graph");
+  if (k < 0) return fail(BLEST_ERR_INVALID_ARG, "negative source count");
+  if (k > BLEST_MSBFS_NOALLOC_MAX_SOURCES)
+    return fail(BLEST_ERR_INVALID_ARG, "blest_msbfs_noalloc takes at most BLEST_MSBFS_NOALLOC_MAX_SOURCES (" +
+                                           std::to_string(BLEST_MSBFS_NOALLOC_MAX_SOURCES) + ") sources per call");
+  if (k == 0) return BLEST_OK;
+  if (!srcs || !levels_dev) return fail(BLEST_ERR_INVALID_ARG, "NULL sources or output");
+  for (int32_t c = 0; c < k; ++c)
+    if (srcs[c] < 0 || srcs[c] >= g->d.n) return fail(BLEST_ERR_OUT_OF_RANGE, "source vertex out of range");
+  CK(hipSetDevice(g->d.device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = blest::ms_run_noalloc(g->d, &g->ms, srcs, g->perm.empty() ? nullptr : g->perm.data(), k,
+                                       g->opts.msbfs_width, g->opts.policy, g->opts.eta, g->opts.random_seed,
+                                       levels_dev, st);
+  if (e == hipErrorNotReady)
+    return fail(BLEST_ERR_UNSUPPORTED,
+                "the graph's multi-source buffers are not allocated yet: make one blest_msbfs call of this batch "
+                "width on the graph first");
+  if (e != hipSuccess) return hip_fail(e, "msbfs_noalloc");
+  if (g->opts.async) return BLEST_OK;
+  return wait_and_check(g, st);
+}
+
 blest_status blest_msbfs_batched(blest_graph* g, const int32_t* srcs, int32_t k, const int32_t* widths,
                                  int32_t nwidths, int16_t* levels_dev, void* stream) {
   if (!g) return fail(BLEST_ERR_INVALID_ARG, "NULL graph");

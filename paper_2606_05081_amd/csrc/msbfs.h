@@ -51,6 +51,16 @@ hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs_internal, in
                   int nwidths, int policy, float eta, uint64_t seed, int16_t* levels16, int64_t* sums,
                   int64_t* reach, double* cc, hipStream_t st, int graph = 0, int64_t* far = nullptr,
                   int probe = 0);
+// True when every buffer a persistent multi-source launch of width 64 * W
+// needs is already allocated for this graph.
+bool ms_ready(const DevGraph& g, const MsDev* ms, int W);
+// blest_msbfs without device allocation: the source list (mapped to internal
+// ids through perm, a host array, when not NULL) and the batch plan of
+// uniform `width` go to a static device array; always the persistent launch.
+// hipErrorNotReady: the graph's multi-source buffers are not allocated yet;
+// hipErrorInvalidValue: k above BLEST_MSBFS_NOALLOC_MAX_SOURCES or a bad width.
+hipError_t ms_run_noalloc(const DevGraph& g, MsDev* ms, const int32_t* srcs, const int32_t* perm, int32_t k,
+                          int width, int policy, float eta, uint64_t seed, int16_t* levels16, hipStream_t st);
 void ms_release(MsDev* ms);   // frees the per-vertex arrays
 void ms_free_all(MsDev* ms);  // frees everything
 void ms_reset(MsDev* ms);     // clears marks after a device-side error

@@ -27,6 +27,7 @@
 // nonzero, int16 levels are written, and per-source counts of newly reached
 // vertices feed the closeness sums.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "device_common.h"
@@ -884,6 +885,51 @@ hipError_t ensure(const DevGraph& g, MsDev* ms, int wmax, int32_t k, int nbatche
   return hipSuccess;
 }
 
+// Kernel arguments of one multi-source call whose source list and batch plan
+// are already on the device (srcs_dev, batches_dev).
+MsArgs ms_args(const DevGraph& g, const MsDev* ms, const int32_t* srcs_dev, const MsBatch* batches_dev, int nplan,
+               int policy, float eta, uint64_t seed, int16_t* levels16, int64_t* sums, int64_t* reach, double* cc,
+               int64_t* far, int probe) {
+  MsArgs a{};
+  a.rp = g.rp;
+  a.col = g.col;
+  a.slice_ptr = g.slice_ptr;
+  a.slices = g.slices;
+  a.orig_id = g.orig_id;
+  a.n = g.n;
+  a.m = g.m;
+  a.nsets = g.nsets;
+  a.tau = g.tau;
+  a.F = ms->F;
+  a.V = ms->V;
+  a.N = ms->N;
+  a.act = ms->act;
+  a.dirty = ms->dirty;
+  a.queue[0] = ms->queue[0];
+  a.queue[1] = ms->queue[1];
+  a.srcs = srcs_dev;
+  a.batches = batches_dev;
+  a.nbatches = nplan;
+  a.levels16 = levels16;
+  a.sums = sums;
+  a.reach = reach;
+  a.cc = cc;
+  a.far = far;
+  a.nvss = g.nvss;
+  a.nslices = g.nslices;
+  a.mlp = g.ms_mlp;
+  a.probe = probe;
+  a.log = ms->log;
+  a.log_cap = ms->log_cap;
+  a.part = ms->part;
+  a.ctl = g.ctl;
+  a.policy = policy;
+  a.eta = eta;
+  a.seed = seed;
+  a.timeout_ticks = 3000000000ULL;  // 30 s
+  return a;
+}
+
 }  // namespace
 
 hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, const int32_t* widths, int nwidths,
@@ -909,43 +955,8 @@ hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, 
     return e;
   // the copies read pageable host memory; wait so `plan` may go out of scope
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-  MsArgs a{};
-  a.rp = g.rp;
-  a.col = g.col;
-  a.slice_ptr = g.slice_ptr;
-  a.slices = g.slices;
-  a.orig_id = g.orig_id;
-  a.n = g.n;
-  a.m = g.m;
-  a.nsets = g.nsets;
-  a.tau = g.tau;
-  a.F = ms->F;
-  a.V = ms->V;
-  a.N = ms->N;
-  a.act = ms->act;
-  a.dirty = ms->dirty;
-  a.queue[0] = ms->queue[0];
-  a.queue[1] = ms->queue[1];
-  a.srcs = ms->srcs;
-  a.batches = static_cast<const MsBatch*>(ms->batches);
-  a.nbatches = nplan;
-  a.levels16 = levels16;
-  a.sums = sums;
-  a.reach = reach;
-  a.cc = cc;
-  a.far = far;
-  a.nvss = g.nvss;
-  a.nslices = g.nslices;
-  a.mlp = g.ms_mlp;
-  a.probe = probe;
-  a.log = ms->log;
-  a.log_cap = ms->log_cap;
-  a.part = ms->part;
-  a.ctl = g.ctl;
-  a.policy = policy;
-  a.eta = eta;
-  a.seed = seed;
-  a.timeout_ticks = 3000000000ULL;  // 30 s
+  MsArgs a = ms_args(g, ms, ms->srcs, static_cast<const MsBatch*>(ms->batches), nplan, policy, eta, seed, levels16,
+                     sums, reach, cc, far, probe);
   const unsigned shmem = policy == BLEST_POLICY_LEARNED ? kLdsMlpFloats * sizeof(float) : 0u;
   if (!graph || probe) {
     void* args[] = {static_cast<void*>(&a)};
@@ -1041,6 +1052,81 @@ void ms_reset(MsDev* ms) {
   // After a device-side error N and dirty may hold stale marks.
   if (ms->N && ms->nhat) (void)hipMemset(ms->N, 0, static_cast<size_t>(ms->nhat) * ms->wmax * 8);
   if (ms->dirty && ms->nsets) (void)hipMemset(ms->dirty, 0, static_cast<size_t>(ms->nsets));
+}
+
+// ----------------------------------------------------------- no-alloc entry
+// blest_msbfs_noalloc keeps the source list and the batch plan of a call in
+// this array instead of in buffers the library allocates: the first
+// BLEST_MSBFS_NOALLOC_MAX_SOURCES entries hold internal source ids, then one
+// 4-int batch descriptor per batch (at most one per 64 sources). Each device
+// holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress gives for the current device.
+constexpr int kNoAllocMaxSources = BLEST_MSBFS_NOALLOC_MAX_SOURCES;
+constexpr int kNoAllocMaxBatches = kNoAllocMaxSources / 64;
+static_assert(sizeof(MsBatch) == 4 * sizeof(int32_t), "batch descriptor layout");
+static __device__ __align__(256) int32_t scratch[kNoAllocMaxSources + 4 * kNoAllocMaxBatches];
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+int32_t* g_noalloc_ptr[kNoAllocDevices] = {};
+
+// This device's copy of `scratch`, looked up once per device (the caller
+// has made `device` current).
+hipError_t noalloc_scratch(int device, int32_t** out) {
+  if (device < 0 || device >= kNoAllocDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[device] = static_cast<int32_t*>(p);
+  }
+  *out = g_noalloc_ptr[device];
+  return hipSuccess;
+}
+
+}  // namespace
+
+bool ms_ready(const DevGraph& g, const MsDev* ms, int W) {
+  return ms->wmax >= W && ms->nhat == g.nsets * g.sigma && ms->F && ms->V && ms->N && ms->act && ms->dirty &&
+         ms->queue[0] && ms->queue[1] && ms->grid > 0 && ms->log && ms->part && ms->part_blocks >= ms->grid;
+}
+
+hipError_t ms_run_noalloc(const DevGraph& g, MsDev* ms, const int32_t* srcs, const int32_t* perm, int32_t k,
+                          int width, int policy, float eta, uint64_t seed, int16_t* levels16, hipStream_t st) {
+  if (k <= 0) return hipSuccess;
+  if (k > kNoAllocMaxSources || width % 64 != 0 || width < 64 || width > 64 * kWMax) return hipErrorInvalidValue;
+  const int W = width / 64;
+  if (!ms_ready(g, ms, W)) return hipErrorNotReady;
+  int32_t* base = nullptr;
+  hipError_t e = noalloc_scratch(g.device, &base);
+  if (e != hipSuccess) return e;
+  int32_t* dsrcs = base;
+  MsBatch* dplan = reinterpret_cast<MsBatch*>(base + kNoAllocMaxSources);
+  // Internal source ids through a fixed host staging buffer; the copies read
+  // pageable memory, so each is waited for before the buffer is refilled.
+  constexpr int kStage = 4096;
+  int32_t stage[kStage];
+  for (int32_t off = 0; off < k; off += kStage) {
+    const int32_t c = std::min<int32_t>(kStage, k - off);
+    for (int32_t i = 0; i < c; ++i) stage[i] = perm ? perm[srcs[off + i]] : srcs[off + i];
+    if ((e = hipMemcpyAsync(dsrcs + off, stage, sizeof(int32_t) * c, hipMemcpyHostToDevice, st)) != hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  }
+  const int per = 64 * W;
+  const int nplan = (k + per - 1) / per;
+  MsBatch plan[kNoAllocMaxBatches];
+  for (int i = 0; i < nplan; ++i) plan[i] = MsBatch{i * per, std::min(per, k - i * per), W, 0};
+  if ((e = hipMemcpyAsync(dplan, plan, sizeof(MsBatch) * nplan, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  MsArgs a = ms_args(g, ms, dsrcs, dplan, nplan, policy, eta, seed, levels16, nullptr, nullptr, nullptr, nullptr, 0);
+  const unsigned shmem = policy == BLEST_POLICY_LEARNED ? kLdsMlpFloats * sizeof(float) : 0u;
+  void* args[] = {static_cast<void*>(&a)};
+  return hipLaunchCooperativeKernel(ms_kernel(g), dim3(ms->grid), dim3(ms->block), args, shmem, st);
 }
 
 }  // namespace blest
