@@ -82,3 +82,18 @@ def dense_eq1_levels(rp, col, src):
         lev[x] = k
         v |= x
     return lev
+
+
+def install_switch_models(g, single=True, multi=True):
+    """Installs the committed switch networks (single- and multi-source) on g."""
+    import json
+    import os
+    pkg = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2606_05081_amd")
+    for name, on, setter in (("switch_model.json", single, g.set_switch_model),
+                             ("switch_model_ms.json", multi, g.set_ms_switch_model)):
+        if not on:
+            continue
+        with open(os.path.join(pkg, name)) as f:
+            m = json.load(f)
+        setter(np.array(m["params"], np.float32), np.array(m["mean"], np.float32), np.array(m["std"], np.float32),
+               m.get("min_confidence", 0.5))

@@ -244,7 +244,9 @@ def test_probe_mode_same_levels_and_times(blest):
 @pytest.mark.parametrize("which", ["rmat22", "grid2048"])
 def test_full_size_sampled_sources(blest, which):
     """The single-GPU workload at full size: 4,194,304-vertex R-MAT (scale 22,
-    edge factor 16) and 2048x2048 grid with 10% edge deletion (RCM-reordered)."""
+    edge factor 16) and 2048x2048 grid with 10% edge deletion (RCM-reordered),
+    under every policy the benchmark times or the learned switch may pick:
+    certificate on three sources, oracle equality on the first."""
     if which == "rmat22":
         rp, col = inputs.rmat_graph(22, 1020)
         srcs = inputs.sources(rp, 64, seed=1021)
@@ -253,17 +255,91 @@ def test_full_size_sampled_sources(blest, which):
         srcs = inputs.sources(rp, 64, seed=1023)
     print(f"[{which}] n={rp.size - 1} m={col.size}", flush=True)
     g = blest.Graph(rp, col)
+    H.install_switch_models(g, multi=False)
+    pols = ("HEURISTIC", "BVSS", "LEARNED", "PUSH") if which == "rmat22" else ("HEURISTIC", "BVSS", "LEARNED")
     for i, s in enumerate(srcs[:3]):
         s = int(s)
-        for pol in ("HEURISTIC", "BVSS"):
+        ref = oracle.bfs(rp, col, s) if i == 0 else None
+        for pol in pols:
             g.set_policy(getattr(blest.Policy, pol), 10.0)
             lev = g.bfs(s).cpu().numpy()
             assert oracle.certificate(rp, col, s, lev) == (0, -1), pol
-            if i == 0:
-                assert np.array_equal(lev, oracle.bfs(rp, col, s)), pol
+            if ref is not None:
+                assert np.array_equal(lev, ref), pol
             if which == "rmat22" and pol == "BVSS":
                 # the dense levels of the plain method read the panel-blocked copy
                 assert any(r["bvss_panel"] for r in g.level_stats()[:-1])
+    g.close()
+
+
+# Learned vs heuristic switch workloads at full size: R-MAT scale 24 (16.8M
+# vertices, edge factor 16) and Erdos-Renyi with 2^24 vertices and 8 * 2^24
+# uniform pairs. At 2^24 vertices the packed 32-bit slice word reaches its
+# 24-bit row limit and the panel layout holds more panels than workgroups.
+_C3 = {}
+
+
+@pytest.fixture(scope="module", params=["rmat24", "er24"])
+def c3_graph(request, blest):
+    which = request.param
+    if which == "rmat24":
+        rp, col = inputs.rmat_graph(24, 1030)
+        srcs = inputs.sources(rp, 3, seed=1031)
+    else:
+        rp, col = inputs.er_graph(24, 1032)
+        srcs = inputs.sources(rp, 3, seed=1033)
+    print(f"[{which}] n={rp.size - 1} m={col.size}", flush=True)
+    g = blest.Graph(rp, col)
+    H.install_switch_models(g, multi=False)
+    info = g.info()
+    ref = oracle.bfs(rp, col, int(srcs[0]))
+    yield which, rp, col, srcs, g, info, ref
+    g.close()
+
+
+@pytest.mark.parametrize("pol", ["HEURISTIC", "LEARNED", "BVSS"])
+def test_c3_full_size(blest, c3_graph, pol):
+    which, rp, col, srcs, g, info, ref = c3_graph
+    assert info["slice_bytes"] == 4  # the 32-bit (row << 8 | mask) form at its 24-bit row limit
+    g.set_policy(getattr(blest.Policy, pol), 10.0)
+    for i, s in enumerate(srcs):
+        s = int(s)
+        lev = g.bfs(s).cpu().numpy()
+        print(f"[{which} {pol}] source {s}: {int(lev.max()) + 1} levels", flush=True)
+        assert oracle.certificate(rp, col, s, lev) == (0, -1), (which, pol, s)
+        if i == 0:
+            assert np.array_equal(lev, ref), (which, pol)
+        if pol == "BVSS" and which == "rmat24":
+            assert any(r["bvss_panel"] for r in g.level_stats()[:-1])
+
+
+def test_er20_every_policy(blest):
+    """Erdos-Renyi, 2^20 vertices, mean degree 16: every policy exact."""
+    rp, col = inputs.er_graph(20, 2301)
+    g = blest.Graph(rp, col)
+    H.install_switch_models(g, multi=False)
+    for s in inputs.sources(rp, 2, seed=2302):
+        ref = oracle.bfs(rp, col, int(s))
+        run_all_policies(blest, g, int(s), ref, seeds=(5, 6))
+        g.set_policy(blest.Policy.LEARNED, 10.0)
+        assert np.array_equal(g.bfs(int(s)).cpu().numpy(), ref)
+    g.close()
+
+
+@pytest.mark.parametrize("panel", [1, 2])
+def test_more_panels_than_workgroups(blest, panel):
+    """32-row panels on scale-14 R-MAT: 512 panels, so each persistent
+    workgroup owns several and runs the fused Stage 2 once per panel."""
+    rp, col = inputs.rmat_graph(14, 2311)
+    g = blest.Graph(rp, col, panel=panel, panel_log2_rows=5)
+    info = g.info()
+    assert info["panel_log2_rows"] == 5 and (info["n"] >> 5) > info["grid_blocks"]
+    for s in inputs.sources(rp, 3, seed=2312):
+        ref = oracle.bfs(rp, col, int(s))
+        run_all_policies(blest, g, int(s), ref, seeds=(8,))
+        g.set_policy(blest.Policy.BVSS, 10.0)
+        g.bfs(int(s))
+        assert any(r["bvss_panel"] for r in g.level_stats()[:-1])
     g.close()
 
 

@@ -141,9 +141,31 @@ def test_msbfs_full_size_rmat20_sampled_rows(blest):
     for r in rows:
         lev = got[r].cpu().numpy().astype(np.int32)
         assert np.array_equal(lev, oracle.bfs(rp, col, int(srcs[r]))), r
-    for r in (5, 300, 700):
-        lev = got[r].cpu().numpy().astype(np.int32)
+    got = got.cpu().numpy()
+    for r in range(5, 960, 15):  # 64 more rows, spread over all four batches
+        lev = got[r].astype(np.int32)
         assert oracle.certificate(rp, col, int(srcs[r]), lev) == (0, -1), r
+    g.close()
+
+
+def test_er18_msbfs_and_closeness_every_policy(blest):
+    """Erdos-Renyi, 2^18 vertices, mean degree 16 (no hubs, no dense
+    low-degree levels the R-MAT-trained switch has seen): multi-source levels,
+    sums, reach and closeness exact under every policy, the multi-source
+    switch network included."""
+    rp, col = inputs.er_graph(18, 2321)
+    srcs = inputs.sources(rp, 700, seed=2322)
+    ref = oracle.msbfs16(rp, col, srcs)
+    osum, oreach, occ = oracle.closeness(rp, col, srcs)
+    g = blest.Graph(rp, col)
+    H.install_switch_models(g)
+    for pol in POLICIES + ["LEARNED"]:
+        g.set_policy(getattr(blest.Policy, pol), 10.0, 3)
+        assert np.array_equal(g.msbfs_batched(srcs, [64, 128, 256, 512]).cpu().numpy(), ref), pol
+        s_, r_, c_ = g.closeness(srcs)
+        assert np.array_equal(s_.cpu().numpy(), osum), pol
+        assert np.array_equal(r_.cpu().numpy(), oreach), pol
+        assert np.array_equal(c_.cpu().numpy(), occ), pol
     g.close()
 
 
@@ -179,7 +201,7 @@ def test_closeness_full_size(blest, which):
     else:
         rp, col = inputs.rmat_graph(23, 1052)
         srcs = inputs.sources(rp, 16384, seed=1053)
-        sample = srcs[::2731]
+        sample = srcs[::64]  # 256 sources, every batch of 512 contributes eight
     print(f"[{which}] n={rp.size - 1} m={col.size} k={srcs.size}", flush=True)
     g = blest.Graph(rp, col, msbfs_width=512)
     s, r, c = g.closeness(srcs)
@@ -191,7 +213,7 @@ def test_closeness_full_size(blest, which):
     with np.errstate(divide="ignore", invalid="ignore"):
         want = np.where(s > 0, (r - 1).astype(np.float64) / s.astype(np.float64), 0.0)
     assert np.array_equal(c, want)
-    idx = np.searchsorted(srcs, sample) if which == "rmat18_all" else np.array([list(srcs).index(x) for x in sample])
+    idx = np.searchsorted(srcs, sample) if which == "rmat18_all" else np.arange(0, srcs.size, 64)
     osum, oreach, occ = oracle.closeness(rp, col, sample)
     assert np.array_equal(s[idx], osum)
     assert np.array_equal(r[idx], oreach)
