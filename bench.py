@@ -124,21 +124,77 @@ def ms_learned_enable(g, trial_srcs, torch, blest):
     return t["learned"] < t["heuristic"], t
 
 
-def cpu_baseline(rp, col, srcs, budget_s=20.0):
-    """The oracle's queue BFS, one thread, on as many of the sources as fit the budget."""
+def host_description():
+    """Host CPU model, logical CPUs and the thread count the oracle legs use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    nproc = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = nproc
+    # the GPU box grants one GPU's share of its host (16 threads), whatever nproc shows
+    threads = max(1, min(avail, int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16))
+    smt = None
+    try:
+        with open("/sys/devices/system/cpu/smt/active") as f:
+            smt = f.read().strip() == "1"
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": nproc, "affinity_cpus": avail, "smt_active": smt, "threads_used": threads}
+
+
+def cpu_baseline(rp, col, srcs, edges, gpu_levels, ms_graphs, budget_s=8.0):
+    """The oracle on the host, on bounded samples of the same workloads.
+
+    value: all-core throughput of the oracle's queue BFS, one traversal per
+    source spread over the threads, on the R-MAT scale-22 sources (GTEPS =
+    their undirected component edges / wall time). Also: one thread alone,
+    the multi-source workload (scale-20 R-MAT) and the closeness workloads
+    (scale-18 and scale-23 R-MAT) in sources/s, and the sampled learned-switch
+    traversals of the timed run compared with the oracle's levels."""
     import oracle
-    edges, times = [], []
-    t_all = time.time()
-    for s in srcs:
+    host = host_description()
+    thr = host["threads_used"]
+    t_lev, times, one_edges, parity = time.time(), [], [], []
+    for i, s in enumerate(srcs):
         t0 = time.perf_counter()
         lev = oracle.bfs(rp, col, int(s))
-        t = time.perf_counter() - t0
-        times.append(t * 1e3)
-        edges.append(traversal_edges(rp, lev))
-        if time.time() - t_all > budget_s:
+        times.append((time.perf_counter() - t0) * 1e3)
+        one_edges.append(edges[i])
+        if i < len(gpu_levels):
+            parity.append(bool(np.array_equal(lev, gpu_levels[i])))
+        if time.time() - t_lev > budget_s and i + 1 >= len(gpu_levels):
             break
-    return {"value": round(harmonic_gteps(edges, times), 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": f"{len(times)} of the {len(srcs)} R-MAT scale-22 sources, FIFO-queue BFS on one host thread"}
+    single = harmonic_gteps(one_edges, times)
+    # all threads: one BFS per source (the oracle's threaded closeness runs exactly that)
+    k_all = min(len(srcs), 4 * thr)
+    t0 = time.perf_counter()
+    oracle.closeness(rp, col, np.asarray(srcs[:k_all], np.int32), threads=thr)
+    wall = time.perf_counter() - t0
+    allcore = float(np.sum(edges[:k_all])) / wall / 1e9
+    legs = {}
+    for tag, (grp, gcol, gsrcs, kind) in ms_graphs.items():
+        t0 = time.perf_counter()
+        if kind == "msbfs":
+            oracle.msbfs16(grp, gcol, gsrcs, threads=thr)
+        else:
+            oracle.closeness(grp, gcol, gsrcs, threads=thr)
+        legs[tag] = {"sources": int(len(gsrcs)), "sources_per_s": round(len(gsrcs) / (time.perf_counter() - t0), 2),
+                     "threads": thr}
+    return {"value": round(allcore, 4), "unit": "GTEPS", "cores": thr, "kind": "oracle",
+            "sample": f"{k_all} of the {len(srcs)} R-MAT scale-22 sources, one FIFO-queue BFS per source over "
+                      f"{thr} host threads",
+            "single_thread": {"value": round(single, 4), "unit": "GTEPS", "sources": len(times)},
+            "host": host, "legs_sources_per_s": legs,
+            "learned_levels_equal_oracle": f"{sum(parity)} of {len(parity)} sampled learned-switch traversals"}
 
 
 # The persistent kernel and what fixes its launch (block size, panel layout):
@@ -178,27 +234,141 @@ def traffic_from_profile():
         return None
 
 
-def profile_leg(policy_name, n_sources=8):
+def profile_leg(leg, n_sources=8):
     """A short run for rocprofv3: a 512 MiB device copy (counter calibration),
-    then n_sources traversals of the scale-22 workload with one policy."""
+    then one workload: `bvss` / `heuristic` -- n_sources traversals of the
+    scale-22 R-MAT with that policy; `msbfs` -- the scale-20 multi-source
+    workload (960 sources, batches 64/128/256/512, one launch); `msbfs_mfma`
+    -- the same with the neighbour check on the matrix cores; `closeness` --
+    4,096 sources of scale-18 R-MAT in batches of 512."""
     import torch
     from paper_2606_05081_amd import blest, inputs
-    rp, col = inputs.rmat_graph(22, 1020)
-    srcs = inputs.sources(rp, n_sources, seed=1021)
-    g = blest.Graph(rp, col, device=0, **{"async": 1})
+    if leg in ("bvss", "heuristic"):
+        rp, col = inputs.rmat_graph(22, 1020)
+    elif leg in ("msbfs", "msbfs_mfma"):
+        rp, col = inputs.rmat_graph(20, 1040)
+    else:
+        rp, col = inputs.rmat_graph(18, 1050)
+    g = blest.Graph(rp, col, device=0, msbfs_width=512, ms_mfma=int(leg == "msbfs_mfma"), **{"async": 1})
     a = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
     c = torch.empty_like(a)
     c.copy_(a)
     torch.cuda.synchronize()
     try:
-        g.set_policy(getattr(blest.Policy, policy_name.upper()))
-        out = torch.empty(g.n, dtype=torch.int32, device="cuda")
-        ts = timed_sources(g, srcs, out, torch)
+        if leg in ("bvss", "heuristic"):
+            g.set_policy(getattr(blest.Policy, leg.upper()))
+            out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+            ms = float(np.mean(timed_sources(g, inputs.sources(rp, n_sources, seed=1021), out, torch)))
+        elif leg in ("msbfs", "msbfs_mfma"):
+            srcs = inputs.sources(rp, 960, seed=1041)
+            out = torch.empty((960, g.n), dtype=torch.int16, device="cuda")
+            ms = timed_call(lambda: (g.msbfs_batched(srcs, [64, 128, 256, 512], out), g.sync()), torch)
+        else:
+            srcs = np.arange(0, 4096, dtype=np.int32)
+            ms = timed_call(lambda: (g.closeness(srcs), g.sync()), torch)
     finally:
         g.close()  # release device memory before the profiler's own exit handlers run
-    print(json.dumps({"profile_leg": policy_name, "sources": n_sources, "ms_per_source": float(np.mean(ts)),
-                      "calibration_copy_bytes": 2 * a.numel() * 4, "kernel_source_sha256_16": kernel_source_hash()}),
-          flush=True)
+    copy_bytes = 2 * a.numel() * 4
+    del a, c
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    print(json.dumps({"profile_leg": leg, "ms": ms, "calibration_copy_bytes": copy_bytes,
+                      "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
+
+
+def load_eta_tuned():
+    """eta of Eq. 3 tuned on the switch network's training graphs
+    (python -m paper_2606_05081_amd.switch --tune-eta), or None."""
+    path = os.path.join(ROOT, "paper_2606_05081_amd", "switch_eta.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return float(json.load(f)["eta"])
+
+
+def install_model(g, model):
+    g.set_switch_model(np.array(model["params"], np.float32), np.array(model["mean"], np.float32),
+                       np.array(model["std"], np.float32), model.get("min_confidence", 0.5))
+
+
+def switching_enable(g, trial_srcs, eta, torch, blest, trials=3):
+    """The paper's per-graph enable of direction switching (switching
+    analysis of its experiments): three trial traversals with Eq. 3 and
+    three without switching (BVSS top-down at every level); switching stays on
+    only if its trials were faster. Returns (enabled, {name: ms})."""
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    t = {}
+    for name, pol in (("switching", blest.Policy.HEURISTIC), ("no_switching", blest.Policy.BVSS)):
+        g.set_policy(pol, eta)
+        g.bfs(int(trial_srcs[0]), out)
+        t[name] = float(np.mean(timed_sources(g, trial_srcs[:trials], out, torch)))
+    return t["switching"] < t["no_switching"], t
+
+
+def policy_gteps(g, srcs, edges, out, pol, eta, torch, reps=1):
+    g.set_policy(pol, eta)
+    timed_sources(g, srcs[:2], out, torch)
+    per = np.mean(np.array([timed_sources(g, srcs, out, torch) for _ in range(reps)]), axis=0)
+    return harmonic_gteps(edges, per), per
+
+
+def c3_leg(kind, scale, gseed, sseed, model, eta_tuned, torch, blest, inputs, nsrc=16):
+    """Learned vs heuristic switch on a held-out graph: R-MAT scale 24 or
+    Erdos-Renyi 2^24 (8 * 2^24 uniform pairs). Heuristic = Eq. 3 with the
+    paper's per-graph enable of switching, at eta = 10 and at the tuned eta;
+    learned = the switch network, kept for the graph only if three trial
+    traversals beat Eq. 3 (eta = 10)."""
+    t0 = time.time()
+    rp, col = inputs.rmat_graph(scale, gseed) if kind == "rmat" else inputs.er_graph(scale, gseed)
+    srcs = inputs.sources(rp, nsrc, seed=sseed)
+    g = blest.Graph(rp, col, device=0, **{"async": 1})
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    edges = []
+    g.set_policy(blest.Policy.HEURISTIC)
+    for s in srcs:
+        g.bfs(int(s), out)
+        g.sync()
+        edges.append(traversal_edges(rp, out.cpu().numpy()))
+    res = {"graph": f"{kind}{scale}", "n": g.n, "m": g.m, "sources": nsrc, "build_s": round(time.time() - t0, 1)}
+    trial = inputs.sources(rp, 3, seed=sseed + 1)
+    plain, _ = policy_gteps(g, srcs, edges, out, blest.Policy.BVSS, 10.0, torch)
+    res["plain_method_gteps"] = round(plain, 3)
+    for tag, eta in (("eta10", 10.0), ("eta_tuned", eta_tuned)):
+        if eta is None:
+            continue
+        gt, _ = policy_gteps(g, srcs, edges, out, blest.Policy.HEURISTIC, eta, torch)
+        en, tt = switching_enable(g, trial, eta, torch, blest)
+        res[f"heuristic_{tag}"] = {"eta": eta, "gteps_switching": round(gt, 3), "switching_enabled_by_trials": en,
+                                   "gteps": round(gt if en else plain, 3)}
+    if model is not None:
+        install_model(g, model)
+        lg, _ = policy_gteps(g, srcs, edges, out, blest.Policy.LEARNED, 10.0, torch)
+        from paper_2606_05081_amd import switch
+        en, tt = switch.per_graph_enable(g, trial)
+        res["learned"] = {"gteps_network": round(lg, 3), "enabled_by_trials": bool(en),
+                          "gteps": round(lg if en else res["heuristic_eta10"]["gteps_switching"], 3)}
+        for tag in ("eta10", "eta_tuned"):
+            if f"heuristic_{tag}" in res:
+                res[f"learned_over_heuristic_{tag}"] = round(res["learned"]["gteps"] / res[f"heuristic_{tag}"]["gteps"],
+                                                            4)
+    g.close()
+    print(f"# C3 {res}", file=sys.stderr, flush=True)
+    return res
+
+
+def ms_algorithmic_bytes(recs, n, nsets, sigma, slice_bytes, k):
+    """Lower bound of the bytes a multi-source call must move, from its level
+    records: per level, the queued slices (slice_bytes each), 16 B per queued
+    VSS descriptor and the sigma * kappa / 8 frontier bytes each VSS stages;
+    per new (vertex, traversal-word) the visited, frontier and next words
+    (3 x 8 B, counted once per new pair / 64 as a lower bound); and the int16
+    level of every (source, vertex) pair."""
+    total = 2 * k * n
+    for r in recs:
+        kappa = r["width"]
+        total += slice_bytes * r["queue_slices"] + 16 * r["queue"] + sigma * kappa // 8 * r["queue"]
+        total += 24 * ((r["new_pairs"] + 63) // 64)
+    return int(total)
 
 
 def main():
@@ -207,9 +377,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sources", type=int, default=64)
-    ap.add_argument("--no-extras", action="store_true", help="skip grid, msBFS and CPU legs")
-    ap.add_argument("--profile-leg", choices=["heuristic", "bvss"], default=None,
-                    help="only a short run of one policy plus a calibration copy, for rocprofv3")
+    ap.add_argument("--no-extras", action="store_true", help="skip grid, msBFS, C3 and CPU legs")
+    ap.add_argument("--no-c3", action="store_true", help="skip the scale-24 R-MAT and 2^24 ER legs")
+    ap.add_argument("--profile-leg", choices=["heuristic", "bvss", "msbfs", "msbfs_mfma", "closeness"], default=None,
+                    help="only a short run of one workload plus a calibration copy, for rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is not built "
@@ -234,7 +405,7 @@ def main():
           f"vss={info['n_vss']} grid={info['grid_blocks']}x{info['block_size']}", file=sys.stderr, flush=True)
     out = torch.empty(g.n, dtype=torch.int32, device=dev)
 
-    # exact edge counts per source (and a parity spot check against the certificate later)
+    # exact edge counts per source
     edges = []
     for s in srcs:
         g.set_policy(blest.Policy.HEURISTIC)
@@ -243,13 +414,13 @@ def main():
         edges.append(traversal_edges(rp, out.cpu().numpy()))
 
     model = load_switch_model()
+    eta_tuned = load_eta_tuned()
     policy = "heuristic"
     if model is not None:
-        g.set_switch_model(np.array(model["params"], np.float32), np.array(model["mean"], np.float32),
-                           np.array(model["std"], np.float32), model.get("min_confidence", 0.5))
+        install_model(g, model)
 
-    def run_policy(pol, steps, warmup):
-        g.set_policy(pol, 10.0)
+    def run_policy(pol, steps, warmup, eta=10.0):
+        g.set_policy(pol, eta)
         for _ in range(warmup):
             timed_sources(g, srcs, out, torch)
         step_ms, all_t = [], []
@@ -265,8 +436,14 @@ def main():
 
     heur_gteps, heur_step_ms, heur_t = run_policy(blest.Policy.HEURISTIC, args.steps, args.warmup)
     print(f"# heuristic: {heur_gteps:.1f} GTEPS, mean {np.mean(heur_t):.3f} ms/source", file=sys.stderr, flush=True)
+    tuned = None
+    if eta_tuned is not None:
+        tg, _, _ = run_policy(blest.Policy.HEURISTIC, 1, 1, eta_tuned)
+        tuned = {"eta": eta_tuned, "gteps": round(tg, 3)}
+    sw_enabled, sw_trial = switching_enable(g, inputs.sources(rp, 3, seed=1022), 10.0, torch, blest)
     learned_gteps, enabled, trial_ms = None, None, None
     value, step_ms = heur_gteps, heur_step_ms
+    learned_levels = []
     if model is not None:
         learned_gteps, learned_step_ms, _ = run_policy(blest.Policy.LEARNED, args.steps, args.warmup)
         print(f"# learned: {learned_gteps:.1f} GTEPS", file=sys.stderr, flush=True)
@@ -277,6 +454,12 @@ def main():
             value, step_ms, policy = learned_gteps, learned_step_ms, "learned"
         else:
             policy = "heuristic (learned switch disabled for this graph by its trial traversals)"
+        # levels of sampled learned traversals, for the oracle comparison in the CPU leg (not timed)
+        g.set_policy(blest.Policy.LEARNED)
+        for s in srcs[:8]:
+            g.bfs(int(s), out)
+            g.sync()
+            learned_levels.append(out.cpu().numpy().copy())
 
     # plain method (BVSS top-down every level): roofline of the persistent kernel
     td_gteps, _, td_t = run_policy(blest.Policy.BVSS, 1, 1)
@@ -314,9 +497,14 @@ def main():
     sw_ach = float(np.mean(nb2)) / (float(np.mean(heur_t[:8])) * 1e-3) / 1e9
     g.set_log_work(False)
 
-    extras = {"heuristic_gteps": round(heur_gteps, 3), "learned_gteps": None if learned_gteps is None else
-              round(learned_gteps, 3), "learned_over_heuristic": None if learned_gteps is None else
-              round(learned_gteps / heur_gteps, 4), "learned_enabled_by_trials": enabled,
+    extras = {"heuristic_gteps": round(heur_gteps, 3), "heuristic_tuned_eta": tuned,
+              "switching_enabled_by_trials": sw_enabled,
+              "switching_trial_ms_per_source": {k: round(v, 4) for k, v in sw_trial.items()},
+              "learned_gteps": None if learned_gteps is None else round(learned_gteps, 3),
+              "learned_over_heuristic": None if learned_gteps is None else round(learned_gteps / heur_gteps, 4),
+              "learned_over_heuristic_tuned_eta": None if (learned_gteps is None or tuned is None) else
+              round(learned_gteps / tuned["gteps"], 4),
+              "learned_enabled_by_trials": enabled,
               "trial_ms_per_source": None if trial_ms is None else {k: round(v, 4) for k, v in trial_ms.items()},
               "plain_method_gteps": round(td_gteps, 3),
               "ms_per_source": round(float(np.mean(heur_t)), 4), "switched_achieved_GBs": round(sw_ach, 1),
@@ -339,35 +527,45 @@ def main():
             gg.sync()
             gedges.append(traversal_edges(grp, gout.cpu().numpy()))
         gt = timed_sources(gg, gs, gout, torch)
+        ginfo = gg.info()
+        nlev = len(gg.level_stats())
         extras["grid2048_ms_per_source"] = round(float(np.mean(gt)), 3)
         extras["grid2048_gteps"] = round(harmonic_gteps(gedges, gt), 4)
-        extras["grid2048_levels"] = len(gg.level_stats())
+        extras["grid2048_levels"] = nlev
+        extras["grid2048_update_scheme"] = "eager" if ginfo["update_scheme"] == blest.Update.EAGER else "lazy"
+        extras["grid2048_u_div"] = round(ginfo["u_div"], 1)
         gg.close()
+        # the other vertex-update scheme on the same sources (Alg. 2 vs Alg. 3)
+        other = blest.Update.LAZY if ginfo["update_scheme"] == blest.Update.EAGER else blest.Update.EAGER
+        go = blest.Graph(grp, gcol, device=0, update_scheme=int(other), **{"async": 1})
+        timed_sources(go, gs[:2], gout, torch)
+        ot = timed_sources(go, gs, gout, torch)
+        tag = "lazy" if other == blest.Update.LAZY else "eager"
+        extras[f"grid2048_{tag}_ms_per_source"] = round(float(np.mean(ot)), 3)
+        extras["grid2048_us_per_level"] = {extras["grid2048_update_scheme"]: round(float(np.mean(gt)) * 1e3 / nlev, 2),
+                                           tag: round(float(np.mean(ot)) * 1e3 / len(go.level_stats()), 2)}
+        go.close()
+        del grp, gcol
         # batched multi-source BFS: scale-20 R-MAT, 960 sources, batches 64/128/256/512 in one launch
         mrp, mcol = inputs.rmat_graph(20, 1040)
         msrcs = inputs.sources(mrp, 960, seed=1041)
         mg = blest.Graph(mrp, mcol, device=0, **{"async": 1})
+        minfo = mg.info()
         mout = torch.empty((960, mg.n), dtype=torch.int16, device=dev)
         mg.msbfs_batched(msrcs, [64, 128, 256, 512], mout)
         mg.sync()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        mg.msbfs_batched(msrcs, [64, 128, 256, 512], mout)
-        e1.record()
-        mg.sync()
-        torch.cuda.synchronize()
-        ms_ms = e0.elapsed_time(e1)
+        ms_ms = timed_call(lambda: mg.msbfs_batched(msrcs, [64, 128, 256, 512], mout), torch)
         extras["msbfs_sources_per_s"] = round(960 / ms_ms * 1e3, 1)
         extras["msbfs_ms"] = round(ms_ms, 3)
+        mb = ms_algorithmic_bytes(mg.ms_level_stats(), minfo["n"], minfo["n_slice_sets"], minfo["sigma"],
+                                  minfo["slice_bytes"], 960)
+        extras["msbfs_roofline"] = {"bound": "hbm", "kernel": "k_ms_persistent (pairs rule)",
+                                    "algorithmic_bytes_lower_bound": mb, "ms": round(ms_ms, 3),
+                                    "achieved_GBs": round(mb / (ms_ms * 1e-3) / 1e9, 1),
+                                    "frac": round(mb / (ms_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         per_width = {}
         for w in (64, 128, 256, 512):  # each batch width alone over the same 960 sources
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            mg.msbfs_batched(msrcs, [w], mout)
-            e1.record()
-            mg.sync()
-            torch.cuda.synchronize()
-            per_width[str(w)] = round(960 / e0.elapsed_time(e1) * 1e3, 1)
+            per_width[str(w)] = round(960 / timed_call(lambda: mg.msbfs_batched(msrcs, [w], mout), torch) * 1e3, 1)
         extras["msbfs_sources_per_s_by_width"] = per_width
         ms_model = load_switch_model("switch_model_ms.json")
         if ms_model is not None:  # the same 960 sources with the multi-source switch network
@@ -378,19 +576,39 @@ def main():
             lms = timed_call(lambda: (mg.msbfs_batched(msrcs, [64, 128, 256, 512], mout), mg.sync()), torch)
             extras["msbfs_learned_sources_per_s"] = round(960 / lms * 1e3, 1)
             mg.set_policy(blest.Policy.HEURISTIC)
+        # the paper's multi-source ablation ladder on the same 960 sources
+        # (Section "Ablation Studies"): naive = one single-source traversal per
+        # source; (A) no getVI remap and no dynamic slice-set tracking; (AB) no
+        # tracking; (Full) = the msbfs leg above
+        sout1 = torch.empty(mg.n, dtype=torch.int32, device=dev)
+        mg.set_policy(blest.Policy.HEURISTIC)
+        naive_ms = timed_call(lambda: [mg.bfs(int(x), sout1) for x in msrcs], torch)
+        ladder = {"naive_single_source": round(960 / naive_ms * 1e3, 1)}
         mg.close()
+        for tag, flags in (("A_no_getvi_no_tracking", 3), ("AB_no_tracking", 2)):
+            ag = blest.Graph(mrp, mcol, device=0, ms_ablation=flags, **{"async": 1})
+            ag.msbfs_batched(msrcs, [64, 128, 256, 512], mout)
+            ladder[tag] = round(960 / timed_call(lambda: ag.msbfs_batched(msrcs, [64, 128, 256, 512], mout),
+                                                 torch) * 1e3, 1)
+            ag.close()
+        ladder["full"] = extras["msbfs_sources_per_s"]
+        extras["msbfs_ablation_sources_per_s"] = ladder
+        # the neighbour check on the matrix cores (int8 MFMA) instead of bitwise, same sources
+        xg = blest.Graph(mrp, mcol, device=0, ms_mfma=1, **{"async": 1})
+        xg.msbfs_batched(msrcs, [64, 128, 256, 512], mout)
+        extras["msbfs_mfma_sources_per_s"] = round(
+            960 / timed_call(lambda: xg.msbfs_batched(msrcs, [64, 128, 256, 512], mout), torch) * 1e3, 1)
+        xg.close()
+        del mout
         # the same 960 sources with the levels as a replayed hipGraph of per-phase kernels
         gmg = blest.Graph(mrp, mcol, device=0, msbfs_graph=1, **{"async": 1})
-        gmg.msbfs_batched(msrcs, [64, 128, 256, 512], mout)
+        gmout = torch.empty((960, gmg.n), dtype=torch.int16, device=dev)
+        gmg.msbfs_batched(msrcs, [64, 128, 256, 512], gmout)
         gmg.sync()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        gmg.msbfs_batched(msrcs, [64, 128, 256, 512], mout)
-        e1.record()
-        gmg.sync()
-        torch.cuda.synchronize()
-        extras["msbfs_graph_sources_per_s"] = round(960 / e0.elapsed_time(e1) * 1e3, 1)
+        extras["msbfs_graph_sources_per_s"] = round(
+            960 / timed_call(lambda: (gmg.msbfs_batched(msrcs, [64, 128, 256, 512], gmout), gmg.sync()), torch) * 1e3, 1)
         gmg.close()
+        del gmout
         # small single-source case: R-MAT scale 16, plain method and Eq. 3
         srp, scol = inputs.rmat_graph(16, 1010)
         ss = inputs.sources(srp, 64, seed=1011)
@@ -405,21 +623,32 @@ def main():
             sg.set_policy(pol)
             timed_sources(sg, ss, sout, torch)
             extras[name] = round(harmonic_gteps(sedges, timed_sources(sg, ss, sout, torch)), 3)
+        sinfo = sg.info()
+        extras["rmat16_update_scheme"] = "eager" if sinfo["update_scheme"] == blest.Update.EAGER else "lazy"
+        extras["rmat16_u_div"] = round(sinfo["u_div"], 1)
         sg.close()
+        # the plain method on the lazy scheme too (the dispatch sends graphs this small to Alg. 2)
+        sl = blest.Graph(srp, scol, device=0, update_scheme=int(blest.Update.LAZY), **{"async": 1})
+        sl.set_policy(blest.Policy.BVSS)
+        timed_sources(sl, ss, sout, torch)
+        extras["rmat16_plain_lazy_gteps"] = round(harmonic_gteps(sedges, timed_sources(sl, ss, sout, torch)), 3)
+        sl.close()
         # exact closeness: all sources of scale-18 R-MAT, 16,384 sources of scale-23 R-MAT (512 per
         # batch), with the pairs rule and with the multi-source switch network (per-graph enabled)
         ms_model = load_switch_model("switch_model_ms.json")
+        cgraphs = {}
         for tag, scale, gseed, k in (("closeness_rmat18_all", 18, 1050, None), ("closeness_rmat23_16k", 23, 1052, 16384)):
             crp, ccol = inputs.rmat_graph(scale, gseed)
             cs = np.arange(crp.size - 1, dtype=np.int32) if k is None else inputs.sources(crp, k, seed=gseed + 1)
+            cgraphs[tag] = (crp, ccol, cs)
             cg = blest.Graph(crp, ccol, device=0, msbfs_width=512, **{"async": 1})
             res = {"sources": int(cs.size)}
             pols = [("heuristic", blest.Policy.HEURISTIC)]
             if ms_model is not None:
                 cg.set_ms_switch_model(np.array(ms_model["params"], np.float32), np.array(ms_model["mean"], np.float32),
                                        np.array(ms_model["std"], np.float32), ms_model.get("min_confidence", 0.5))
-                enabled, trial = ms_learned_enable(cg, inputs.sources(crp, 512, seed=gseed + 7), torch, blest)
-                res["learned_enabled_by_trial"] = bool(enabled)
+                en, trial = ms_learned_enable(cg, inputs.sources(crp, 512, seed=gseed + 7), torch, blest)
+                res["learned_enabled_by_trial"] = bool(en)
                 res["trial_ms"] = {k2: round(v, 2) for k2, v in trial.items()}
                 pols.append(("learned", blest.Policy.LEARNED))
             for name, pol in pols:
@@ -434,7 +663,17 @@ def main():
             res["sources_per_s"] = round(cs.size / res["ms"] * 1e3, 1)
             extras[tag] = res
             cg.close()
-        cpu = cpu_baseline(rp, col, srcs)
+        # CPU oracle: the scale-22 sources, plus bounded samples of the multi-source and closeness workloads
+        c18, c23 = cgraphs["closeness_rmat18_all"], cgraphs["closeness_rmat23_16k"]
+        cpu = cpu_baseline(rp, col, srcs, edges, learned_levels,
+                           {"msbfs_rmat20": (mrp, mcol, msrcs[:64], "msbfs"),
+                            "closeness_rmat18": (c18[0], c18[1], c18[2][::512], "closeness"),
+                            "closeness_rmat23": (c23[0], c23[1], c23[2][:32], "closeness")})
+        del cgraphs, c18, c23, mrp, mcol
+        if not args.no_c3:
+            # learned vs heuristic switch at full size on held-out graphs
+            extras["c3_rmat24"] = c3_leg("rmat", 24, 1030, 1031, model, eta_tuned, torch, blest, inputs)
+            extras["c3_er24"] = c3_leg("er", 24, 1032, 1033, model, eta_tuned, torch, blest, inputs)
 
     line = {
         "metric": METRIC,

@@ -115,16 +115,53 @@ typedef struct {
                            replayed until done, instead of one persistent launch (default 0) */
   int32_t jaccard_window; /* window width W of BLEST_REORDER_JACCARD: a multiple of sigma greater
                              than sigma; 0 (default) = 1024 */
+  int32_t update_scheme;  /* BLEST_UPDATE_*: how a single-source top-down level updates the vertices
+                             it reaches (default AUTO) */
+  int32_t directed;       /* 1: the CSR lists the out-arcs of a directed graph (A[i][j] = 1 iff arc
+                             j -> i, Background); levels are distances along arcs. 0 (default): the
+                             CSR must be symmetric */
+  int32_t ms_ablation;    /* multi-source steps switched off, for the paper's ablation (Section
+                             "Ablation Studies", MS-BFS): BLEST_MS_NO_GETVI | BLEST_MS_NO_DIRTY;
+                             0 (default) = the full method. Results are unchanged */
+  int32_t ms_mfma;        /* 1: the multi-source top-down neighbour check as an int8 matrix product on
+                             the matrix cores (sigma = 8; an experiment against the bitwise check,
+                             same results). 0 (default): bitwise */
   int32_t reserved;
 } blest_opts;
+
+/* Multi-source ablation flags (Section "Ablation Studies", MS-BFS: (A) drops
+ * both, (AB) drops the tracking): NO_GETVI keeps the vertex words in vertex
+ * order instead of the getVI remap (Section "Multi-Source BFS"); NO_DIRTY
+ * drops the dynamic slice-set tracking (activeSets / dirtySets): every slice
+ * set is finalised, all its words count as active and all its VSSs are queued
+ * at every level. */
+#define BLEST_MS_NO_GETVI 1
+#define BLEST_MS_NO_DIRTY 2
+
+/* Vertex update schemes of single-source BFS. LAZY: Alg. 3 (marks in Stage 1,
+ * a Stage 2 pass builds the next frontier and queue; Section "Lazy Vertex
+ * Updates"). EAGER: Alg. 2 (each hit sets the level and the next-frontier bit
+ * at once; the first writer of a slice set enqueues its VSSs; one device-wide
+ * barrier per level). AUTO: the paper's dispatch (Section "Ablation
+ * Studies"): EAGER iff the built graph's update divergence U_div <= 25,000.
+ * EAGER levels run the BVSS top-down engine or the bottom-up engine (a push
+ * choice runs BVSS top-down); probe mode (blest_bfs_probe) always runs LAZY. */
+#define BLEST_UPDATE_LAZY 0
+#define BLEST_UPDATE_EAGER 1
+#define BLEST_UPDATE_AUTO 2
 
 /* Fills *opts with the defaults listed above. */
 void blest_default_opts(blest_opts* opts);
 
 /* Builds the BVSS of a CSR on the device (Section BVSS). The CSR is copied;
  * *out is owned by the caller until blest_free. opts may be NULL.
- * Errors: INVALID_GRAPH (not symmetric, unsorted, self loops, duplicates,
- * n <= 0, m >= 2^31), UNSUPPORTED (sigma/tau), OOM, HIP, NO_DEVICE. */
+ * Directed graphs (opts.directed = 1): the slices of a set are the out-arcs
+ * of its columns, the bottom-up engines read a transposed copy (in-arcs,
+ * Alg. 4), and RCM or JaccardWithWindows orders the underlying undirected
+ * graph. Every output (levels, multi-source levels, sums, reach, far) then
+ * follows arcs from the sources.
+ * Errors: INVALID_GRAPH (not symmetric unless directed, unsorted, self loops,
+ * duplicates, n <= 0, m >= 2^31), UNSUPPORTED (sigma/tau), OOM, HIP, NO_DEVICE. */
 blest_status blest_build(const blest_csr* csr, const blest_opts* opts, blest_graph** out);
 
 /* Releases every host and device resource of g. NULL is a no-op. */
@@ -261,7 +298,11 @@ typedef struct {
   int32_t block_size;
   int32_t device;
   int32_t panel_log2_rows; /* rows per panel of the panel-blocked copy = 2^this; 0 if not built */
-  int32_t reserved[4];
+  int32_t update_scheme;   /* BLEST_UPDATE_LAZY or BLEST_UPDATE_EAGER: the scheme traversals use */
+  int32_t directed;        /* 1 if built from a directed CSR */
+  int32_t reserved[2];
+  double u_div;            /* update divergence of the built BVSS (after reordering); see
+                              blest_update_divergence */
 } blest_graph_stats;
 
 /* Fills *out with structure sizes. Errors: INVALID_ARG. */
@@ -281,6 +322,16 @@ blest_status blest_graph_info(const blest_graph* g, blest_graph_stats* out);
  * Errors: INVALID_ARG (NULL, sigma < 1, window not a multiple of sigma or not
  * greater than it), INVALID_GRAPH, OOM. */
 blest_status blest_reorder_jaccard(const blest_csr* csr, int32_t sigma, int32_t window, int32_t* new_of_old);
+
+/* Update divergence U_div (Section "Boosting Cache Locality") of the BVSS of
+ * csr as given (no reordering) with slice-set width sigma and tau slices per
+ * VSS: each VSS is a (tau/32) x ... matrix of 32 rows and theta = tau / 32
+ * columns, slice j in column j mod theta; a column's divergence is the
+ * population standard deviation of its slices' row ids, a VSS's divergence
+ * the mean over its non-empty columns, U_div the mean over all VSSs (0 if
+ * there are none). Host only, no device needed. Errors: INVALID_ARG,
+ * INVALID_GRAPH, UNSUPPORTED (sigma/tau), OOM. */
+blest_status blest_update_divergence(const blest_csr* csr, int32_t sigma, int32_t tau, double* u_div);
 
 /* Per-level record of the last single-source BFS (Alg. 3, Stage 2 statistics). */
 typedef struct {

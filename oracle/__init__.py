@@ -14,9 +14,11 @@ Contents, each following the passage cited beside it:
   components     -- connected-component labels (reach(s) = size of s's
                     component, the reachable set of Eq. 4's sums)
   certificate    -- O(m) proof that a level array is the BFS distance
+  certificate_directed -- the same along arcs of a directed graph
   bvss           -- BVSS slices, realPtrs, virtualToReal (Section BVSS)
   get_vi         -- the multi-source index remap (Multi-Source BFS)
   switch_replay  -- Eq. 3 decisions replayed from oracle levels
+  update_divergence -- U_div of a BVSS (Section "Boosting Cache Locality")
   mlp            -- float64 MLP forward/backward/Adam (oracle/mlp.py)
   jaccard        -- JaccardWithWindows over Python sets (oracle/jaccard.py,
                     Section "Increasing Compression Ratio")
@@ -58,6 +60,8 @@ def _load():
     lib.oracle_closeness.argtypes = [i64, p32, p32, p32, i64, p64, p64, pf64, i32]
     lib.oracle_closeness.restype = i32
     lib.oracle_far.argtypes = [i64, p32, p32, p32, i64, p64, i32]
+    lib.oracle_certificate_directed.argtypes = [i64, p32, p32, i32, p32, p64]
+    lib.oracle_certificate_directed.restype = i32
     lib.oracle_far.restype = i32
     lib.oracle_certificate.argtypes = [i64, p32, p32, i32, p32, p64]
     lib.oracle_certificate.restype = i32
@@ -174,6 +178,20 @@ def certificate(rp, col, src: int, levels):
     return int(r), int(where[0])
 
 
+def certificate_directed(rp, col, src: int, levels):
+    """(code, where) for a directed graph (rp/col hold out-arcs); code 0 iff
+    levels are the hop distances from src along arcs (oracle.c documents the
+    four conditions)."""
+    rp, col, n = _csr(rp, col)
+    lev = np.ascontiguousarray(levels, dtype=np.int32)
+    where = np.zeros(1, np.int64)
+    r = _load().oracle_certificate_directed(n, _ptr(rp, ctypes.c_int32), _ptr(col, ctypes.c_int32), int(src),
+                                            _ptr(lev, ctypes.c_int32), _ptr(where, ctypes.c_int64))
+    if r < 0:
+        raise ValueError(f"oracle_certificate_directed failed ({r})")
+    return int(r), int(where[0])
+
+
 def bvss(rp, col, sigma: int = 8, tau: int = 128):
     """BVSS arrays as a dict: real_ptrs, v2r, slice_ptr, slice_row, slice_mask."""
     rp, col, n = _csr(rp, col)
@@ -197,6 +215,38 @@ def bvss(rp, col, sigma: int = 8, tau: int = 128):
         raise ValueError(f"oracle_bvss_fill failed ({r})")
     return {"real_ptrs": real_ptrs, "v2r": v2r[:nv], "slice_ptr": slice_ptr, "slice_row": rows[:nsl],
             "slice_mask": masks[:nsl], "n_slice_sets": nsets, "n_vss": nv, "n_slices": nsl}
+
+
+def update_divergence(rp, col, sigma: int = 8, tau: int = 128, theta: int | None = None) -> float:
+    """Update divergence U_div (Section "Boosting Cache Locality").
+
+    Each VSS is read as the paper's matrix of tau / theta rows and theta
+    columns (32 x 4 at tau = 128), slice j of the VSS in column j mod theta.
+    Column divergence: standard deviation (population form) of the row ids of
+    the column's slices with a nonzero mask; set divergence of a VSS: mean
+    over its non-empty columns; U_div: mean over all N_v VSSs. Computed from
+    the oracle's own BVSS, one VSS at a time."""
+    theta = max(1, tau // 32) if theta is None else theta
+    b = bvss(rp, col, sigma, tau)
+    rows = b["slice_row"].astype(np.float64)
+    masks = b["slice_mask"]
+    sp, real_ptrs, v2r = b["slice_ptr"], b["real_ptrs"], b["v2r"]
+    nv = int(b["n_vss"])
+    if nv == 0:
+        return 0.0
+    total = 0.0
+    for v in range(nv):
+        s = int(v2r[v])
+        first = int(sp[s]) + (v - int(real_ptrs[s])) * tau
+        last = min(first + tau, int(sp[s + 1]))
+        col_div = []
+        for c in range(theta):
+            idx = np.arange(first + c, last, theta)
+            idx = idx[masks[idx] != 0]
+            if idx.size:
+                col_div.append(float(np.std(rows[idx])))
+        total += float(np.mean(col_div))
+    return total / nv
 
 
 def get_vi(u, sigma: int, rho: int):

@@ -270,6 +270,40 @@ int32_t oracle_certificate(int64_t n, const int32_t *rp, const int32_t *col, int
   return 0;
 }
 
+/* Certificate for a directed graph (rp/col: out-arcs u -> col[p]): level[]
+ * is the hop distance from src along arcs iff
+ *  1: level[src] = 0 and every level is >= -1;
+ *  2: every arc u -> v with u reached has v reached;
+ *  3: ... and level[v] <= level[u] + 1;
+ *  4: every reached v != src has an in-arc from some u at level[v] - 1.
+ * 4 gives a path of length level[v] from src, 3 forbids a shorter one, and 2
+ * makes the reached set closed under arcs, so it is exactly what src reaches.
+ * The in-arc test of 4 is collected on the way over the out-arcs. */
+int32_t oracle_certificate_directed(int64_t n, const int32_t *rp, const int32_t *col, int32_t src,
+                                    const int32_t *level, int64_t *where) {
+  *where = -1;
+  if (src < 0 || src >= n) return ORACLE_ERR_ARG;
+  if (level[src] != 0) { *where = src; return 1; }
+  uint8_t *parent = (uint8_t *)calloc((size_t)n, 1);
+  if (!parent) return ORACLE_ERR_OOM;
+  int32_t r = 0;
+  for (int64_t u = 0; u < n && !r; ++u) {
+    int32_t du = level[u];
+    if (du < -1) { *where = u; r = 1; break; }
+    if (du < 0) continue;
+    for (int32_t p = rp[u]; p < rp[u + 1]; ++p) {
+      int32_t v = col[p], dv = level[v];
+      if (dv < 0) { *where = v; r = 2; break; }
+      if (dv > du + 1) { *where = v; r = 3; break; }
+      if (dv == du + 1) parent[v] = 1;
+    }
+  }
+  for (int64_t v = 0; v < n && !r; ++v)
+    if (level[v] > 0 && !parent[v]) { *where = v; r = 4; }
+  free(parent);
+  return r;
+}
+
 /* BVSS of the (symmetric) adjacency: counts first. */
 int32_t oracle_bvss_count(int64_t n, const int32_t *rp, const int32_t *col, int32_t sigma, int32_t tau,
                           int64_t *nslices, int64_t *nvss) {

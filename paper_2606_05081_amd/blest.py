@@ -44,6 +44,12 @@ class Policy(IntEnum):
     RANDOM = 5
 
 
+class Update(IntEnum):
+    LAZY = 0
+    EAGER = 1
+    AUTO = 2
+
+
 class Engine(IntEnum):
     BVSS = 0
     PUSH = 1
@@ -79,7 +85,9 @@ class Opts(ctypes.Structure):
                 ("random_seed", ctypes.c_uint64), ("device", ctypes.c_int32), ("single_block", ctypes.c_int32),
                 ("panel", ctypes.c_int32), ("panel_log2_rows", ctypes.c_int32),
                 ("stage2_count_first", ctypes.c_int32), ("msbfs_graph", ctypes.c_int32),
-                ("jaccard_window", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("jaccard_window", ctypes.c_int32), ("update_scheme", ctypes.c_int32),
+                ("directed", ctypes.c_int32), ("ms_ablation", ctypes.c_int32), ("ms_mfma", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class GraphStats(ctypes.Structure):
@@ -88,7 +96,8 @@ class GraphStats(ctypes.Structure):
                 ("n_vss", ctypes.c_int64), ("n_slices", ctypes.c_int64), ("bvss_bytes", ctypes.c_int64),
                 ("csr_bytes", ctypes.c_int64), ("work_bytes", ctypes.c_int64), ("grid_blocks", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("panel_log2_rows", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("panel_log2_rows", ctypes.c_int32), ("update_scheme", ctypes.c_int32),
+                ("directed", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2), ("u_div", ctypes.c_double)]
 
 
 class LevelStat(ctypes.Structure):
@@ -136,6 +145,7 @@ SIGNATURES = {
     "blest_graph_info": (_i32, [_vp, ctypes.POINTER(GraphStats)]),
     "blest_closeness_resumable": (_i32, [_vp, _p32, _i64, _vp, _vp, _vp, ctypes.c_char_p, _i64, _p64, _vp]),
     "blest_reorder_jaccard": (_i32, [ctypes.POINTER(CSR), _i32, _i32, _p32]),
+    "blest_update_divergence": (_i32, [ctypes.POINTER(CSR), _i32, _i32, ctypes.POINTER(ctypes.c_double)]),
     "blest_last_level_stats": (_i32, [_vp, ctypes.POINTER(LevelStat), _i32, _p32]),
     "blest_last_level_features": (_i32, [_vp, _pf32, _i32, _p32]),
     "blest_export_bvss": (_i32, [_vp, _p64, _p64, _p64, _p32, _pu64, _p32]),
@@ -215,6 +225,18 @@ def blest_closeness_resumable(h, srcs, sums, reach, cc, path: str, max_sources: 
                                            _ptr(reach), _ptr(cc), os.fsencode(path), int(max_sources),
                                            ctypes.byref(done), _stream(stream)))
     return done.value
+
+
+def blest_update_divergence(row_ptr, col, sigma: int = 8, tau: int = 128) -> float:
+    """Update divergence U_div of the CSR's BVSS as given (host only)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    if cl.size == 0:
+        cl = np.zeros(1, dtype=np.int32)
+    csr = CSR(rp.size - 1, int(rp[-1]) if rp.size else 0, rp.ctypes.data_as(_p32), cl.ctypes.data_as(_p32))
+    out = ctypes.c_double()
+    _check(lib().blest_update_divergence(ctypes.byref(csr), int(sigma), int(tau), ctypes.byref(out)))
+    return float(out.value)
 
 
 def blest_reorder_jaccard(row_ptr, col, sigma: int = 8, window: int = 1024) -> np.ndarray:
@@ -352,8 +374,15 @@ class Graph:
     interpreter finalises; a graph collected during finalisation is not freed
     (the process is ending and the HIP runtime may already be torn down)."""
 
-    def __init__(self, row_ptr, col, **opts):
+    def __init__(self, row_ptr, col, autotune: bool = False, family: str | None = None, **opts):
+        """autotune=True: options the autotuner cached for the closest graph of
+        this family (autotune.graph_options) fill in every option not given."""
         self._h = None
+        self.autotuned = None
+        if autotune:
+            from . import autotune as _at
+            tuned, self.autotuned = _at.graph_options(row_ptr, col, family)
+            opts = {**tuned, **opts}
         self.opts = default_opts(**opts)
         self._h = blest_build(row_ptr, col, self.opts)
         _live_graphs.add(self)

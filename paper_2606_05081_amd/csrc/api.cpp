@@ -181,6 +181,7 @@ void blest_default_opts(blest_opts* o) {
   o->single_block = 1;
   o->panel = 1;
   o->stage2_count_first = 1;
+  o->update_scheme = BLEST_UPDATE_AUTO;
 }
 
 blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_graph** out) {
@@ -207,11 +208,20 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   if (o.msbfs_graph < 0 || o.msbfs_graph > 1) return fail(BLEST_ERR_INVALID_ARG, "msbfs_graph must be 0 or 1");
   if (o.stage2_count_first < 0 || o.stage2_count_first > 2)
     return fail(BLEST_ERR_INVALID_ARG, "stage2_count_first must be 0, 1 or 2");
+  if (o.directed < 0 || o.directed > 1) return fail(BLEST_ERR_INVALID_ARG, "directed must be 0 or 1");
+  if (o.ms_mfma < 0 || o.ms_mfma > 1) return fail(BLEST_ERR_INVALID_ARG, "ms_mfma must be 0 or 1");
+  if ((o.ms_mfma || o.ms_ablation) && o.sigma != 8)
+    return fail(BLEST_ERR_UNSUPPORTED, "ms_mfma and ms_ablation need sigma = 8");
+  if (o.ms_ablation < 0 || o.ms_ablation > (BLEST_MS_NO_GETVI | BLEST_MS_NO_DIRTY))
+    return fail(BLEST_ERR_INVALID_ARG, "ms_ablation must combine BLEST_MS_NO_GETVI and BLEST_MS_NO_DIRTY");
+  if (o.update_scheme < BLEST_UPDATE_LAZY || o.update_scheme > BLEST_UPDATE_AUTO)
+    return fail(BLEST_ERR_INVALID_ARG, "update_scheme must be 0 (lazy), 1 (eager) or 2 (auto)");
   if (o.panel_log2_rows != 0 && (o.panel_log2_rows < 5 || o.panel_log2_rows > 15))
     return fail(BLEST_ERR_UNSUPPORTED, "panel_log2_rows must be 0 (auto) or in [5, 15]");
   const int64_t n = csr->n, m = csr->m;
   std::string why;
-  if (!blest::validate_csr(n, m, csr->row_ptr, csr->col_idx, &why)) return fail(BLEST_ERR_INVALID_GRAPH, why);
+  if (!blest::validate_csr(n, m, csr->row_ptr, csr->col_idx, &why, o.directed == 0))
+    return fail(BLEST_ERR_INVALID_GRAPH, why);
   int dev = 0, num_cu = 0;
   double tick_us = 0.01;
   blest_status s = check_device(o.device, &dev, &num_cu, &tick_us);
@@ -222,19 +232,31 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   g->opts = o;
   const int32_t* rp = csr->row_ptr;
   const int32_t* col = csr->col_idx;
-  std::vector<int32_t> rp2, col2, orig;
+  std::vector<int32_t> rp2, col2, orig, rps, cols;
+  // The orderings work on the undirected graph underlying a directed one.
+  const bool want_order = o.reorder != BLEST_REORDER_NONE && n > 1;
+  if (o.directed && want_order) {
+    try {
+      blest::symmetrize_csr(n, rp, col, rps, cols);
+    } catch (...) {
+      delete g;
+      return fail(BLEST_ERR_OOM, "host allocation during reordering");
+    }
+  }
+  const int32_t* ord_rp = o.directed && want_order ? rps.data() : rp;
+  const int32_t* ord_col = o.directed && want_order ? cols.data() : col;
   // AUTO follows the section "Reordering the Graph": JaccardWithWindows for
   // scale-free-like degree distributions, RCM for the others.
-  const bool scale_free = o.reorder == BLEST_REORDER_AUTO && blest::is_scale_free_like(n, rp);
+  const bool scale_free = o.reorder == BLEST_REORDER_AUTO && blest::is_scale_free_like(n, ord_rp);
   const bool rcm = o.reorder == BLEST_REORDER_RCM || (o.reorder == BLEST_REORDER_AUTO && !scale_free);
   const bool jac = o.reorder == BLEST_REORDER_JACCARD || scale_free;
   if ((rcm || jac) && n > 1) {
     try {
       if (rcm) {
-        orig = blest::rcm_order(n, rp, col);
+        orig = blest::rcm_order(n, ord_rp, ord_col);
       } else {
         const std::vector<int32_t> nof =
-            blest::jaccard_order(n, rp, col, o.sigma, o.jaccard_window ? o.jaccard_window : 1024);
+            blest::jaccard_order(n, ord_rp, ord_col, o.sigma, o.jaccard_window ? o.jaccard_window : 1024);
         orig.assign(static_cast<size_t>(n), 0);
         for (int64_t i = 0; i < n; ++i) orig[nof[i]] = static_cast<int32_t>(i);
       }
@@ -246,6 +268,20 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
     rp = rp2.data();
     col = col2.data();
     g->reordered = rcm ? 1 : 3;
+  }
+  rps.clear();
+  rps.shrink_to_fit();
+  cols.clear();
+  cols.shrink_to_fit();
+  // in-arcs of a directed graph, for the bottom-up engines (Alg. 4 reads the CSR of the transpose)
+  std::vector<int32_t> rpt, colt;
+  if (o.directed) {
+    try {
+      blest::transpose_csr(n, rp, col, rpt, colt);
+    } catch (...) {
+      delete g;
+      return fail(BLEST_ERR_OOM, "host allocation during the transpose");
+    }
   }
   const bool wide = o.sigma != 8 || o.wide_slices || n > (int64_t(1) << 24);
   blest::Bvss b;
@@ -273,8 +309,13 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   d.single_block = o.single_block;
   d.count_first = o.stage2_count_first;
   d.tick_us = tick_us;
+  // the paper's dispatch between Alg. 2 and Alg. 3 (Section "Ablation Studies")
+  d.u_div = blest::update_divergence(b, o.tau);
+  d.eager = o.update_scheme == BLEST_UPDATE_EAGER ||
+            (o.update_scheme == BLEST_UPDATE_AUTO && d.u_div <= blest::kEagerMaxUdiv);
   {
     hipError_t ge = blest::bfs_grid_size(d, 1, o.blocks_per_cu, &d.grid);
+    if (ge == hipSuccess) ge = blest::bfs_grid_size_eager(d, o.blocks_per_cu, &d.grid_eager);
     if (ge != hipSuccess) {
       delete g;
       return hip_fail(ge, "bfs_grid_size");
@@ -320,6 +361,28 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   TRY(dalloc_t(g, &d.rp, rp_len + 32));
   // col is padded by 4 entries: the bottom-up engine reads 4 neighbours at a time
   TRY(dalloc_t(g, &d.col, static_cast<size_t>(m) + 4));
+  d.directed = o.directed;
+  d.ms_ablation = o.ms_ablation;
+  d.ms_mfma = o.ms_mfma;
+  if (o.directed) {
+    int32_t* rpi = nullptr;
+    int32_t* coli = nullptr;
+    void* dmi = nullptr;
+    TRY(dalloc_t(g, &rpi, rp_len + 32));
+    TRY(dalloc_t(g, &coli, static_cast<size_t>(m) + 4));
+    TRY(dalloc(g, &dmi, ns * mb));
+    std::vector<int32_t> rpp(rp_len + 4, static_cast<int32_t>(m));
+    std::copy(rpt.begin(), rpt.end(), rpp.begin());
+    TRY(hipMemcpy(rpi, rpp.data(), sizeof(int32_t) * rpp.size(), hipMemcpyHostToDevice));
+    if (m > 0) TRY(hipMemcpy(coli, colt.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice));
+    std::vector<uint8_t> dm(ns * mb, 0);
+    for (int64_t u = 0; u < n; ++u)
+      if (rpt[u + 1] > rpt[u]) dm[(u / o.sigma) * mb + (u % o.sigma) / 8] |= static_cast<uint8_t>(1u << (u % 8));
+    TRY(hipMemcpy(dmi, dm.data(), dm.size(), hipMemcpyHostToDevice));
+    d.rp_in = rpi;
+    d.col_in = coli;
+    d.degmask_in = dmi;
+  }
   TRY(dalloc_t(g, &d.slice_ptr, ns + 8));
   TRY(dalloc(g, &d.slices, static_cast<size_t>(std::max<int64_t>(b.nslices, 1)) * (wide ? 8 : 4)));
   TRY(dalloc(g, &d.degmask, ns * mb));
@@ -330,13 +393,14 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   // words starting at its first set (rounded down to 8).
   const size_t state_bytes = std::max(ns * mb, prow / 8) + 512;
   const size_t mark_bytes = std::max(ns * static_cast<size_t>(o.sigma), prow);
-  // the frontier is double-buffered by level parity: level l reads buffer
-  // l & 1 while Stage 2 (or the fused panel step) writes the other
+  // the frontier is double-buffered by level parity in the lazy scheme: level
+  // l reads buffer l & 1 while Stage 2 (or the fused panel step) writes the
+  // other; the eager scheme rotates three buffers (level mod 3)
   const size_t fstride = (state_bytes + 255) / 256 * 256;
   TRY(dalloc(g, &d.vis, state_bytes));
-  TRY(dalloc(g, &d.front, 2 * fstride));
+  TRY(dalloc(g, &d.front, 3 * fstride));
   TRY(hipMemset(d.vis, 0, state_bytes));
-  TRY(hipMemset(d.front, 0, 2 * fstride));
+  TRY(hipMemset(d.front, 0, 3 * fstride));
   d.fstride = fstride;
   TRY(dalloc_t(g, &d.mark, mark_bytes));
   d.mark_bytes = mark_bytes;
@@ -348,6 +412,7 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
     TRY(hipMemcpy(d.pbase, pn.base.data(), 4 * pn.base.size(), hipMemcpyHostToDevice));
     TRY(hipMemcpy(d.pptr, pn.ptr.data(), 4 * pn.ptr.size(), hipMemcpyHostToDevice));
   }
+  TRY(dalloc_t(g, &d.queue[2], static_cast<size_t>(std::max<int64_t>(b.nvss, 1))));
   for (int i = 0; i < 2; ++i) {
     TRY(dalloc_t(g, &d.queue[i], static_cast<size_t>(std::max<int64_t>(b.nvss, 1))));
     TRY(dalloc_t(g, &d.flight[i], static_cast<size_t>(n)));
@@ -390,6 +455,11 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
     if (g_model_set) TRY(hipMemcpy(d.mlp, &g_model, sizeof(g_model), hipMemcpyHostToDevice));
     if (g_ms_model_set) TRY(hipMemcpy(d.ms_mlp, &g_ms_model, sizeof(g_ms_model), hipMemcpyHostToDevice));
   }
+  if (!o.directed) {
+    d.rp_in = d.rp;
+    d.col_in = d.col;
+    d.degmask_in = d.degmask;
+  }
   TRY(hipDeviceSynchronize());
 #undef TRY
   g->real_ptrs = std::move(b.real_ptrs);
@@ -397,7 +467,7 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   g->csr_bytes = 4 * (n + 1) + 4 * m;
   g->bvss_bytes = 4 * static_cast<int64_t>(ns + 1) + (wide ? 8 : 4) * b.nslices +
                   4 * static_cast<int64_t>(pn.words.size() + pn.base.size() + pn.ptr.size());
-  g->work_bytes = static_cast<int64_t>(ns * mb * 3 + ns * o.sigma) + 2 * 16 * std::max<int64_t>(b.nvss, 1) +
+  g->work_bytes = static_cast<int64_t>(ns * mb * 4 + ns * o.sigma) + 3 * 16 * std::max<int64_t>(b.nvss, 1) +
                   2 * 4 * n + 2 * 8 * d.nheavy_cap;
   g->ms.device = dev;
   *out = g;
@@ -455,6 +525,27 @@ blest_status blest_graph_info(const blest_graph* g, blest_graph_stats* out) {
   out->block_size = g->d.block;
   out->device = g->d.device;
   out->panel_log2_rows = g->d.npanels > 0 ? g->d.panel_rb : 0;
+  out->update_scheme = g->d.eager ? BLEST_UPDATE_EAGER : BLEST_UPDATE_LAZY;
+  out->directed = g->d.directed;
+  out->u_div = g->d.u_div;
+  return BLEST_OK;
+}
+
+blest_status blest_update_divergence(const blest_csr* csr, int32_t sigma, int32_t tau, double* u_div) {
+  if (!csr || !u_div) return fail(BLEST_ERR_INVALID_ARG, "NULL argument");
+  if (sigma != 8 && sigma != 16 && sigma != 32) return fail(BLEST_ERR_UNSUPPORTED, "sigma must be 8, 16 or 32");
+  if (tau != 64 && tau != 128 && tau != 192 && tau != 256)
+    return fail(BLEST_ERR_UNSUPPORTED, "tau must be 64, 128, 192 or 256");
+  std::string why;
+  if (!blest::validate_csr(csr->n, csr->m, csr->row_ptr, csr->col_idx, &why))
+    return fail(BLEST_ERR_INVALID_GRAPH, why);
+  try {
+    blest::Bvss b;
+    blest::build_bvss(csr->n, csr->row_ptr, csr->col_idx, sigma, tau, true, &b);
+    *u_div = blest::update_divergence(b, tau);
+  } catch (...) {
+    return fail(BLEST_ERR_OOM, "host allocation during the BVSS build");
+  }
   return BLEST_OK;
 }
 

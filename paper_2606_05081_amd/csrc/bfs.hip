@@ -137,8 +137,9 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
 }
 
 // Uniform engine choice for the step out of `level`. Contains __syncthreads().
-__device__ int choose_engine(const BfsArgs& a, const LevelView& v, const float (&feat)[kMaxSwitchFeatures],
-                             int level, const float* s_mlp, int* fallback) {
+__device__ __forceinline__ int choose_engine_inl(const BfsArgs& a, const LevelView& v,
+                                                 const float (&feat)[kMaxSwitchFeatures], int level,
+                                                 const float* s_mlp, int* fallback) {
   __shared__ int s_choice;
   const long long unvisited = a.n - v.cumv;
   *fallback = 0;
@@ -167,6 +168,13 @@ __device__ int choose_engine(const BfsArgs& a, const LevelView& v, const float (
     default:
       return heuristic_engine(unvisited, v.queue, a.eta);
   }
+}
+
+// The same as an out-of-line call (the lazy kernel, where inlining it would
+// only add to the register pressure).
+__device__ int choose_engine(const BfsArgs& a, const LevelView& v, const float (&feat)[kMaxSwitchFeatures],
+                             int level, const float* s_mlp, int* fallback) {
+  return choose_engine_inl(a, v, feat, level, s_mlp, fallback);
 }
 
 // ------------------------------------------------------------ Stage 1
@@ -605,9 +613,9 @@ __device__ __attribute__((noinline)) long long engine_pull(const BfsArgs& a, int
   using M = typename MaskOf<SIGMA>::T;
   gptr<const M> __restrict__ vis = to_global(static_cast<const M*>(a.vis));
   gptr<const M> __restrict__ front = to_global(static_cast<const M*>(front_buf(a, sel)));
-  gptr<const M> __restrict__ degm = to_global(static_cast<const M*>(a.degmask));
-  gptr<const int32_t> __restrict__ rp = to_global(a.rp);
-  gptr<const int32_t> __restrict__ col = to_global(a.col);
+  gptr<const M> __restrict__ degm = to_global(static_cast<const M*>(a.degmask_in));
+  gptr<const int32_t> __restrict__ rp = to_global(a.rp_in);
+  gptr<const int32_t> __restrict__ col = to_global(a.col_in);
   gptr<uint8_t> __restrict__ mark = to_global(a.mark);
   const long long nv = a.nsets * SIGMA;
   const int lane = lane_id();
@@ -1134,7 +1142,7 @@ template <int SIGMA>
 // seeded: the threads that clear the source's visited/frontier word and
 // level write the source's values instead (level 0), so no barrier is needed
 // between the clear and those writes.
-__device__ void clear_state(const BfsArgs& a, long long gtid, long long nthreads, bool seeded = false) {
+__device__ __forceinline__ void clear_state(const BfsArgs& a, long long gtid, long long nthreads, bool seeded = false) {
   using M = typename MaskOf<SIGMA>::T;
   M* vis = static_cast<M*>(a.vis);
   M* front0 = static_cast<M*>(front_buf(a, 0));
@@ -1156,7 +1164,7 @@ __device__ void clear_state(const BfsArgs& a, long long gtid, long long nthreads
 // Level 0: frontier = {src}, queue = the VSSs of src's slice set. One block.
 template <int SIGMA>
 // lists_only: clear_state(seeded) already wrote the visited/frontier bit and level.
-__device__ void seed_source(const BfsArgs& a, bool lists_only = false) {
+__device__ __forceinline__ void seed_source(const BfsArgs& a, bool lists_only = false) {
   using M = typename MaskOf<SIGMA>::T;
   const long long src = a.src;
   const long long s = src / SIGMA;
@@ -1250,6 +1258,9 @@ __device__ int single_episode(const BfsArgs& a, int level, int engine, int fallb
     }
     const long long prev = v.frontier;
     ++level;
+    // progress for the waiting workgroups: their time bound restarts with every level
+    if (threadIdx.x == 0)
+      __hip_atomic_store(&a.ctl->single_progress[0], level, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     v = read_level_atomic(a.ctl, level % kStatSlots);
     if (v.frontier == 0) return level;
     if (__hip_atomic_load(&a.ctl->error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return level;
@@ -1314,13 +1325,21 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
           s_level = next;
         }
       } else if (threadIdx.x == 0) {
-        // wait for workgroup 0 to finish the episode (bounded like a barrier)
-        const unsigned long long t0 = dev_ticks();
+        // wait for workgroup 0 to finish the episode, bounded like a barrier;
+        // the bound restarts whenever the episode finishes a level, so it
+        // measures a stall, not the length of a long run of small levels
+        unsigned long long t0 = dev_ticks();
+        int seen = -1;
         bool ok = true;
         while (__hip_atomic_load(&a.ctl->single_gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < episodes) {
           if (__hip_atomic_load(&a.ctl->error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
             ok = false;
             break;
+          }
+          const int prog = __hip_atomic_load(&a.ctl->single_progress[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (prog != seen) {
+            seen = prog;
+            t0 = dev_ticks();
           }
           if (dev_ticks() - t0 > a.timeout_ticks) {
             __hip_atomic_store(&a.ctl->error[0], static_cast<int>(BLEST_ERR_TIMEOUT), __ATOMIC_RELAXED,
@@ -1443,6 +1462,452 @@ __global__ void __launch_bounds__(BLOCK) k_bfs_persistent(BfsArgs a) {
   }
 }
 
+// ------------------------------------------- eager vertex updates (Alg. 2)
+//
+// Alg. 2 (Section "Compute Mechanics") updates a vertex as soon as a slice
+// hits it: the level is written, the vertex's bit is ORed into the next
+// frontier word by an atomic whose returned value identifies the first
+// writer of each slice set, and that writer enqueues the set's VSSs. There is
+// no Stage 2 sweep and one device-wide barrier per level, which suits graphs
+// whose rows inside a VSS are clustered (update divergence at most 25,000,
+// Section "Ablation Studies"): there the scattered updates that the lazy
+// scheme defers are cheap, and its per-level Stage 2 pass is what dominates
+// thousands of small levels.
+//
+// Buffers rotate over three levels. Level l reads the frontier words F_l and
+// the queue Q_l (buffers l mod 3), builds F_{l+1} and Q_{l+1} (buffers
+// (l + 1) mod 3, all-zero words when the level starts), ORs F_l into the
+// visited words walking Q_l, and zeroes the words of F_{l-1} walking Q_{l-1},
+// which makes that buffer clean for level l + 1. Visited words therefore hold
+// every vertex of levels < l and possibly some of level l, so a vertex was
+// reached before level l + 1 iff its bit is set in visited | F_l, whichever
+// of the two copies a wave reads. The statistics of level l + 1 (the inputs
+// of Eq. 3 and of the switch network) are summed by device atomics into the
+// rotating counter slot (l + 1) mod 3, which level l - 1 zeroed.
+
+__device__ __forceinline__ void* eager_front(const BfsArgs& a, int b) {
+  return static_cast<char*>(a.front) + static_cast<long long>(b) * a.fstride;
+}
+
+// Atomic OR of a sigma-bit word (8- and 16-bit words through the aligned
+// 32-bit word that holds them); returns the word's previous value.
+template <int SIGMA>
+__device__ __forceinline__ typename MaskOf<SIGMA>::T atomic_or_word(typename MaskOf<SIGMA>::T* p,
+                                                                    typename MaskOf<SIGMA>::T bits) {
+  using M = typename MaskOf<SIGMA>::T;
+  if constexpr (SIGMA == 32) {
+    return __hip_atomic_fetch_or(p, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(p);
+    uint32_t* w = reinterpret_cast<uint32_t*>(addr & ~uintptr_t(3));
+    const uint32_t sh = static_cast<uint32_t>(addr & 3u) * 8u;
+    const uint32_t old =
+        __hip_atomic_fetch_or(w, static_cast<uint32_t>(bits) << sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return static_cast<M>(old >> sh);
+  }
+}
+
+// Per-lane counts of a level's new vertices, summed per wave at the end.
+struct EagerStats {
+  long long frontier = 0, qslices = 0, fedges = 0, deg32 = 0, deg1024 = 0, work = 0;
+};
+
+__device__ __forceinline__ void eager_new_vertex(const BfsArgs& a, uint32_t u, int32_t deg, int new_level,
+                                                 EagerStats& st) {
+  a.levels[a.orig_id ? a.orig_id[u] : static_cast<int32_t>(u)] = new_level;
+  st.frontier += 1;
+  st.fedges += deg;
+  st.deg32 += deg >= 32;
+  st.deg1024 += deg >= 1024;
+}
+
+// Appends every VSS of slice set s to q; qcur is the F_QUEUE counter of the
+// next level's slot, which doubles as q's append cursor.
+__device__ __forceinline__ void eager_enqueue(const BfsArgs& a, uint32_t s, uint4* q, unsigned long long* qcur,
+                                              EagerStats& st) {
+  const uint32_t s0 = a.slice_ptr[s], ns = a.slice_ptr[s + 1] - s0;
+  const uint32_t tau = static_cast<uint32_t>(a.tau);
+  const uint32_t nv = (ns + tau - 1) / tau;
+  if (nv == 0) return;
+  const unsigned long long off = fetch_add_u64(qcur, nv);
+  for (uint32_t k = 0; k < nv; ++k) q[off + k] = make_uint4(s0 + k * tau, min(tau, ns - k * tau), 0u, s);
+  st.qslices += ns;
+}
+
+// Top-down step of Alg. 2: a wave takes G queued VSSs at a time, reads their
+// sets' frontier words from F_l and all their slices, then handles the hits.
+template <int SIGMA, class SliceT, int K>
+__device__ void eager_td_k(const BfsArgs& a, int level, long long qlen, long long gwave, long long nwaves,
+                           EagerStats& st) {
+  using M = typename MaskOf<SIGMA>::T;
+  constexpr int G = 4;
+  const int cb = level % 3, nb = (level + 1) % 3;
+  const gptr<const uint4> qg = to_global(static_cast<const uint4*>(a.queue[cb]));
+  uint4* qn = a.queue[nb];
+  unsigned long long* qcur = &a.ctl->acc[(level + 1) % kStatSlots][F_QUEUE][0];
+  gptr<const SliceT> __restrict__ sl = to_global(static_cast<const SliceT*>(a.slices));
+  gptr<const M> vis = to_global(static_cast<const M*>(a.vis));
+  gptr<const M> fc = to_global(static_cast<const M*>(eager_front(a, cb)));
+  M* fn = static_cast<M*>(eager_front(a, nb));
+  gptr<const int32_t> rp = to_global(a.rp);
+  const uint32_t lane = static_cast<uint32_t>(lane_id());
+  for (long long base = gwave * G; base < qlen; base += nwaves * G) {
+    uint4 dl = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t al_l = 0;
+    if (lane < G && base + lane < qlen) {
+      dl = qg[base + lane];
+      al_l = static_cast<uint32_t>(fc[dl.w]);
+    }
+    uint32_t s0[G], cn[G];
+    SliceT al[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      s0[g] = __builtin_amdgcn_readlane(dl.x, g);
+      cn[g] = __builtin_amdgcn_readlane(dl.y, g);
+      al[g] = static_cast<SliceT>(static_cast<uint32_t>(__builtin_amdgcn_readlane(al_l, g)));
+    }
+    SliceT w[G][K];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const uint32_t j = lane + 64u * k;
+        st.work += j < cn[g];
+        w[g][k] = (j < cn[g]) ? sl[s0[g] + j] : SliceT(0);
+      }
+    // visited | F_l of every hit row, all loads issued before any test
+    M seen[G][K];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const uint32_t row = static_cast<uint32_t>(w[g][k] >> SliceFmt<SliceT>::kRowShift);
+        seen[g][k] = (w[g][k] & al[g]) ? static_cast<M>(vis[row / SIGMA] | fc[row / SIGMA]) : M(~M(0));
+      }
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const uint32_t row = static_cast<uint32_t>(w[g][k] >> SliceFmt<SliceT>::kRowShift);
+        const M bit = static_cast<M>(M(1) << (row % SIGMA));
+        if (!(seen[g][k] & bit)) {
+          const M old = atomic_or_word<SIGMA>(fn + row / SIGMA, bit);
+          if (!(old & bit)) {
+            eager_new_vertex(a, row, rp[row + 1] - rp[row], level + 1, st);
+            if (old == 0) eager_enqueue(a, row / SIGMA, qn, qcur, st);
+          }
+        }
+      }
+  }
+}
+
+template <int SIGMA, class SliceT>
+__device__ __forceinline__ void eager_td(const BfsArgs& a, int level, long long qlen, long long gwave,
+                                                   long long nwaves, EagerStats& st) {
+  switch (a.tau) {
+    case 64:
+      return eager_td_k<SIGMA, SliceT, 1>(a, level, qlen, gwave, nwaves, st);
+    case 128:
+      return eager_td_k<SIGMA, SliceT, 2>(a, level, qlen, gwave, nwaves, st);
+    case 192:
+      return eager_td_k<SIGMA, SliceT, 3>(a, level, qlen, gwave, nwaves, st);
+    default:
+      return eager_td_k<SIGMA, SliceT, 4>(a, level, qlen, gwave, nwaves, st);
+  }
+}
+
+// Bottom-up step (Alg. 4) with eager updates: a lane owns a vertex, an
+// unvisited vertex scans its row (the whole wave scans rows longer than
+// kPullLight) for a neighbour in F_l. The wave owns all sigma vertices of each
+// of its sets, so it writes their F_{l+1} words with plain stores and
+// enqueues the sets that gained vertices.
+template <int SIGMA>
+__device__ __forceinline__ void eager_bu(const BfsArgs& a, int level, long long gwave, long long nwaves,
+                                                   EagerStats& st) {
+  using M = typename MaskOf<SIGMA>::T;
+  const int cb = level % 3, nb = (level + 1) % 3;
+  gptr<const M> vis = to_global(static_cast<const M*>(a.vis));
+  gptr<const M> fc = to_global(static_cast<const M*>(eager_front(a, cb)));
+  gptr<const M> degm = to_global(static_cast<const M*>(a.degmask_in));
+  M* fn = static_cast<M*>(eager_front(a, nb));
+  uint4* qn = a.queue[nb];
+  unsigned long long* qcur = &a.ctl->acc[(level + 1) % kStatSlots][F_QUEUE][0];
+  gptr<const int32_t> rp = to_global(a.rp_in);
+  gptr<const int32_t> col = to_global(a.col_in);
+  gptr<const int32_t> rp_out = to_global(a.rp);
+  const long long nv = a.nsets * SIGMA;
+  const int lane = lane_id();
+  const long long nchunks = (nv + 63) / 64;
+  // 64-vertex chunks, round k rotated by k (as in the lazy bottom-up engine)
+  for (long long k = 0; k * nwaves < nchunks; ++k) {
+    const long long chunk = k * nwaves + (gwave + k) % nwaves;
+    if (chunk >= nchunks) continue;
+    const long long u = chunk * 64 + lane;
+    bool cand = false;
+    int p = 0, e = 0;
+    if (u < nv) {
+      const long long s = u / SIGMA;
+      const M unv = static_cast<M>(~(vis[s] | fc[s]) & degm[s]);
+      cand = (unv >> (u % SIGMA)) & 1u;
+    }
+    if (!__ballot(cand)) continue;
+    if (cand) {
+      p = rp[u];
+      e = rp[u + 1];
+    }
+    const bool heavy = cand && e - p > kPullLight;
+    bool found = false;
+    if (cand && !heavy) {
+      for (int q = p; q < e && !found; ++q) {
+        const int v = col[q];
+        found = (fc[v / SIGMA] >> (v % SIGMA)) & 1u;
+        ++st.work;
+      }
+    }
+    unsigned long long hb = __ballot(heavy);
+    while (hb) {
+      const int l = __builtin_ctzll(hb);
+      hb &= hb - 1;
+      const int hp = __builtin_amdgcn_readlane(p, l), he = __builtin_amdgcn_readlane(e, l);
+      for (int q = hp; q < he; q += 64) {
+        const int i = q + lane;
+        bool f = false;
+        if (i < he) {
+          const int v = col[i];
+          f = (fc[v / SIGMA] >> (v % SIGMA)) & 1u;
+          ++st.work;
+        }
+        if (__ballot(f)) {
+          if (lane == l) found = true;
+          break;
+        }
+      }
+    }
+    const unsigned long long got = __ballot(found);
+    if (!got) continue;
+    // the statistics count out-arcs (the frontier's edges for the next step)
+    if (found) eager_new_vertex(a, static_cast<uint32_t>(u), rp_out[u + 1] - rp_out[u], level + 1, st);
+    if (lane % SIGMA == 0) {
+      const M bits = static_cast<M>(got >> lane);
+      if (bits) {
+        fn[u / SIGMA] = bits;
+        eager_enqueue(a, static_cast<uint32_t>(u / SIGMA), qn, qcur, st);
+      }
+    }
+  }
+}
+
+// Adds the wave's counts to the next level's slot (one atomic per wave and field).
+__device__ __forceinline__ void eager_flush(const BfsArgs& a, const EagerStats& st, int nslot, int slot) {
+  long long v[6] = {st.frontier, st.qslices, st.fedges, st.deg32, st.deg1024, st.work};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+  if (lane_id() == 0) {
+    constexpr int f[5] = {F_FRONTIER, F_QSLICES, F_FEDGES, F_DEG32, F_DEG1024};
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+      if (v[k]) add_u64(&a.ctl->acc[nslot][f[k]][0], static_cast<unsigned long long>(v[k]));
+    if (v[5] && (a.count_work || a.probe)) add_u64(&a.ctl->acc[slot][F_WORK][0], static_cast<unsigned long long>(v[5]));
+  }
+}
+
+// Levels whose queue holds at most this many slices run on workgroup 0 alone
+// (workgroup barriers instead of device-wide ones), consecutively, while the
+// other workgroups wait; a bottom-up level never does.
+constexpr long long kEagerSingleSlices = 4096;
+
+// One level of the eager scheme by the calling workgroups (the whole grid,
+// or workgroup 0 alone): bookkeeping, the engine and its counters. The caller
+// synchronises afterwards (device-wide or workgroup barrier).
+template <int SIGMA, class SliceT, int BLOCK>
+__device__ __forceinline__ void eager_level(const BfsArgs& a, int level, const LevelView& v, long long prev_queue,
+                                            int engine, int fallback, const float (&feat)[kMaxSwitchFeatures],
+                                            long long gtid, long long nthreads, long long gwave, long long nwaves) {
+  using M = typename MaskOf<SIGMA>::T;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      log_level(a, level, v, engine, fallback, feat);
+      if (level < a.log_cap) a.log[level].panel = 0;
+    }
+    // the slot level + 2 accumulates into during the next level
+    const int zslot = (level + 2) % kStatSlots;
+    for (int t = threadIdx.x; t < kStatFields; t += BLOCK)
+      __hip_atomic_store(&a.ctl->acc[zslot][t][0], 0ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  EagerStats st;
+  if (engine == BLEST_ENGINE_BOTTOM_UP)
+    eager_bu<SIGMA>(a, level, gwave, nwaves, st);
+  else
+    eager_td<SIGMA, SliceT>(a, level, v.queue, gwave, nwaves, st);
+  {
+    // F_l into the visited words (walking Q_l); F_{l-1} cleared (walking Q_{l-1})
+    const gptr<const uint4> qc = to_global(static_cast<const uint4*>(a.queue[level % 3]));
+    const gptr<const uint4> qp = to_global(static_cast<const uint4*>(a.queue[(level + 2) % 3]));
+    gptr<M> vis = to_global(static_cast<M*>(a.vis));
+    const gptr<const M> fc = to_global(static_cast<const M*>(eager_front(a, level % 3)));
+    gptr<M> fp = to_global(static_cast<M*>(eager_front(a, (level + 2) % 3)));
+    for (long long i = gtid; i < v.queue; i += nthreads) {
+      const uint32_t s = qc[i].w;
+      vis[s] = static_cast<M>(vis[s] | fc[s]);
+    }
+    for (long long i = gtid; i < prev_queue; i += nthreads) fp[qp[i].w] = 0;
+  }
+  eager_flush(a, st, (level + 1) % kStatSlots, level % kStatSlots);
+}
+
+template <int SIGMA, class SliceT, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_bfs_eager(BfsArgs a) {
+  extern __shared__ float s_mlp[];
+  __shared__ int s_level;
+  using M = typename MaskOf<SIGMA>::T;
+  const unsigned nblocks = gridDim.x;
+  const long long nthreads = static_cast<long long>(nblocks) * BLOCK;
+  const long long gtid = static_cast<long long>(blockIdx.x) * BLOCK + threadIdx.x;
+  const long long gwave = static_cast<long long>(blockIdx.x) * (BLOCK / 64) + wave_in_block();
+  const long long nwaves = static_cast<long long>(nblocks) * (BLOCK / 64);
+  const bool learned = a.policy == BLEST_POLICY_LEARNED && a.mlp != nullptr && a.mlp->valid;
+  if (learned) mlp_to_lds(a.mlp, s_mlp);
+  // levels, visited words and F_0, F_1 as in the lazy scheme, plus F_2; the
+  // registration barrier publishes them with the level-0 counters and queue
+  clear_state<SIGMA>(a, gtid, nthreads, true);
+  {
+    M* f2 = static_cast<M*>(eager_front(a, 2));
+    for (long long s = gtid; s < a.nsets; s += nthreads) f2[s] = 0;
+  }
+  if (blockIdx.x == 0) {
+    __syncthreads();  // block 0's counter clear before its seed counters
+    seed_source<SIGMA>(a, true);
+    if (threadIdx.x == 0) a.ctl->single_gen[0] = 0u;
+  }
+  BarrierCtx bc;
+  if (!barrier_register(a.ctl, &bc, a.timeout_ticks)) return;
+  int level = 0;
+  unsigned episodes = 0;
+  bool in_episode = false;  // workgroup 0: running consecutive levels alone
+  LevelView v = read_level(a.ctl, 0);
+  long long prev_frontier = 0, prev_queue = 0;
+  float feat[kMaxSwitchFeatures];
+  for (;;) {
+    const bool done = v.frontier == 0;
+    int engine = 0, fallback = 0;
+    bool single = false;
+    if (!done) {
+      level_features(feat, v, a, level, prev_frontier);
+      engine = choose_engine_inl(a, v, feat, level, learned ? s_mlp : nullptr, &fallback);
+      if (engine == BLEST_ENGINE_PUSH) engine = BLEST_ENGINE_BVSS;
+      single = a.single_block && engine != BLEST_ENGINE_BOTTOM_UP && v.qslices <= kEagerSingleSlices;
+    }
+    if (blockIdx.x == 0 && in_episode && (done || !single)) {
+      // end of an episode: hand the state to the waiting workgroups, with the
+      // cumulative counts they did not follow
+      block_sync_mem();
+      if (threadIdx.x == 0) {
+        unsigned long long* acc = &a.ctl->acc[level % kStatSlots][0][0];
+        __hip_atomic_store(acc + F_CUMV * kPad, static_cast<unsigned long long>(v.cumv), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(acc + F_CUME * kPad, static_cast<unsigned long long>(v.cume), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.ctl->single_level[0], level, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.ctl->single_gen[0], episodes, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      in_episode = false;
+    }
+    if (done) break;
+    if (single && blockIdx.x == 0) {
+      // a small level on workgroup 0 alone, workgroup barrier only
+      if (!in_episode) {
+        in_episode = true;
+        ++episodes;
+      }
+      eager_level<SIGMA, SliceT, BLOCK>(a, level, v, prev_queue, engine, fallback, feat, threadIdx.x, BLOCK,
+                                        wave_in_block(), BLOCK / 64);
+      block_sync_mem();
+      if (threadIdx.x == 0 && level < a.log_cap) {
+        const unsigned long long t = dev_ticks();
+        a.log[level].t_mid = t;
+        a.log[level].t_end = t;
+      }
+      LevelView nv = read_level_atomic(a.ctl, (level + 1) % kStatSlots);
+      nv.light = 0;
+      nv.heavy = 0;
+      nv.cumv = v.cumv + nv.frontier;
+      nv.cume = v.cume + nv.fedges;
+      prev_frontier = v.frontier;
+      prev_queue = v.queue;
+      v = nv;
+      ++level;
+      // progress for the waiting workgroups: their time bound restarts with every level
+      if (threadIdx.x == 0)
+        __hip_atomic_store(&a.ctl->single_progress[0], level, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__hip_atomic_load(&a.ctl->error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+      continue;
+    }
+    if (single) {
+      // wait for workgroup 0's episode, bounded like a barrier; the bound
+      // restarts at every level the episode finishes
+      ++episodes;
+      if (threadIdx.x == 0) {
+        unsigned long long t0 = dev_ticks();
+        int seen = -1;
+        bool ok = true;
+        while (__hip_atomic_load(&a.ctl->single_gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < episodes) {
+          if (__hip_atomic_load(&a.ctl->error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            ok = false;
+            break;
+          }
+          const int prog = __hip_atomic_load(&a.ctl->single_progress[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (prog != seen) {
+            seen = prog;
+            t0 = dev_ticks();
+          }
+          if (dev_ticks() - t0 > a.timeout_ticks) {
+            __hip_atomic_store(&a.ctl->error[0], static_cast<int>(BLEST_ERR_TIMEOUT), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_level = ok ? __hip_atomic_load(&a.ctl->single_level[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
+      }
+      __syncthreads();
+      if (s_level < 0 || __hip_atomic_load(&a.ctl->error[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+        return;
+      level = s_level;
+      v = read_level(a.ctl, level % kStatSlots);
+      v.light = 0;
+      v.heavy = 0;
+      const LevelView pv = read_level(a.ctl, (level + kStatSlots - 1) % kStatSlots);
+      prev_frontier = pv.frontier;
+      prev_queue = pv.queue;
+      continue;
+    }
+    eager_level<SIGMA, SliceT, BLOCK>(a, level, v, prev_queue, engine, fallback, feat, gtid, nthreads, gwave, nwaves);
+    if (!grid_barrier(a.ctl, bc)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && level < a.log_cap) {
+      const unsigned long long t = dev_ticks();
+      a.log[level].t_mid = t;
+      a.log[level].t_end = t;
+      a.log[level].work = static_cast<long long>(a.ctl->acc[level % kStatSlots][F_WORK][0]);
+    }
+    LevelView nv = read_level(a.ctl, (level + 1) % kStatSlots);
+    nv.light = 0;
+    nv.heavy = 0;
+    nv.cumv = v.cumv + nv.frontier;
+    nv.cume = v.cume + nv.fedges;
+    prev_frontier = v.frontier;
+    prev_queue = v.queue;
+    v = nv;
+    ++level;
+  }
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < 8) a.ctl->xcd_blocks[threadIdx.x][0] = 0u;
+    if (threadIdx.x == 8) a.ctl->xcd_active[0] = 0u;
+    if (threadIdx.x == 0) a.ctl->nlevels[0] = level;
+  }
+}
+
 // ------------------------------------------------------ per-stage kernels
 
 template <int SIGMA, int BLOCK>
@@ -1517,8 +1982,18 @@ const void* persistent_fn() {
 }
 
 template <int SIGMA, class SliceT, int BLOCK>
+const void* eager_fn() {
+  return reinterpret_cast<const void*>(&k_bfs_eager<SIGMA, SliceT, BLOCK>);
+}
+
+template <int SIGMA, class SliceT, int BLOCK>
 hipError_t run_t(const DevGraph& g, BfsArgs& a, hipStream_t st) {
   const size_t shmem = (a.policy == BLEST_POLICY_LEARNED) ? kLdsMlpFloats * sizeof(float) : 0;
+  if (g.eager && !a.probe) {
+    void* args[] = {static_cast<void*>(&a)};
+    return hipLaunchCooperativeKernel(eager_fn<SIGMA, SliceT, BLOCK>(), dim3(g.grid_eager), dim3(BLOCK), args,
+                                      static_cast<unsigned>(shmem), st);
+  }
   if (g.persistent || a.probe) {
     void* args[] = {static_cast<void*>(&a)};
     return hipLaunchCooperativeKernel(persistent_fn<SIGMA, SliceT, BLOCK>(), dim3(g.grid), dim3(BLOCK), args,
@@ -1572,7 +2047,41 @@ hipError_t occupancy_block(const DevGraph& g, size_t shmem, int* nb) {
   }
 }
 
+template <int SIGMA, class SliceT>
+hipError_t occupancy_eager(const DevGraph& g, size_t shmem, int* nb) {
+  switch (g.block) {
+    case 256:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, eager_fn<SIGMA, SliceT, 256>(), 256, shmem);
+    case 1024:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, eager_fn<SIGMA, SliceT, 1024>(), 1024, shmem);
+    default:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, eager_fn<SIGMA, SliceT, 512>(), 512, shmem);
+  }
+}
+
 }  // namespace
+
+hipError_t bfs_grid_size_eager(const DevGraph& g, int blocks_per_cu, int* grid) {
+  // sized with the switch network's LDS, which the learned policy adds
+  const size_t shmem = kLdsMlpFloats * sizeof(float);
+  int nb = 0;
+  hipError_t e;
+  if (g.sigma == 8 && !g.wide)
+    e = occupancy_eager<8, uint32_t>(g, shmem, &nb);
+  else if (g.sigma == 8)
+    e = occupancy_eager<8, uint64_t>(g, shmem, &nb);
+  else if (g.sigma == 16)
+    e = occupancy_eager<16, uint64_t>(g, shmem, &nb);
+  else
+    e = occupancy_eager<32, uint64_t>(g, shmem, &nb);
+  if (e != hipSuccess) return e;
+  if (nb < 1) return hipErrorInvalidConfiguration;
+  // its levels are small and latency-bound: one workgroup per compute unit
+  // (fewer arrivals per device-wide barrier) unless asked otherwise
+  nb = blocks_per_cu > 0 ? std::min(nb, blocks_per_cu) : 1;
+  *grid = nb * g.num_cu;
+  return hipSuccess;
+}
 
 BfsArgs bfs_args(const DevGraph& g) {
   BfsArgs a{};
@@ -1581,6 +2090,9 @@ BfsArgs bfs_args(const DevGraph& g) {
   a.slice_ptr = g.slice_ptr;
   a.slices = g.slices;
   a.degmask = g.degmask;
+  a.rp_in = g.rp_in;
+  a.col_in = g.col_in;
+  a.degmask_in = g.degmask_in;
   a.orig_id = g.orig_id;
   a.n = g.n;
   a.m = g.m;
@@ -1590,6 +2102,7 @@ BfsArgs bfs_args(const DevGraph& g) {
   a.front = g.front;
   a.fstride = static_cast<long long>(g.fstride);
   a.mark = g.mark;
+  a.queue[2] = g.queue[2];
   for (int i = 0; i < 2; ++i) {
     a.queue[i] = g.queue[i];
     a.flight[i] = g.flight[i];

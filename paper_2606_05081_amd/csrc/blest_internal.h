@@ -8,6 +8,9 @@
 //                            64-bit  (row << 32) | mask   otherwise
 //   degmask[N_s]             sigma-bit mask of vertices with degree > 0
 //   orig_id[n]               internal id -> input id (NULL when not reordered)
+//   rp_in, col_in            in-arcs of a directed graph (Alg. 4 reads the CSR
+//                            of the transpose); the same arrays as rp, col
+//                            for an undirected graph
 // A virtual slice set (VSS) is a run of at most tau consecutive slices of one
 // slice set, so VSS k of set s covers slices [slice_ptr[s] + k*tau, ...). The
 // queue holds one 16-byte descriptor per VSS (first slice, count, frontier
@@ -62,6 +65,7 @@ struct alignas(256) Ctl {
   int overflow[kPad * 2];
   int single_level[kPad];          // first level after a single-workgroup episode
   unsigned int single_gen[kPad];   // number of finished single-workgroup episodes
+  int single_progress[kPad];       // last level a running single-workgroup episode finished
   int nlevels[kPad * 2]; // frontier levels of the last traversal
   int ms_state[2][kPad];   // multi-source graph mode: {phase, batch, level} read by even/odd kernels
   int ms_nrec[kPad];       // multi-source level records written by the last call
@@ -102,6 +106,9 @@ struct MlpDev {
 struct BfsArgs {
   const int32_t* rp;
   const int32_t* col;
+  const int32_t* rp_in;     // in-arcs, read by the bottom-up engines (rp/col for an undirected graph)
+  const int32_t* col_in;
+  const void* degmask_in;   // vertices with an in-arc (degmask for an undirected graph)
   const uint32_t* slice_ptr;
   const void* slices;
   const void* degmask;
@@ -111,10 +118,12 @@ struct BfsArgs {
   int32_t tau;
   // working state
   void* vis;       // sigma-bit visited word per slice set (V_curr)
-  void* front;     // two sigma-bit frontier words per slice set: F_curr of even levels, then of odd levels
+  void* front;     // sigma-bit frontier words per slice set, three buffers fstride bytes apart: the lazy
+                   // scheme uses the first two (by level parity), the eager scheme all three (level mod 3)
   long long fstride;  // bytes from the first frontier buffer to the second
   uint8_t* mark;   // one byte per vertex: lazily marked in Stage 1 (V_next)
-  uint4* queue[2]; // VSS descriptors {first slice, count, frontier bits, set}
+  uint4* queue[3]; // VSS descriptors {first slice, count, frontier bits, set}; the eager
+                   // scheme rotates all three, the lazy scheme uses the first two
   int32_t* flight[2];             // light frontier vertices
   unsigned long long* fheavy[2];  // heavy frontier edge chunks: (vertex << 32) | first edge offset
   Ctl* ctl;
@@ -146,6 +155,7 @@ struct BfsArgs {
 // Device-resident graph and working buffers (owned by one blest_graph).
 struct DevGraph {
   int device = 0;
+  int directed = 0;           // rp/col hold out-arcs; rp_in/col_in the in-arcs
   int sigma = 8, tau = 128, wide = 0;
   int64_t n = 0, m = 0, nsets = 0, nvss = 0, nslices = 0, nheavy_cap = 0;
   int32_t* rp = nullptr;
@@ -154,11 +164,14 @@ struct DevGraph {
   void* slices = nullptr;
   void* degmask = nullptr;
   int32_t* orig_id = nullptr;
+  const int32_t* rp_in = nullptr;   // = rp, col, degmask unless directed
+  const int32_t* col_in = nullptr;
+  const void* degmask_in = nullptr;
   void* vis = nullptr;
-  void* front = nullptr;  // two buffers, fstride bytes apart
+  void* front = nullptr;  // three buffers, fstride bytes apart
   size_t fstride = 0;
   uint8_t* mark = nullptr;
-  uint4* queue[2] = {nullptr, nullptr};
+  uint4* queue[3] = {nullptr, nullptr, nullptr};
   int32_t* flight[2] = {nullptr, nullptr};
   unsigned long long* fheavy[2] = {nullptr, nullptr};
   Ctl* ctl = nullptr;
@@ -177,6 +190,11 @@ struct DevGraph {
   int count_first = 1;
   size_t mark_bytes = 0;
   double tick_us = 0.01;      // device clock period in microseconds
+  int eager = 0;              // single-source traversals use the eager scheme (Alg. 2)
+  int ms_ablation = 0;        // multi-source ablation flags (BLEST_MS_NO_*)
+  int ms_mfma = 0;            // multi-source top-down check on MFMA (experiment)
+  int grid_eager = 0;         // co-resident grid of the eager kernel
+  double u_div = 0.0;         // update divergence of the BVSS
 };
 
 // Single-source traversal on the device (bfs.hip). Returns a HIP error;
@@ -184,6 +202,8 @@ struct DevGraph {
 hipError_t bfs_run(const DevGraph& g, BfsArgs a, hipStream_t st);
 // Largest co-resident grid of the persistent kernel for this graph.
 hipError_t bfs_grid_size(const DevGraph& g, int policy_learned, int blocks_per_cu, int* grid);
+// Same for the eager-scheme kernel.
+hipError_t bfs_grid_size_eager(const DevGraph& g, int blocks_per_cu, int* grid);
 BfsArgs bfs_args(const DevGraph& g);
 
 // Switch-network kernels (mlp.hip).

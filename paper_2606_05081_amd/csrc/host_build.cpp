@@ -18,6 +18,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <iterator>
 #include <numeric>
 #include <thread>
 
@@ -50,7 +51,7 @@ void parallel_for(int64_t n, F&& f) {
 
 }  // namespace
 
-bool validate_csr(int64_t n, int64_t m, const int32_t* rp, const int32_t* col, std::string* why) {
+bool validate_csr(int64_t n, int64_t m, const int32_t* rp, const int32_t* col, std::string* why, bool symmetric) {
   if (n <= 0 || n > INT32_MAX - 1) return *why = "n must be in [1, 2^31-1)", false;
   if (m < 0 || m >= (int64_t(1) << 31)) return *why = "m must be in [0, 2^31)", false;
   if (!rp || (m > 0 && !col)) return *why = "NULL CSR array", false;
@@ -66,6 +67,7 @@ bool validate_csr(int64_t n, int64_t m, const int32_t* rp, const int32_t* col, s
         if (v < 0 || v >= n) { bad = 2; where = u; return; }
         if (v == u) { bad = 3; where = u; return; }
         if (p > lo && col[p - 1] >= v) { bad = 4; where = u; return; }
+        if (!symmetric) continue;
         // symmetric: u must appear in row v
         const int32_t* first = col + rp[v];
         const int32_t* last = col + rp[v + 1];
@@ -80,6 +82,36 @@ bool validate_csr(int64_t n, int64_t m, const int32_t* rp, const int32_t* col, s
     return false;
   }
   return true;
+}
+
+void transpose_csr(int64_t n, const int32_t* rp, const int32_t* col, std::vector<int32_t>& rpt,
+                   std::vector<int32_t>& colt) {
+  rpt.assign(static_cast<size_t>(n) + 1, 0);
+  for (int64_t p = 0; p < rp[n]; ++p) ++rpt[col[p] + 1];
+  for (int64_t v = 0; v < n; ++v) rpt[v + 1] += rpt[v];
+  colt.resize(static_cast<size_t>(rp[n]));
+  std::vector<int32_t> next(rpt.begin(), rpt.end() - 1);
+  // sources in ascending order, so every transposed row comes out sorted
+  for (int64_t u = 0; u < n; ++u)
+    for (int32_t p = rp[u]; p < rp[u + 1]; ++p) colt[next[col[p]]++] = static_cast<int32_t>(u);
+}
+
+void symmetrize_csr(int64_t n, const int32_t* rp, const int32_t* col, std::vector<int32_t>& rps,
+                    std::vector<int32_t>& cols) {
+  std::vector<int32_t> rpt, colt;
+  transpose_csr(n, rp, col, rpt, colt);
+  rps.assign(static_cast<size_t>(n) + 1, 0);
+  std::vector<int32_t> merged;
+  cols.clear();
+  cols.reserve(static_cast<size_t>(2 * rp[n]));
+  for (int64_t u = 0; u < n; ++u) {
+    merged.clear();
+    std::merge(col + rp[u], col + rp[u + 1], colt.begin() + rpt[u], colt.begin() + rpt[u + 1],
+               std::back_inserter(merged));
+    merged.erase(std::unique(merged.begin(), merged.end()), merged.end());
+    cols.insert(cols.end(), merged.begin(), merged.end());
+    rps[u + 1] = static_cast<int32_t>(cols.size());
+  }
 }
 
 bool is_scale_free_like(int64_t n, const int32_t* rp) {
@@ -383,6 +415,42 @@ bool build_bvss(int64_t n, const int32_t* rp, const int32_t* col, int sigma, int
   for (int64_t u = 0; u < n; ++u)
     if (rp[u + 1] > rp[u]) out->degmask[u / sigma] |= uint64_t(1) << (u % sigma);
   return true;
+}
+
+double update_divergence(const Bvss& b, int tau) {
+  if (b.nvss == 0) return 0.0;
+  const int theta = std::max(1, tau / 32);
+  std::vector<double> part(static_cast<size_t>(b.nsets), 0.0);
+  parallel_for(b.nsets, [&](int64_t lo, int64_t hi) {
+    for (int64_t s = lo; s < hi; ++s) {
+      const int64_t s0 = b.slice_ptr[s], s1 = b.slice_ptr[s + 1];
+      auto row = [&](int64_t k) -> double {
+        return b.wide ? static_cast<double>(b.slices64[k] >> 32) : static_cast<double>(b.slices32[k] >> 8);
+      };
+      double acc = 0.0;
+      for (int64_t v0 = s0; v0 < s1; v0 += tau) {
+        const int64_t v1 = std::min<int64_t>(s1, v0 + tau);
+        double sum = 0.0;
+        int cols = 0;
+        for (int c = 0; c < theta; ++c) {
+          int64_t cnt = 0;
+          double mean = 0.0;
+          for (int64_t k = v0 + c; k < v1; k += theta, ++cnt) mean += row(k);
+          if (cnt == 0) continue;
+          mean /= static_cast<double>(cnt);
+          double m2 = 0.0;
+          for (int64_t k = v0 + c; k < v1; k += theta) m2 += (row(k) - mean) * (row(k) - mean);
+          sum += std::sqrt(m2 / static_cast<double>(cnt));
+          ++cols;
+        }
+        acc += sum / cols;
+      }
+      part[s] = acc;
+    }
+  });
+  double tot = 0.0;
+  for (double x : part) tot += x;
+  return tot / static_cast<double>(b.nvss);
 }
 
 int panel_log2_rows(int64_t n, int64_t workgroups) {

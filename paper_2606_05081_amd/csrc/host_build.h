@@ -17,8 +17,19 @@ struct Bvss {
   std::vector<uint64_t> degmask;    // per set: bit b = vertex s*sigma+b has degree > 0
 };
 
-// O(m log d) check of an undirected simple CSR; *why explains a failure.
-bool validate_csr(int64_t n, int64_t m, const int32_t* rp, const int32_t* col, std::string* why);
+// O(m log d) check of a simple CSR (sorted rows, no duplicates or self
+// loops; symmetric unless the graph is directed); *why explains a failure.
+bool validate_csr(int64_t n, int64_t m, const int32_t* rp, const int32_t* col, std::string* why,
+                  bool symmetric = true);
+
+// CSR of the transposed graph (in-arcs), rows sorted.
+void transpose_csr(int64_t n, const int32_t* rp, const int32_t* col, std::vector<int32_t>& rpt,
+                   std::vector<int32_t>& colt);
+
+// CSR of the undirected graph underlying a directed one (union of out- and
+// in-arcs per vertex), rows sorted and deduplicated.
+void symmetrize_csr(int64_t n, const int32_t* rp, const int32_t* col, std::vector<int32_t>& rps,
+                    std::vector<int32_t>& cols);
 
 // Heavy-tailed degree distribution test used to pick the reordering.
 bool is_scale_free_like(int64_t n, const int32_t* rp);
@@ -40,6 +51,18 @@ void permute_csr(int64_t n, const int32_t* rp, const int32_t* col, const std::ve
                  std::vector<int32_t>& new_of_old, std::vector<int32_t>& rp2, std::vector<int32_t>& col2);
 
 bool build_bvss(int64_t n, const int32_t* rp, const int32_t* col, int sigma, int tau, bool wide, Bvss* out);
+
+// Update divergence (Section "Boosting Cache Locality"): a VSS of tau slices
+// is a (tau / theta) x theta matrix whose slice j sits in column j mod theta;
+// a column's divergence is the population standard deviation of the row ids
+// of its slices (every stored slice has a nonzero mask), a VSS's divergence
+// the mean over its non-empty columns, and U_div the mean over all N_v VSSs.
+// theta = tau / 32 (the paper's 32 x 4 matrix at tau = 128). 0 without VSSs.
+double update_divergence(const Bvss& b, int tau);
+
+// The paper's dispatch (Section "Ablation Studies"): graphs with U_div above
+// this threshold use lazy vertex updates (Alg. 3), the others Alg. 2.
+constexpr double kEagerMaxUdiv = 25000.0;
 
 // Panel-blocked copy of a sigma = 8, 32-bit BVSS for dense top-down levels.
 // Rows are cut into panels of 2^rb consecutive rows; a panel's slices are

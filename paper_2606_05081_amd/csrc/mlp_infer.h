@@ -15,7 +15,7 @@ namespace blest {
 constexpr int kLdsW1T = 0, kLdsB1 = 768, kLdsW2T = 832, kLdsB2 = 4928, kLdsW3 = 4992, kLdsB3 = 5184,
               kLdsMean = 5187, kLdsInvStd = 5199, kLdsMaxRatio = 5211, kLdsMlpFloats = 5212;
 
-static __device__ void mlp_to_lds(const MlpDev* mlp, float* s) {
+static __device__ __forceinline__ void mlp_to_lds(const MlpDev* mlp, float* s) {
   const float* p = mlp->params;
   for (int i = threadIdx.x; i < 768; i += blockDim.x) {
     int j = i / 12, k = i % 12;  // W1[j][k]

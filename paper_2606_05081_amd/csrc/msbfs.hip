@@ -50,6 +50,8 @@ struct MsBatch {
 struct MsArgs {
   const int32_t* rp;
   const int32_t* col;
+  const int32_t* rp_in;   // in-arcs (the bottom-up engine); rp/col for an undirected graph
+  const int32_t* col_in;
   const uint32_t* slice_ptr;
   const void* slices;
   const int32_t* orig_id;
@@ -80,10 +82,27 @@ struct MsArgs {
   MsLevelRec* log;        // one record per level of the call, or NULL
   int32_t log_cap;
   unsigned long long timeout_ticks;
+  int32_t ablation;       // BLEST_MS_NO_GETVI | BLEST_MS_NO_DIRTY (the paper's ablation steps), else 0
 };
 
 __device__ __forceinline__ long long get_vi(long long u, long long rho, int sigma) {
   return (u % sigma) * rho + u / sigma;
+}
+
+// Ablation flags: ABL >= 0 is a compile-time value (the full method's kernel
+// uses 0, so the flags cost it nothing); ABL = -1 reads them from the arguments.
+template <int ABL>
+__device__ __forceinline__ int ms_abl(const MsArgs& a) {
+  if constexpr (ABL >= 0)
+    return ABL;
+  else
+    return a.ablation;
+}
+
+// Word index of vertex u: getVI order, or u itself in the ablation without it.
+template <int ABL>
+__device__ __forceinline__ long long ms_vi(const MsArgs& a, long long u, long long rho, int sigma) {
+  return (ms_abl<ABL>(a) & BLEST_MS_NO_GETVI) ? u : get_vi(u, rho, sigma);
 }
 
 __device__ __forceinline__ unsigned long long batch_mask(int count, int w) {
@@ -199,7 +218,7 @@ __device__ void fill_minus_one(int16_t* p, long long count, long long gtid, long
 
 // ---------------------------------------------------------------- Stage 1
 
-template <int SIGMA, class SliceT, int K>
+template <int SIGMA, class SliceT, int K, int ABL>
 __device__ void ms_engine_bvss_k(const MsArgs& a, const uint4* __restrict__ q, long long qlen, int W,
                                  long long gwave, long long nwaves, unsigned long long* lds_f) {
   const SliceT* __restrict__ sl = static_cast<const SliceT*>(a.slices);
@@ -213,7 +232,7 @@ __device__ void ms_engine_bvss_k(const MsArgs& a, const uint4* __restrict__ q, l
     // sits at b*rho + s in getVI order).
     for (int j = lane; j < SIGMA * W; j += 64) {
       const int b = j / W, w = j % W;
-      lds_f[j] = a.F[(b * rho + s) * W + w];
+      lds_f[j] = a.F[ms_vi<ABL>(a, s * SIGMA + b, rho, SIGMA) * W + w];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -229,7 +248,7 @@ __device__ void ms_engine_bvss_k(const MsArgs& a, const uint4* __restrict__ q, l
       const uint32_t mask = static_cast<uint32_t>(sv[k] & ((SliceT(1) << SIGMA) - 1));
       if (!mask) continue;
       const long long row = static_cast<long long>(sv[k] >> SliceFmt<SliceT>::kRowShift);
-      const long long vi = get_vi(row, rho, SIGMA);
+      const long long vi = ms_vi<ABL>(a, row, rho, SIGMA);
       bool any = false;
       for (int w = 0; w < W; ++w) {
         if (!a.act[s * W + w]) continue;
@@ -253,26 +272,112 @@ __device__ void ms_engine_bvss_k(const MsArgs& a, const uint4* __restrict__ q, l
   }
 }
 
-template <int SIGMA, class SliceT>
+// The same neighbour check as an int8 matrix product on the matrix cores (an
+// experiment kept behind opts.ms_mfma; sigma = 8 only). For 16 slices of a VSS
+// and 16 traversals c, C = A B with A[i][b] = bit b of slice i's mask and
+// B[b][c] = bit c of vertex b's frontier word: C[i][c] > 0 iff row i has a
+// neighbour in traversal c's frontier, the count Eq. 2 tests (popc(a & x) > 0).
+// One v_mfma_i32_16x16x32_i8 per (16 slices, 16 traversals): K = 32 holds the
+// 8 mask bits and 24 zeros; lane l supplies A[l % 16][8 (l / 16) .. + 7] and
+// B[8 (l / 16) .. + 7][l % 16], so only lanes 0..15 carry nonzero operands,
+// and receives C[4 (l / 16) + r][l % 16] in its r-th result.
+typedef int ms_v4i __attribute__((ext_vector_type(4)));
+
+template <class SliceT, int ABL>
+__device__ void ms_engine_mfma(const MsArgs& a, const uint4* __restrict__ q, long long qlen, int W, long long gwave,
+                               long long nwaves, unsigned long long* lds_f) {
+  constexpr int SIGMA = 8;
+  const SliceT* __restrict__ sl = static_cast<const SliceT*>(a.slices);
+  const long long rho = a.nsets;
+  const int lane = lane_id();
+  const int c16 = lane & 15;
+  const bool carrier = lane < 16;
+  for (long long i = gwave; i < qlen; i += nwaves) {
+    const uint4 d = q[i];
+    const uint32_t start = d.x, cnt = d.y;
+    const long long s = d.w;
+    for (int j = lane; j < SIGMA * W; j += 64) {
+      const int b = j / W, w = j % W;
+      lds_f[j] = a.F[ms_vi<ABL>(a, s * SIGMA + b, rho, SIGMA) * W + w];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t t0 = 0; t0 < cnt; t0 += 16) {
+      SliceT sw = 0;
+      if (carrier && t0 + c16 < cnt) sw = sl[start + t0 + c16];
+      const uint32_t mask = static_cast<uint32_t>(sw & SliceT(0xff));
+      long afrag = 0;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) afrag |= static_cast<long>((mask >> b) & 1u) << (8 * b);
+      unsigned long long hw[kWMax];
+#pragma unroll
+      for (int w = 0; w < kWMax; ++w) hw[w] = 0ULL;
+      for (int w = 0; w < W; ++w) {
+        if (!a.act[s * W + w]) continue;
+#pragma unroll
+        for (int j4 = 0; j4 < 4; ++j4) {
+          long bfrag = 0;
+          if (carrier) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+              bfrag |= static_cast<long>((lds_f[b * W + w] >> (16 * j4 + c16)) & 1ULL) << (8 * b);
+          }
+          ms_v4i c = {0, 0, 0, 0};
+          c = __builtin_amdgcn_mfma_i32_16x16x32_i8(afrag, bfrag, c, 0, 0, 0);
+          // row i = 4 q + r of the tile holds its 16 bits at [16 q, 16 q + 16) of ballot r
+          unsigned long long bal[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) bal[r] = __ballot(c[r] > 0);
+          const int rq = c16 >> 2, rr = c16 & 3;
+          const unsigned long long br = rr == 0 ? bal[0] : rr == 1 ? bal[1] : rr == 2 ? bal[2] : bal[3];
+          hw[w] |= ((br >> (16 * rq)) & 0xffffULL) << (16 * j4);
+        }
+      }
+      if (carrier && mask) {
+        const long long row = static_cast<long long>(sw >> SliceFmt<SliceT>::kRowShift);
+        const long long vi = ms_vi<ABL>(a, row, rho, SIGMA);
+        bool any = false;
+        for (int w = 0; w < W; ++w) {
+          unsigned long long mw = hw[w];
+          if (!mw) continue;
+          mw &= ~a.V[vi * W + w];
+          if (mw) {
+            __hip_atomic_fetch_or(&a.N[vi * W + w], mw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            any = true;
+          }
+        }
+        if (any) a.dirty[row / SIGMA] = 1;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+template <int SIGMA, class SliceT, bool MF, int ABL>
 __device__ void ms_engine_bvss(const MsArgs& a, const uint4* q, long long qlen, int W, long long gwave,
                                long long nwaves, unsigned long long* lds_f) {
+  if constexpr (MF && SIGMA == 8) {
+    ms_engine_mfma<SliceT, ABL>(a, q, qlen, W, gwave, nwaves, lds_f);
+    return;
+  }
   switch (a.tau) {
     case 64:
-      ms_engine_bvss_k<SIGMA, SliceT, 1>(a, q, qlen, W, gwave, nwaves, lds_f);
+      ms_engine_bvss_k<SIGMA, SliceT, 1, ABL>(a, q, qlen, W, gwave, nwaves, lds_f);
       break;
     case 128:
-      ms_engine_bvss_k<SIGMA, SliceT, 2>(a, q, qlen, W, gwave, nwaves, lds_f);
+      ms_engine_bvss_k<SIGMA, SliceT, 2, ABL>(a, q, qlen, W, gwave, nwaves, lds_f);
       break;
     case 192:
-      ms_engine_bvss_k<SIGMA, SliceT, 3>(a, q, qlen, W, gwave, nwaves, lds_f);
+      ms_engine_bvss_k<SIGMA, SliceT, 3, ABL>(a, q, qlen, W, gwave, nwaves, lds_f);
       break;
     default:
-      ms_engine_bvss_k<SIGMA, SliceT, 4>(a, q, qlen, W, gwave, nwaves, lds_f);
+      ms_engine_bvss_k<SIGMA, SliceT, 4, ABL>(a, q, qlen, W, gwave, nwaves, lds_f);
       break;
   }
 }
 
-template <int SIGMA>
+template <int SIGMA, int ABL>
 __device__ void ms_engine_pull(const MsArgs& a, int W, int count, const unsigned long long* live, long long gtid,
                                long long nthreads) {
   const long long rho = a.nsets;
@@ -280,9 +385,9 @@ __device__ void ms_engine_pull(const MsArgs& a, int W, int count, const unsigned
 #pragma unroll
   for (int w = 0; w < kWMax; ++w) bm[w] = (w < W) ? (batch_mask(count, w) & live[w]) : 0ULL;
   for (long long u = gtid; u < a.n; u += nthreads) {
-    const int p0 = a.rp[u], p1 = a.rp[u + 1];
+    const int p0 = a.rp_in[u], p1 = a.rp_in[u + 1];
     if (p0 == p1) continue;
-    const long long vi = get_vi(u, rho, SIGMA);
+    const long long vi = ms_vi<ABL>(a, u, rho, SIGMA);
     unsigned long long unv[kWMax], acc[kWMax];
     bool open = false;
 #pragma unroll
@@ -293,7 +398,7 @@ __device__ void ms_engine_pull(const MsArgs& a, int W, int count, const unsigned
     }
     if (!open) continue;
     for (int p = p0; p < p1; ++p) {
-      const long long iv = get_vi(a.col[p], rho, SIGMA);
+      const long long iv = ms_vi<ABL>(a, a.col_in[p], rho, SIGMA);
       bool covered = true;
 #pragma unroll
       for (int w = 0; w < kWMax; ++w) {
@@ -326,7 +431,7 @@ struct MsExpandRec {
 constexpr int kMsExpandMin = 8;
 constexpr int kMsMaxExpand = 128;
 
-template <int SIGMA, int BLOCK>
+template <int SIGMA, int BLOCK, int ABL>
 __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, int slot_out, int sel_out,
                             long long cum_in, int* lds_cnt, bool count_sources) {
   __shared__ int lds32[BLOCK / 64];
@@ -348,7 +453,11 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
   for (long long base = static_cast<long long>(blockIdx.x) * BLOCK; base < a.nsets;
        base += static_cast<long long>(gridDim.x) * BLOCK) {
     const long long s = base + threadIdx.x;
-    const bool mine = s < a.nsets && a.dirty[s];
+    // Without dynamic slice-set tracking (an ablation step) every set is
+    // finalised at every level, all its words count as active and all its
+    // VSSs are queued.
+    const bool track = !(ms_abl<ABL>(a) & BLEST_MS_NO_DIRTY);
+    const bool mine = s < a.nsets && (!track || a.dirty[s]);
     int nq = 0;
     uint32_t s0 = 0, ns = 0;
     if (__syncthreads_or(mine)) {
@@ -366,7 +475,7 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
           for (int b = 0; b < SIGMA; ++b) {
             dw[b] = 0ULL;
             if (mine) {
-              const long long idx = (b * rho + s) * W + w;
+              const long long idx = ms_vi<ABL>(a, s * SIGMA + b, rho, SIGMA) * W + w;
               const unsigned long long nx = a.N[idx];
               unsigned long long dd = 0ULL;
               if (nx) {
@@ -381,7 +490,7 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
               far_cnt[b] += __popcll(dd);
             }
           }
-          if (mine) a.act[s * W + w] = Aw;
+          if (mine) a.act[s * W + w] = track ? Aw : ~0ULL;
           A_any |= Aw;
           if (Aw & ~lds_live[w])
             __hip_atomic_fetch_or(&lds_live[w], Aw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -430,7 +539,7 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
             a.far[a.orig_id ? a.orig_id[u] : u] += static_cast<int64_t>(new_level) * far_cnt[b];
           }
       }
-      if (mine && A_any) {
+      if (mine && (A_any || !track)) {
         s0 = a.slice_ptr[s];
         ns = a.slice_ptr[s + 1] - s0;
         nq = static_cast<int>((ns + tau - 1) / tau);
@@ -500,8 +609,13 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
 
 // ------------------------------------------------------------- kernel
 
-template <int SIGMA, class SliceT, int BLOCK>
+// MODE 0: the full method with the bitwise check; 1: the check on the matrix
+// cores; 10 + f: the bitwise check with ablation flags f (each a kernel of its
+// own, so no variant's branches or registers weigh on another).
+template <int SIGMA, class SliceT, int BLOCK, int MODE = 0>
 __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
+  constexpr bool MF = MODE == 1;
+  constexpr int ABL = MODE >= 10 ? MODE - 10 : 0;
   extern __shared__ float s_mlp[];
   __shared__ unsigned long long lds_f[(BLOCK / 64) * SIGMA * kWMax];
   __shared__ int lds_cnt[64 * kWMax];
@@ -541,12 +655,12 @@ __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
     // seed: mark each source in its own traversal's bit
     for (long long c = gtid; c < bt.count; c += nthreads) {
       const long long u = a.srcs[bt.offset + c];
-      const long long vi = get_vi(u, rho, SIGMA);
+      const long long vi = ms_vi<ABL>(a, u, rho, SIGMA);
       __hip_atomic_fetch_or(&a.N[vi * W + c / 64], 1ULL << (c % 64), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       a.dirty[u / SIGMA] = 1;
     }
     if (!grid_barrier(a.ctl, bc)) return;
-    ms_finalize<SIGMA, BLOCK>(a, bt, 0, 0, 0, 0, lds_cnt, count_sources);
+    ms_finalize<SIGMA, BLOCK, ABL>(a, bt, 0, 0, 0, 0, lds_cnt, count_sources);
     if (!grid_barrier(a.ctl, bc)) return;
     const long long pairs_total = static_cast<long long>(bt.count) * a.n;
     for (int level = 0;; ++level) {
@@ -583,10 +697,10 @@ __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
       if (a.probe) {
         // both engines from the same state: their marks are the same set
         const unsigned long long t0 = dev_ticks();
-        ms_engine_bvss<SIGMA, SliceT>(a, a.queue[level & 1], qlen, W, gwave, nwaves, my_f);
+        ms_engine_bvss<SIGMA, SliceT, MF, ABL>(a, a.queue[level & 1], qlen, W, gwave, nwaves, my_f);
         if (!grid_barrier(a.ctl, bc)) return;
         const unsigned long long t1 = dev_ticks();
-        ms_engine_pull<SIGMA>(a, W, bt.count, live_w, gtid, nthreads);
+        ms_engine_pull<SIGMA, ABL>(a, W, bt.count, live_w, gtid, nthreads);
         if (!grid_barrier(a.ctl, bc)) return;
         if (blockIdx.x == 0 && threadIdx.x == 0 && rec) {
           rec->t_engine[0] = t1 - t0;
@@ -594,12 +708,12 @@ __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
         }
       } else {
         if (engine == BLEST_ENGINE_BVSS)
-          ms_engine_bvss<SIGMA, SliceT>(a, a.queue[level & 1], qlen, W, gwave, nwaves, my_f);
+          ms_engine_bvss<SIGMA, SliceT, MF, ABL>(a, a.queue[level & 1], qlen, W, gwave, nwaves, my_f);
         else
-          ms_engine_pull<SIGMA>(a, W, bt.count, live_w, gtid, nthreads);
+          ms_engine_pull<SIGMA, ABL>(a, W, bt.count, live_w, gtid, nthreads);
         if (!grid_barrier(a.ctl, bc)) return;
       }
-      ms_finalize<SIGMA, BLOCK>(a, bt, level + 1, (level + 1) % kStatSlots, (level & 1) ^ 1, cumv, lds_cnt,
+      ms_finalize<SIGMA, BLOCK, ABL>(a, bt, level + 1, (level + 1) % kStatSlots, (level & 1) ^ 1, cumv, lds_cnt,
                                 count_sources);
       if (!grid_barrier(a.ctl, bc)) return;
       total_levels = max(total_levels, level + 1);
@@ -644,6 +758,7 @@ constexpr int kMsGraphKernels = 32;  // kernels per captured graph (even)
 
 template <int SIGMA, class SliceT, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_ms_phase(MsArgs a, int parity) {
+  constexpr int ABL = -1;
   extern __shared__ float s_mlp[];
   __shared__ unsigned long long lds_f[(BLOCK / 64) * SIGMA * kWMax];
   __shared__ int lds_cnt[64 * kWMax];
@@ -685,14 +800,14 @@ __global__ void __launch_bounds__(BLOCK) k_ms_phase(MsArgs a, int parity) {
       case MS_SEED:
         for (long long q = gtid; q < bt.count; q += nthreads) {
           const long long u = a.srcs[bt.offset + q];
-          const long long vi = get_vi(u, rho, SIGMA);
+          const long long vi = ms_vi<ABL>(a, u, rho, SIGMA);
           __hip_atomic_fetch_or(&a.N[vi * W + q / 64], 1ULL << (q % 64), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           a.dirty[u / SIGMA] = 1;
         }
         next[0] = MS_FIN0;
         break;
       case MS_FIN0:
-        ms_finalize<SIGMA, BLOCK>(a, bt, 0, 0, 0, 0, lds_cnt, count_sources);
+        ms_finalize<SIGMA, BLOCK, ABL>(a, bt, 0, 0, 0, 0, lds_cnt, count_sources);
         next[0] = MS_ENGINE;
         next[2] = 0;
         break;
@@ -737,15 +852,15 @@ __global__ void __launch_bounds__(BLOCK) k_ms_phase(MsArgs a, int parity) {
         }
         next[3] = nrec + 1;
         if (engine == BLEST_ENGINE_BVSS)
-          ms_engine_bvss<SIGMA, SliceT>(a, a.queue[level & 1], qlen, W, gwave, nwaves, my_f);
+          ms_engine_bvss<SIGMA, SliceT, false, ABL>(a, a.queue[level & 1], qlen, W, gwave, nwaves, my_f);
         else
-          ms_engine_pull<SIGMA>(a, W, bt.count, accr + F_LIVE * kPad, gtid, nthreads);
+          ms_engine_pull<SIGMA, ABL>(a, W, bt.count, accr + F_LIVE * kPad, gtid, nthreads);
         next[0] = MS_FIN;
         break;
       }
       case MS_FIN: {
         const long long cumv = static_cast<long long>(a.ctl->acc[level % kStatSlots][F_CUMV][0]);
-        ms_finalize<SIGMA, BLOCK>(a, bt, level + 1, (level + 1) % kStatSlots, (level & 1) ^ 1, cumv, lds_cnt,
+        ms_finalize<SIGMA, BLOCK, ABL>(a, bt, level + 1, (level + 1) % kStatSlots, (level & 1) ^ 1, cumv, lds_cnt,
                                   count_sources);
         next[0] = MS_ENGINE;
         next[2] = level + 1;
@@ -819,6 +934,20 @@ constexpr int kMsBlock = 512;
 constexpr int kMsLogCap = 1 << 16;  // level records per call
 
 const void* ms_kernel(const DevGraph& g) {
+  // the matrix-core check and the ablation steps are kernels of their own, so
+  // their registers and branches never weigh on the full method's kernel
+  if (g.ms_mfma && g.sigma == 8)
+    return g.wide ? reinterpret_cast<const void*>(&k_ms_persistent<8, uint64_t, kMsBlock, 1>)
+                  : reinterpret_cast<const void*>(&k_ms_persistent<8, uint32_t, kMsBlock, 1>);
+  if (g.ms_ablation && g.sigma == 8) {
+    if (g.wide)
+      return g.ms_ablation == 1   ? reinterpret_cast<const void*>(&k_ms_persistent<8, uint64_t, kMsBlock, 11>)
+             : g.ms_ablation == 2 ? reinterpret_cast<const void*>(&k_ms_persistent<8, uint64_t, kMsBlock, 12>)
+                                  : reinterpret_cast<const void*>(&k_ms_persistent<8, uint64_t, kMsBlock, 13>);
+    return g.ms_ablation == 1   ? reinterpret_cast<const void*>(&k_ms_persistent<8, uint32_t, kMsBlock, 11>)
+           : g.ms_ablation == 2 ? reinterpret_cast<const void*>(&k_ms_persistent<8, uint32_t, kMsBlock, 12>)
+                                : reinterpret_cast<const void*>(&k_ms_persistent<8, uint32_t, kMsBlock, 13>);
+  }
   if (g.sigma == 8 && !g.wide) return ms_fn_block<8, uint32_t>(kMsBlock);
   if (g.sigma == 8) return ms_fn_block<8, uint64_t>(kMsBlock);
   if (g.sigma == 16) return ms_fn_block<16, uint64_t>(kMsBlock);
@@ -893,6 +1022,8 @@ MsArgs ms_args(const DevGraph& g, const MsDev* ms, const int32_t* srcs_dev, cons
   MsArgs a{};
   a.rp = g.rp;
   a.col = g.col;
+  a.rp_in = g.rp_in;
+  a.col_in = g.col_in;
   a.slice_ptr = g.slice_ptr;
   a.slices = g.slices;
   a.orig_id = g.orig_id;
@@ -927,6 +1058,7 @@ MsArgs ms_args(const DevGraph& g, const MsDev* ms, const int32_t* srcs_dev, cons
   a.eta = eta;
   a.seed = seed;
   a.timeout_ticks = 3000000000ULL;  // 30 s
+  a.ablation = g.ms_ablation;
   return a;
 }
 

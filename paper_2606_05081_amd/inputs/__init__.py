@@ -3,7 +3,8 @@
 A module of its own: it manufactures inputs and holds none of the BFS
 arithmetic. Both the GPU library's callers and the CPU oracle take their
 graphs from here. Graphs are returned as (row_ptr int32[n+1], col int32[m])
-numpy arrays of an undirected simple graph with sorted rows.
+numpy arrays of an undirected simple graph with sorted rows (the directed
+generators: out-neighbour rows of a simple digraph).
 """
 from __future__ import annotations
 
@@ -44,6 +45,10 @@ def _load():
     lib.gg_erdos_renyi.restype = vp
     lib.gg_from_pairs.argtypes = [i64, i64, p32, p32]
     lib.gg_from_pairs.restype = vp
+    lib.gg_directed_from_pairs.argtypes = [i64, i64, p32, p32, i32]
+    lib.gg_directed_from_pairs.restype = vp
+    lib.gg_rmat_directed.argtypes = [i32, i32, f64, f64, f64, u64, i32, i32, i32]
+    lib.gg_rmat_directed.restype = vp
     lib.gg_permute.argtypes = [i64, p32, p32, u64, p32, i32]
     lib.gg_permute.restype = vp
     lib.gg_sources.argtypes = [i64, p32, i64, u64, i32, i32, p32]
@@ -92,6 +97,21 @@ def from_pairs(n: int, us, vs):
     if us.shape != vs.shape:
         raise ValueError("us and vs differ in length")
     return _take(_load().gg_from_pairs(n, us.size, _p32(us), _p32(vs)))
+
+
+def directed_from_pairs(n: int, us, vs):
+    """CSR of the arcs us[i] -> vs[i] (sorted rows, self loops and duplicates dropped)."""
+    us = np.ascontiguousarray(us, dtype=np.int32)
+    vs = np.ascontiguousarray(vs, dtype=np.int32)
+    if us.shape != vs.shape:
+        raise ValueError("us and vs differ in length")
+    return _take(_load().gg_directed_from_pairs(n, us.size, _p32(us), _p32(vs), 1))
+
+
+def rmat_directed(scale: int, seed: int, edgefactor: int = 16, permute: bool = True, threads: int = 0):
+    """Directed R-MAT: the same samples as rmat_graph kept as arcs u -> v."""
+    a, b, c = RMAT_ABC
+    return _take(_load().gg_rmat_directed(scale, edgefactor, a, b, c, seed, int(permute), threads, 1))
 
 
 def permute(row_ptr, col, seed: int, threads: int = 0):

@@ -75,8 +75,9 @@ struct Csr {
 };
 
 // Builds the symmetric, deduplicated, loop-free CSR of the undirected pairs
-// (u_i, v_i), i < npairs. `pairs` packs u in the high and v in the low 32 bits.
-Csr csr_from_pairs(int64_t n, const std::vector<uint64_t>& pairs, int threads) {
+// (u_i, v_i), i < npairs (directed: only the arc u_i -> v_i is kept). `pairs`
+// packs u in the high and v in the low 32 bits.
+Csr csr_from_pairs(int64_t n, const std::vector<uint64_t>& pairs, int threads, bool directed = false) {
   const int64_t np = static_cast<int64_t>(pairs.size());
   std::vector<std::atomic<int64_t>> cnt(n + 1);
   parallel_for(n + 1, threads, [&](int64_t b, int64_t e) {
@@ -87,7 +88,7 @@ Csr csr_from_pairs(int64_t n, const std::vector<uint64_t>& pairs, int threads) {
       uint32_t u = static_cast<uint32_t>(pairs[i] >> 32), v = static_cast<uint32_t>(pairs[i]);
       if (u == v) continue;
       cnt[u].fetch_add(1, std::memory_order_relaxed);
-      cnt[v].fetch_add(1, std::memory_order_relaxed);
+      if (!directed) cnt[v].fetch_add(1, std::memory_order_relaxed);
     }
   });
   std::vector<int64_t> off(n + 1, 0);
@@ -101,7 +102,7 @@ Csr csr_from_pairs(int64_t n, const std::vector<uint64_t>& pairs, int threads) {
       uint32_t u = static_cast<uint32_t>(pairs[i] >> 32), v = static_cast<uint32_t>(pairs[i]);
       if (u == v) continue;
       adj[cnt[u].fetch_add(1, std::memory_order_relaxed)] = static_cast<int32_t>(v);
-      adj[cnt[v].fetch_add(1, std::memory_order_relaxed)] = static_cast<int32_t>(u);
+      if (!directed) adj[cnt[v].fetch_add(1, std::memory_order_relaxed)] = static_cast<int32_t>(u);
     }
   });
   // Sort and deduplicate each row in place; record the unique length.
@@ -187,6 +188,10 @@ Result* publish(const Csr& g) {
 
 extern "C" {
 
+void* gg_rmat_directed(int32_t scale, int32_t edgefactor, double a, double b, double c, uint64_t seed,
+                       int32_t permute, int32_t threads, int32_t directed);
+void* gg_directed_from_pairs(int64_t n, int64_t npairs, const int32_t* us, const int32_t* vs, int32_t directed);
+
 // Releases a graph returned by one of the generators below.
 void gg_free(void* h) {
   Result* r = static_cast<Result*>(h);
@@ -207,6 +212,13 @@ const int32_t* gg_col(const void* h) { return static_cast<const Result*>(h)->col
 // random permutation. Returns NULL on bad arguments or out of memory.
 void* gg_rmat(int32_t scale, int32_t edgefactor, double a, double b, double c, uint64_t seed,
               int32_t permute, int32_t threads) {
+  return gg_rmat_directed(scale, edgefactor, a, b, c, seed, permute, threads, 0);
+}
+
+// The same samples kept as arcs u -> v when `directed` (self loops and
+// duplicate arcs dropped), else symmetrised as above.
+void* gg_rmat_directed(int32_t scale, int32_t edgefactor, double a, double b, double c, uint64_t seed,
+                       int32_t permute, int32_t threads, int32_t directed) {
   if (scale < 1 || scale > 30 || edgefactor < 1 || a < 0 || b < 0 || c < 0 || a + b + c > 1.0) return nullptr;
   const int64_t n = int64_t(1) << scale;
   const int64_t ne = n * edgefactor;
@@ -235,7 +247,7 @@ void* gg_rmat(int32_t scale, int32_t edgefactor, double a, double b, double c, u
         pairs[e] = (u << 32) | v;
       }
     });
-    Csr g = csr_from_pairs(n, pairs, threads);
+    Csr g = csr_from_pairs(n, pairs, threads, directed != 0);
     pairs.clear();
     pairs.shrink_to_fit();
     if (permute) g = relabel(g, random_permutation(n, s_perm), threads);
@@ -297,6 +309,12 @@ void* gg_erdos_renyi(int64_t n, int64_t npairs, uint64_t seed, int32_t threads) 
 // Builds a graph from caller-supplied undirected pairs (same canonicalisation
 // as the generators). Used for hand-made test graphs.
 void* gg_from_pairs(int64_t n, int64_t npairs, const int32_t* us, const int32_t* vs) {
+  return gg_directed_from_pairs(n, npairs, us, vs, 0);
+}
+
+// CSR of the arcs us[i] -> vs[i] when `directed` (sorted rows, self loops and
+// duplicate arcs dropped), else of the undirected pairs as above.
+void* gg_directed_from_pairs(int64_t n, int64_t npairs, const int32_t* us, const int32_t* vs, int32_t directed) {
   if (n < 1 || n > INT32_MAX || npairs < 0) return nullptr;
   try {
     std::vector<uint64_t> pairs(npairs);
@@ -304,7 +322,7 @@ void* gg_from_pairs(int64_t n, int64_t npairs, const int32_t* us, const int32_t*
       if (us[i] < 0 || us[i] >= n || vs[i] < 0 || vs[i] >= n) return nullptr;
       pairs[i] = (uint64_t(uint32_t(us[i])) << 32) | uint64_t(uint32_t(vs[i]));
     }
-    return publish(csr_from_pairs(n, pairs, 1));
+    return publish(csr_from_pairs(n, pairs, 1, directed != 0));
   } catch (...) {
     return nullptr;
   }

@@ -41,10 +41,11 @@ def test_status_strings_and_defaults():
     assert L.blest_status_str(-8) == b"TIMEOUT"
     o = blest.default_opts()
     assert (o.sigma, o.tau, o.eta, o.policy, o.persistent, o.msbfs_width) == (8, 128, 10.0, 0, 1, 512)
-    # layout of blest_opts in include/blest.h: 12 int32/float fields, a uint64, an int32, int32[7]
-    assert ctypes.sizeof(blest.Opts) == 88 and blest.Opts.random_seed.offset == 48
+    # layout of blest_opts in include/blest.h: 12 int32/float fields, a uint64, an int32, int32[11]
+    assert ctypes.sizeof(blest.Opts) == 104 and blest.Opts.random_seed.offset == 48
     assert ctypes.sizeof(blest.LevelStat) == 8 + 8 * 8 + 16 + 24 + 8 + 8 + 8
-    assert ctypes.sizeof(blest.GraphStats) == 16 + 16 + 48 + 12 + 20
+    assert ctypes.sizeof(blest.GraphStats) == 16 + 16 + 48 + 12 + 20 + 8
+    assert o.update_scheme == blest.Update.AUTO and o.directed == 0
 
 
 @pytest.mark.parametrize("case,status", [
@@ -88,12 +89,14 @@ def test_struct_layout_matches_c_compiler(tmp_path):
         ' offsetof(blest_opts, random_seed), offsetof(blest_opts, device), sizeof(blest_level_stat),'
         ' offsetof(blest_level_stat, t_step_us), sizeof(blest_graph_stats), sizeof(blest_csr),'
         ' sizeof(blest_ms_level_stat), offsetof(blest_ms_level_stat, t_engine_us),'
-        ' offsetof(blest_ms_level_stat, feat)); printf("%zu\\n", offsetof(blest_opts, jaccard_window)); return 0;}\n')
+        ' offsetof(blest_ms_level_stat, feat)); printf("%zu %zu %zu\\n", offsetof(blest_opts, jaccard_window),'
+        ' offsetof(blest_opts, update_scheme), offsetof(blest_graph_stats, u_div)); return 0;}\n')
     exe = tmp_path / "probe"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     exp = [ctypes.sizeof(blest.Opts), blest.Opts.random_seed.offset, blest.Opts.device.offset,
            ctypes.sizeof(blest.LevelStat), blest.LevelStat.t_step_us.offset, ctypes.sizeof(blest.GraphStats),
            ctypes.sizeof(blest.CSR), ctypes.sizeof(blest.MsLevelStat), blest.MsLevelStat.t_engine_us.offset,
-           blest.MsLevelStat.feat.offset, blest.Opts.jaccard_window.offset]
+           blest.MsLevelStat.feat.offset, blest.Opts.jaccard_window.offset, blest.Opts.update_scheme.offset,
+           blest.GraphStats.u_div.offset]
     assert got == exp

@@ -26,6 +26,13 @@ def blest():
     return b
 
 
+def _lazy(blest, rp, col, **opt):
+    """A graph on the lazy scheme (Alg. 3): every test of its machinery (panel
+    copy, Stage 2 variants, single-workgroup levels) must run it even where the
+    update-divergence dispatch would pick the eager kernel (small graphs)."""
+    return blest.Graph(rp, col, **{"update_scheme": blest.Update.LAZY, **opt})
+
+
 def run_all_policies(blest, g, src, ref, seeds=(1, 2, 3)):
     for pol in POLICIES:
         for sd in (seeds if pol == "RANDOM" else (1,)):
@@ -51,7 +58,7 @@ def test_closed_form_families(blest, name):
         rp, col = H.complete_bipartite(37, 91)
     else:
         rp, col = H.gnp(300, 0.02, 5)
-    g = blest.Graph(rp, col)
+    g = _lazy(blest, rp, col)
     n = rp.size - 1
     for src in {0, n // 3, n - 1}:
         run_all_policies(blest, g, src, oracle.bfs(rp, col, src))
@@ -61,7 +68,7 @@ def test_closed_form_families(blest, name):
 def test_rmat_s16_all_policies(blest):
     """Scale-16 R-MAT (65,536 vertices, edge factor 16, a,b,c = .57,.19,.19)."""
     rp, col = inputs.rmat_graph(16, 1010)
-    g = blest.Graph(rp, col)
+    g = _lazy(blest, rp, col)
     srcs = inputs.sources(rp, 4, seed=1011)
     for s in srcs:
         run_all_policies(blest, g, int(s), oracle.bfs(rp, col, int(s)))
@@ -80,7 +87,7 @@ def test_rmat_s16_all_policies(blest):
 ])
 def test_option_matrix(blest, opt):
     for rp, col in [inputs.rmat_graph(13, 77), inputs.grid_graph(70, 78)]:
-        g = blest.Graph(rp, col, **opt)
+        g = _lazy(blest, rp, col, **opt)
         for s in inputs.sources(rp, 2, seed=79):
             run_all_policies(blest, g, int(s), oracle.bfs(rp, col, int(s)), seeds=(4,))
         g.close()
@@ -105,7 +112,7 @@ def test_panel_copy_every_bvss_level(blest, name):
         rp, col = inputs.rmat_graph(12, 88)
     else:
         rp, col = inputs.from_pairs(13, [0, 1, 2, 5, 6], [1, 2, 3, 6, 7])
-    g = blest.Graph(rp, col, panel=2)
+    g = _lazy(blest, rp, col, panel=2)
     assert g.info()["panel_log2_rows"] >= 5
     n = rp.size - 1
     for src in sorted({0, n // 3, n - 1}):
@@ -124,24 +131,24 @@ def test_panel_copy_every_bvss_level(blest, name):
 def test_edge_cases(blest):
     # ragged n (not a multiple of sigma), isolated source, unreachable parts
     rp, col = inputs.from_pairs(13, [0, 1, 2, 5, 6], [1, 2, 3, 6, 7])
-    g = blest.Graph(rp, col)
+    g = _lazy(blest, rp, col)
     for s in range(13):
         run_all_policies(blest, g, s, oracle.bfs(rp, col, s))
     g.close()
     # no edges at all
     rp, col = inputs.from_pairs(9, [], [])
-    g = blest.Graph(rp, col)
+    g = _lazy(blest, rp, col)
     run_all_policies(blest, g, 4, oracle.bfs(rp, col, 4))
     g.close()
     # a single vertex
-    g = blest.Graph(np.array([0, 0], np.int32), np.zeros(0, np.int32))
+    g = _lazy(blest, np.array([0, 0], np.int32), np.zeros(0, np.int32))
     assert g.bfs(0).cpu().tolist() == [0]
     g.close()
 
 
 def test_errors(blest):
     rp, col = H.path(10)
-    g = blest.Graph(rp, col)
+    g = _lazy(blest, rp, col)
     for bad in (-1, 10, 1 << 30):
         with pytest.raises(blest.BlestError) as ei:
             g.bfs(bad)
@@ -154,7 +161,7 @@ def test_bvss_export_matches_oracle_and_fig1(blest, golden):
     from tests.test_oracle_pins import bits_lsb_first, fig1_graph
     fig = golden("fig1_bvss.txt")
     rp, col = fig1_graph()
-    g = blest.Graph(rp, col, tau=64, reorder=0)
+    g = _lazy(blest, rp, col, tau=64, reorder=0)
     b = g.export_bvss()
     ob = oracle.bvss(rp, col, 8, 64)
     for k in ("real_ptrs", "v2r", "slice_ptr", "slice_row", "slice_mask"):
@@ -167,7 +174,7 @@ def test_bvss_export_matches_oracle_and_fig1(blest, golden):
     g.close()
     for sigma, tau, wide in [(8, 128, 0), (8, 256, 1), (16, 64, 1), (32, 192, 1)]:
         rp, col = inputs.rmat_graph(11, 5)
-        g = blest.Graph(rp, col, sigma=sigma, tau=tau, wide_slices=wide, reorder=0)
+        g = _lazy(blest, rp, col, sigma=sigma, tau=tau, wide_slices=wide, reorder=0)
         b = g.export_bvss()
         ob = oracle.bvss(rp, col, sigma, tau)
         for k in ("real_ptrs", "v2r", "slice_ptr", "slice_row", "slice_mask"):
@@ -177,7 +184,7 @@ def test_bvss_export_matches_oracle_and_fig1(blest, golden):
 
 def test_rcm_export_is_bvss_of_permuted_graph(blest):
     rp, col = inputs.grid_graph(50, 9)
-    g = blest.Graph(rp, col, reorder=1)
+    g = _lazy(blest, rp, col, reorder=1)
     b = g.export_bvss()
     assert g.info()["reordered"] == 1
     perm = b["perm"]
@@ -195,7 +202,7 @@ def test_rcm_export_is_bvss_of_permuted_graph(blest):
 @pytest.mark.parametrize("single", [1, 0])
 def test_level_log_matches_oracle_counts_and_eq3_replay(blest, single):
     for rp, col in [inputs.rmat_graph(16, 1010), inputs.grid_graph(96, 4)]:
-        g = blest.Graph(rp, col, reorder=0, single_block=single)
+        g = _lazy(blest, rp, col, reorder=0, single_block=single)
         b = g.export_bvss()
         for s in inputs.sources(rp, 3, seed=12):
             s = int(s)
@@ -221,7 +228,7 @@ def test_level_log_matches_oracle_counts_and_eq3_replay(blest, single):
 def test_relabelling_equivariance(blest):
     rp, col = inputs.rmat_graph(14, 31)
     rp2, col2, perm = inputs.permute(rp, col, seed=32)
-    g1, g2 = blest.Graph(rp, col), blest.Graph(rp2, col2)
+    g1, g2 = _lazy(blest, rp, col), _lazy(blest, rp2, col2)
     for s in inputs.sources(rp, 3, seed=33):
         a = g1.bfs(int(s)).cpu().numpy()
         b = g2.bfs(int(perm[s])).cpu().numpy()
@@ -232,7 +239,7 @@ def test_relabelling_equivariance(blest):
 
 def test_probe_mode_same_levels_and_times(blest):
     rp, col = inputs.rmat_graph(15, 41)
-    g = blest.Graph(rp, col)
+    g = _lazy(blest, rp, col)
     s = int(inputs.sources(rp, 1, seed=42)[0])
     lev = g.bfs_probe(s).cpu().numpy()
     assert np.array_equal(lev, oracle.bfs(rp, col, s))
@@ -270,6 +277,15 @@ def test_full_size_sampled_sources(blest, which):
                 # the dense levels of the plain method read the panel-blocked copy
                 assert any(r["bvss_panel"] for r in g.level_stats()[:-1])
     g.close()
+    if which == "grid2048":
+        # the dispatch runs the grid on the eager kernel; the lazy scheme at full size too
+        g = _lazy(blest, rp, col)
+        s = int(srcs[0])
+        for pol in ("HEURISTIC", "BVSS"):
+            g.set_policy(getattr(blest.Policy, pol), 10.0)
+            lev = g.bfs(s).cpu().numpy()
+            assert oracle.certificate(rp, col, s, lev) == (0, -1), pol
+        g.close()
 
 
 # Learned vs heuristic switch workloads at full size: R-MAT scale 24 (16.8M
@@ -331,7 +347,7 @@ def test_more_panels_than_workgroups(blest, panel):
     """32-row panels on scale-14 R-MAT: 512 panels, so each persistent
     workgroup owns several and runs the fused Stage 2 once per panel."""
     rp, col = inputs.rmat_graph(14, 2311)
-    g = blest.Graph(rp, col, panel=panel, panel_log2_rows=5)
+    g = _lazy(blest, rp, col, panel=panel, panel_log2_rows=5)
     info = g.info()
     assert info["panel_log2_rows"] == 5 and (info["n"] >> 5) > info["grid_blocks"]
     for s in inputs.sources(rp, 3, seed=2312):
@@ -349,8 +365,8 @@ def test_jaccard_reordering_exact_and_compresses(blest):
     still in input ids and exact (the relabelling only changes the BVSS)."""
     import oracle.jaccard as J
     rp, col = inputs.rmat_graph(13, 91)
-    base = blest.Graph(rp, col, reorder=0)
-    g = blest.Graph(rp, col, reorder=3, jaccard_window=256)
+    base = _lazy(blest, rp, col, reorder=0)
+    g = _lazy(blest, rp, col, reorder=3, jaccard_window=256)
     sb, sj = base.info(), g.info()
     assert sj["reordered"] == 3 and sb["reordered"] == 0
     nof = blest.blest_reorder_jaccard(rp, col, 8, 256)
@@ -374,3 +390,18 @@ def test_jaccard_reordering_exact_and_compresses(blest):
     auto = blest.Graph(grp, gcol)
     assert auto.info()["reordered"] == 1
     auto.close()
+
+
+def test_long_single_workgroup_episode_is_not_a_timeout(blest):
+    """A 600,000-vertex path: on the lazy scheme every level runs on
+    workgroup 0 alone (one episode of ~600K small levels, longer than the 10 s
+    bound of a barrier wait); the waiting workgroups restart their bound at
+    every finished level, so the traversal completes. Both schemes exact."""
+    n = 600_000
+    rp, col = H.path(n)
+    want = np.arange(n, dtype=np.int32)
+    for scheme in (blest.Update.LAZY, blest.Update.EAGER):
+        g = blest.Graph(rp, col, update_scheme=int(scheme), reorder=0)
+        lev = g.bfs(0).cpu().numpy()
+        assert np.array_equal(lev, want), scheme
+        g.close()

@@ -120,7 +120,8 @@ def test_in_kernel_inference_matches_oracle_decisions(env):
     rng = np.random.default_rng(8)
     theta = rng.normal(0, 0.5, omlp.N_PARAMS).astype(np.float32)
     for rp, col in (inputs.rmat_graph(15, 9), inputs.grid_graph(64, 9)):
-        g = blest.Graph(rp, col)
+        # the lazy scheme runs every engine the network picks (the eager one runs push levels top-down)
+        g = blest.Graph(rp, col, update_scheme=blest.Update.LAZY)
         feats = []
         for s in inputs.sources(rp, 3, seed=10):
             g.set_policy(blest.Policy.HEURISTIC)

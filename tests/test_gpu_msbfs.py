@@ -391,3 +391,39 @@ def test_closeness_resumable_checkpoint(blest, tmp_path):
         g.closeness_resumable(srcs[::-1].copy(), path)
     assert ei.value.status == blest.Status.INVALID_ARG
     g.close()
+
+
+@pytest.mark.parametrize("ablation", [1, 2, 3])
+def test_ablation_variants_exact(blest, ablation):
+    """The multi-source ablation steps (no getVI remap, no dynamic slice-set
+    tracking, neither) change the work, never the results."""
+    for rp, col in [inputs.rmat_graph(12, 2401), inputs.grid_graph(50, 2402)]:
+        srcs = inputs.sources(rp, 200, seed=2403)
+        ref = oracle.msbfs16(rp, col, srcs)
+        osum, oreach, occ = oracle.closeness(rp, col, srcs)
+        g = blest.Graph(rp, col, ms_ablation=ablation)
+        for pol in ("HEURISTIC", "BVSS", "BOTTOM_UP"):
+            g.set_policy(getattr(blest.Policy, pol), 10.0)
+            assert np.array_equal(g.msbfs_batched(srcs, [64, 128]).cpu().numpy(), ref), (ablation, pol)
+            s_, r_, c_ = g.closeness(srcs)
+            assert np.array_equal(s_.cpu().numpy(), osum) and np.array_equal(r_.cpu().numpy(), oreach)
+            assert np.array_equal(c_.cpu().numpy(), occ)
+        g.close()
+
+
+@pytest.mark.parametrize("wide", [0, 1])
+def test_mfma_neighbour_check_exact(blest, wide):
+    """The multi-source top-down check as an int8 matrix product on the matrix
+    cores (opts.ms_mfma): identical levels, sums, reach and closeness."""
+    for rp, col in [inputs.rmat_graph(12, 2501), inputs.grid_graph(40, 2502), H.hypercube(9)]:
+        srcs = inputs.sources(rp, 300, seed=2503, distinct=False)
+        ref = oracle.msbfs16(rp, col, srcs)
+        osum, oreach, occ = oracle.closeness(rp, col, srcs)
+        g = blest.Graph(rp, col, ms_mfma=1, wide_slices=wide)
+        for pol in ("BVSS", "HEURISTIC", "RANDOM"):
+            g.set_policy(getattr(blest.Policy, pol), 10.0, 4)
+            assert np.array_equal(g.msbfs_batched(srcs, [64, 128, 256, 512]).cpu().numpy(), ref), pol
+            s_, r_, c_ = g.closeness(srcs)
+            assert np.array_equal(s_.cpu().numpy(), osum) and np.array_equal(r_.cpu().numpy(), oreach)
+            assert np.array_equal(c_.cpu().numpy(), occ)
+        g.close()

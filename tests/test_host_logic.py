@@ -2,6 +2,7 @@
 import json
 
 import numpy as np
+import pytest
 
 from paper_2606_05081_amd import autotune, switch
 
@@ -92,3 +93,19 @@ def test_jaccard_host_rejects_bad_arguments():
     with pytest.raises(blest.BlestError) as ei:
         blest.blest_reorder_jaccard(np.array([0, 1, 1], np.int32), np.array([1], np.int32), 8, 16)
     assert ei.value.status == blest.Status.INVALID_GRAPH
+
+
+def test_update_divergence_host_equals_oracle():
+    """The library's host U_div (used for the lazy/eager dispatch) equals the
+    oracle's on several graphs, slice-set widths and VSS sizes."""
+    import oracle
+    from paper_2606_05081_amd import blest, inputs
+    cases = [inputs.rmat_graph(10, 5), inputs.grid_graph(40, 6), inputs.er_graph(10, 7),
+             inputs.from_pairs(300, np.arange(299), np.arange(1, 300))]
+    for rp, col in cases:
+        for sigma, tau in [(8, 128), (8, 64), (16, 256), (32, 192)]:
+            got = blest.blest_update_divergence(rp, col, sigma, tau)
+            want = oracle.update_divergence(rp, col, sigma, tau)
+            assert got == pytest.approx(want, rel=1e-12, abs=1e-12), (sigma, tau)
+    with pytest.raises(blest.BlestError):
+        blest.blest_update_divergence(rp, col, 12, 128)

@@ -503,3 +503,91 @@ def test_jaccard_score_is_the_ratio_not_the_overlap():
     rp, col = _jaccard_case(13, [(4, 4), (3, 0)])
     nof = J.jaccard_with_windows(rp, col, sigma=2, window=4)
     assert nof[:4].tolist() == [3, 1, 2, 0]
+
+
+def test_update_divergence_hand_worked():
+    """U_div (Section "Boosting Cache Locality") on a graph worked by hand:
+    vertex 0 adjacent to rows R = 9, 12, 20, 28, 33, 41, 50, 62, 63; sigma = 8,
+    tau = 8, theta = 4. Slice set 0 holds nine slices (rows R): its first VSS
+    is the 2 x 4 matrix with columns {9, 33}, {12, 41}, {20, 50}, {28, 62}
+    (standard deviations 12, 14.5, 15, 17, mean 14.625); its second VSS is the
+    single slice of row 63 (0). Sets 1..7 hold one slice each (row 0): 0.
+    U_div = 14.625 / 9 VSSs = 1.625. A column-major reading of the matrix
+    (slice j in column j // 2) would give 0.4306, the sample standard
+    deviation 2.2981, an average over slice sets 1.828."""
+    R = [9, 12, 20, 28, 33, 41, 50, 62, 63]
+    rp, col = inputs.from_pairs(64, [0] * len(R), R)
+    assert oracle.update_divergence(rp, col, sigma=8, tau=8, theta=4) == pytest.approx(1.625, rel=1e-15)
+    # a star on 9 vertices, tau = 128 (the 32 x 4 matrix): set 0 has the
+    # slices of rows 0..8 in one VSS, columns {0, 4, 8}, {1, 5}, {2, 6}, {3, 7}
+    # (deviations sqrt(32/3), 2, 2, 2); set 1 one slice: 0
+    rp, col = H.star(9)
+    want = (np.sqrt(32.0 / 3.0) + 6.0) / 4.0 / 2.0
+    assert oracle.update_divergence(rp, col) == pytest.approx(want, rel=1e-15)
+    # no edges: no VSS at all
+    rp, col = inputs.from_pairs(20, [], [])
+    assert oracle.update_divergence(rp, col) == 0.0
+
+
+def _digraph(n, p, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.random((n, n)) < p
+    np.fill_diagonal(a, False)
+    u, v = np.nonzero(a)
+    return inputs.directed_from_pairs(n, u, v)
+
+
+def test_directed_bfs_brute_force_and_eq1():
+    """Directed graphs (Background: A is the transposed adjacency, A[i][j] = 1
+    iff arc j -> i): the oracle's queue BFS over out-arcs equals Floyd-Warshall
+    on the arcs and the literal Boolean-semiring iteration of Eq. 1."""
+    for n, p, seed in [(40, 0.05, 1), (60, 0.03, 2), (25, 0.15, 3), (50, 0.0, 4)]:
+        rp, col = _digraph(n, p, seed)
+        fw = H.floyd_warshall(rp, col)
+        for s in range(0, n, 7):
+            lev = oracle.bfs(rp, col, s)
+            assert np.array_equal(lev, fw[s]), (n, p, s)
+            assert np.array_equal(lev, H.dense_eq1_levels(rp, col, s)), (n, p, s)
+            assert oracle.certificate_directed(rp, col, s, lev) == (0, -1)
+
+
+def test_directed_closed_forms():
+    n = 200
+    rp, col = inputs.directed_from_pairs(n, np.arange(n - 1), np.arange(1, n))  # path 0 -> 1 -> ... -> n-1
+    for s in (0, 57, n - 1):
+        want = np.where(np.arange(n) >= s, np.arange(n) - s, -1)
+        assert np.array_equal(oracle.bfs(rp, col, s), want)
+    rp, col = inputs.directed_from_pairs(n, np.arange(n), (np.arange(n) + 1) % n)  # directed cycle
+    for s in (0, 123):
+        assert np.array_equal(oracle.bfs(rp, col, s), (np.arange(n) - s) % n)
+    # per-source sums along arcs: the cycle's are n(n-1)/2 for every source
+    srcs = np.array([0, 5, 199], np.int32)
+    sums, reach, _ = oracle.closeness(rp, col, srcs)
+    assert sums.tolist() == [n * (n - 1) // 2] * 3 and reach.tolist() == [n] * 3
+
+
+def test_directed_certificate_rejects_planted_mistakes():
+    rp, col = _digraph(60, 0.04, 9)
+    s = max(range(60), key=lambda x: int((oracle.bfs(rp, col, x) >= 0).sum()))
+    good = oracle.bfs(rp, col, s)
+    assert 3 < (good >= 0).sum() < 60
+    assert oracle.certificate_directed(rp, col, s, good)[0] == 0
+    reached = np.nonzero(good > 0)[0]
+    unreached = np.nonzero(good < 0)[0]
+    v = int(reached[-1])
+    bad = good.copy()
+    bad[v] += 1  # too far: some in-arc from level good[v]-1 now skips a level
+    assert oracle.certificate_directed(rp, col, s, bad)[0] in (3, 4)
+    bad = good.copy()
+    bad[v] -= 1  # too close: no parent one level up
+    assert oracle.certificate_directed(rp, col, s, bad)[0] in (3, 4)
+    bad = good.copy()
+    bad[v] = -1  # a reached vertex claimed unreachable
+    assert oracle.certificate_directed(rp, col, s, bad)[0] == 2
+    if unreached.size:
+        bad = good.copy()
+        bad[int(unreached[0])] = int(good.max()) + 1  # an unreachable vertex with a level
+        assert oracle.certificate_directed(rp, col, s, bad)[0] == 4
+    bad = good.copy()
+    bad[s] = 1
+    assert oracle.certificate_directed(rp, col, s, bad)[0] == 1
