@@ -1714,7 +1714,7 @@ __device__ __forceinline__ void eager_flush(const BfsArgs& a, const EagerStats& 
 // Levels whose queue holds at most this many slices run on workgroup 0 alone
 // (workgroup barriers instead of device-wide ones), consecutively, while the
 // other workgroups wait; a bottom-up level never does.
-constexpr long long kEagerSingleSlices = 4096;
+constexpr long long kEagerSingleSlices = 256;
 
 // One level of the eager scheme by the calling workgroups (the whole grid,
 // or workgroup 0 alone): bookkeeping, the engine and its counters. The caller
