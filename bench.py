@@ -513,6 +513,22 @@ def main():
                   "us_per_level": round(float(np.mean(pan_us)), 1),
                   "GBs": round(float(np.sum(pan_b)) / (float(np.sum(pan_us)) * 1e-6) / 1e9, 1)}}
     g.close()
+    # the same sources on the autotuner's options for this graph size (the
+    # switch network and the tuned eta were fitted at the default 128 slices
+    # per VSS, which the headline keeps)
+    tg = blest.Graph(rp, col, device=0, autotune=True, **{"async": 1})
+    if model is not None:
+        install_model(tg, model)
+    tinfo = tg.info()
+    tres = {"cache_entry": tg.autotuned, "tau": tinfo["tau"], "sigma": tinfo["sigma"]}
+    tout = torch.empty(tg.n, dtype=torch.int32, device=dev)
+    for tag, pol, eta in (("learned", blest.Policy.LEARNED, 10.0), ("heuristic_eta10", blest.Policy.HEURISTIC, 10.0),
+                          ("plain", blest.Policy.BVSS, 10.0)):
+        if pol == blest.Policy.LEARNED and model is None:
+            continue
+        tres[f"{tag}_gteps"] = round(policy_gteps(tg, srcs, edges, tout, pol, eta, torch)[0], 3)
+    extras["rmat22_autotuned"] = tres
+    tg.close()
 
     cpu = None
     if not args.no_extras:
@@ -549,8 +565,11 @@ def main():
         # batched multi-source BFS: scale-20 R-MAT, 960 sources, batches 64/128/256/512 in one launch
         mrp, mcol = inputs.rmat_graph(20, 1040)
         msrcs = inputs.sources(mrp, 960, seed=1041)
-        mg = blest.Graph(mrp, mcol, device=0, **{"async": 1})
+        # slice width and VSS size from the autotuner (the batch widths are the workload's)
+        mg = blest.Graph(mrp, mcol, device=0, autotune=True, **{"async": 1})
         minfo = mg.info()
+        extras["msbfs_autotuned"] = {"cache_entry": mg.autotuned, "sigma": minfo["sigma"], "tau": minfo["tau"],
+                                     "slice_bytes": minfo["slice_bytes"]}
         mout = torch.empty((960, mg.n), dtype=torch.int16, device=dev)
         mg.msbfs_batched(msrcs, [64, 128, 256, 512], mout)
         mg.sync()
@@ -586,7 +605,7 @@ def main():
         ladder = {"naive_single_source": round(960 / naive_ms * 1e3, 1)}
         mg.close()
         for tag, flags in (("A_no_getvi_no_tracking", 3), ("AB_no_tracking", 2)):
-            ag = blest.Graph(mrp, mcol, device=0, ms_ablation=flags, **{"async": 1})
+            ag = blest.Graph(mrp, mcol, device=0, ms_ablation=flags, autotune=True, **{"async": 1})
             ag.msbfs_batched(msrcs, [64, 128, 256, 512], mout)
             ladder[tag] = round(960 / timed_call(lambda: ag.msbfs_batched(msrcs, [64, 128, 256, 512], mout),
                                                  torch) * 1e3, 1)
@@ -594,14 +613,14 @@ def main():
         ladder["full"] = extras["msbfs_sources_per_s"]
         extras["msbfs_ablation_sources_per_s"] = ladder
         # the neighbour check on the matrix cores (int8 MFMA) instead of bitwise, same sources
-        xg = blest.Graph(mrp, mcol, device=0, ms_mfma=1, **{"async": 1})
+        xg = blest.Graph(mrp, mcol, device=0, ms_mfma=1, autotune=True, **{"async": 1})
         xg.msbfs_batched(msrcs, [64, 128, 256, 512], mout)
         extras["msbfs_mfma_sources_per_s"] = round(
             960 / timed_call(lambda: xg.msbfs_batched(msrcs, [64, 128, 256, 512], mout), torch) * 1e3, 1)
         xg.close()
         del mout
         # the same 960 sources with the levels as a replayed hipGraph of per-phase kernels
-        gmg = blest.Graph(mrp, mcol, device=0, msbfs_graph=1, **{"async": 1})
+        gmg = blest.Graph(mrp, mcol, device=0, msbfs_graph=1, autotune=True, **{"async": 1})
         gmout = torch.empty((960, gmg.n), dtype=torch.int16, device=dev)
         gmg.msbfs_batched(msrcs, [64, 128, 256, 512], gmout)
         gmg.sync()
@@ -641,8 +660,8 @@ def main():
             crp, ccol = inputs.rmat_graph(scale, gseed)
             cs = np.arange(crp.size - 1, dtype=np.int32) if k is None else inputs.sources(crp, k, seed=gseed + 1)
             cgraphs[tag] = (crp, ccol, cs)
-            cg = blest.Graph(crp, ccol, device=0, msbfs_width=512, **{"async": 1})
-            res = {"sources": int(cs.size)}
+            cg = blest.Graph(crp, ccol, device=0, msbfs_width=512, autotune=True, **{"async": 1})
+            res = {"sources": int(cs.size), "autotuned": cg.autotuned, "tau": cg.info()["tau"]}
             pols = [("heuristic", blest.Policy.HEURISTIC)]
             if ms_model is not None:
                 cg.set_ms_switch_model(np.array(ms_model["params"], np.float32), np.array(ms_model["mean"], np.float32),

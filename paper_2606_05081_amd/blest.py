@@ -405,8 +405,10 @@ class Graph:
         self.close()
         return False
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # the default argument keeps the check reachable while module globals
+        # (sys among them) are being torn down
+        if _finalizing():
             return
         try:
             self.close()
