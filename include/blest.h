@@ -300,7 +300,9 @@ typedef struct {
   int32_t panel_log2_rows; /* rows per panel of the panel-blocked copy = 2^this; 0 if not built */
   int32_t update_scheme;   /* BLEST_UPDATE_LAZY or BLEST_UPDATE_EAGER: the scheme traversals use */
   int32_t directed;        /* 1 if built from a directed CSR */
-  int32_t reserved[2];
+  int32_t ms_graph_captures; /* multi-source graph mode (msbfs_graph = 1): hipGraphs built so far;
+                                one per kernel variant, grid and LDS size, reused by later calls */
+  int32_t reserved;
   double u_div;            /* update divergence of the built BVSS (after reordering); see
                               blest_update_divergence */
 } blest_graph_stats;

@@ -97,7 +97,8 @@ class GraphStats(ctypes.Structure):
                 ("csr_bytes", ctypes.c_int64), ("work_bytes", ctypes.c_int64), ("grid_blocks", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("panel_log2_rows", ctypes.c_int32), ("update_scheme", ctypes.c_int32),
-                ("directed", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2), ("u_div", ctypes.c_double)]
+                ("directed", ctypes.c_int32), ("ms_graph_captures", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("u_div", ctypes.c_double)]
 
 
 class LevelStat(ctypes.Structure):

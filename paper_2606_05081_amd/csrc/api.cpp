@@ -527,6 +527,7 @@ blest_status blest_graph_info(const blest_graph* g, blest_graph_stats* out) {
   out->panel_log2_rows = g->d.npanels > 0 ? g->d.panel_rb : 0;
   out->update_scheme = g->d.eager ? BLEST_UPDATE_EAGER : BLEST_UPDATE_LAZY;
   out->directed = g->d.directed;
+  out->ms_graph_captures = static_cast<int32_t>(g->ms.gcaptures);
   out->u_div = g->d.u_div;
   return BLEST_OK;
 }

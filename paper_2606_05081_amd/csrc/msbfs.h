@@ -33,6 +33,16 @@ struct MsDev {
   int log_cap = 0;
   hipStream_t gstream = nullptr;  // graph mode: capture/replay stream (non-blocking)
   hipEvent_t gev[2] = {nullptr, nullptr};
+  // graph mode: the graph of phase kernels, built and instantiated once per
+  // kernel variant, grid and LDS size; a call rewrites its kernel nodes'
+  // arguments
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraphNode_t gnode[32] = {};
+  const void* gfn = nullptr;
+  int ggrid = 0;
+  unsigned gshmem = 0;
+  long long gcaptures = 0;  // graphs built so far
 };
 
 // Runs all k sources in one persistent launch, in consecutive batches whose

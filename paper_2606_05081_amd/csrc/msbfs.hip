@@ -27,6 +27,7 @@
 // nonzero, int16 levels are written, and per-source counts of newly reached
 // vertices feed the closeness sums.
 #include <algorithm>
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -754,7 +755,8 @@ __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
 // slot while it is being written). After the last batch the phase is
 // MS_DONE and the remaining kernels of a replay do nothing.
 enum MsPhase : int { MS_INIT = 0, MS_SEED = 1, MS_FIN0 = 2, MS_ENGINE = 3, MS_FIN = 4, MS_END = 5, MS_DONE = 6 };
-constexpr int kMsGraphKernels = 32;  // kernels per captured graph (even)
+constexpr int kMsGraphKernels = 32;  // kernels per graph (even)
+static_assert(sizeof(MsDev::gnode) / sizeof(hipGraphNode_t) == kMsGraphKernels, "one node handle per kernel");
 
 template <int SIGMA, class SliceT, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_ms_phase(MsArgs a, int parity) {
@@ -954,6 +956,15 @@ const void* ms_kernel(const DevGraph& g) {
   return ms_fn_block<32, uint64_t>(kMsBlock);
 }
 
+void ms_graph_destroy(MsDev* ms) {
+  if (ms->gexec) (void)hipGraphExecDestroy(ms->gexec);
+  if (ms->graph) (void)hipGraphDestroy(ms->graph);
+  ms->gexec = nullptr;
+  ms->graph = nullptr;
+  ms->gfn = nullptr;
+  for (auto& nd : ms->gnode) nd = nullptr;
+}
+
 hipError_t ensure(const DevGraph& g, MsDev* ms, int wmax, int32_t k, int nbatches) {
   const int64_t nhat = g.nsets * g.sigma;
   if (ms->wmax < wmax || ms->nhat != nhat) {
@@ -1094,10 +1105,12 @@ hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, 
     void* args[] = {static_cast<void*>(&a)};
     return hipLaunchCooperativeKernel(ms_kernel(g), dim3(ms->grid), dim3(ms->block), args, shmem, st);
   }
-  // Graph mode: capture kMsGraphKernels phase kernels plus a copy of the state
-  // and error words to pinned host memory on a stream of our own (the caller's
-  // may be the null stream, which cannot be captured), ordered after the
-  // caller's stream by an event; replay until the state says MS_DONE.
+  // Graph mode: kMsGraphKernels phase kernels, then copies of the state and
+  // error words to pinned host memory, built once as a hipGraph for a stream
+  // of our own (the caller's may be the null stream) and replayed until the
+  // state says MS_DONE. One instantiated graph serves every call with the
+  // same kernel, grid and LDS size: a call only rewrites the kernel nodes'
+  // arguments. The replays are ordered after the caller's stream by an event.
   if (!ms->gstream) {
     if ((e = hipStreamCreateWithFlags(&ms->gstream, hipStreamNonBlocking)) != hipSuccess) return e;
     for (int i = 0; i < 2; ++i)
@@ -1108,26 +1121,56 @@ hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, 
                    : g.sigma == 16           ? ms_phase_fn<16, uint64_t>()
                                              : ms_phase_fn<32, uint64_t>();
   hipStream_t gs = ms->gstream;
-  if ((e = hipEventRecord(ms->gev[0], st)) != hipSuccess) return e;
-  if ((e = hipStreamWaitEvent(gs, ms->gev[0], 0)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ms_start, dim3(1), dim3(64), 0, gs, g.ctl);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   int* flags = g.host_flags;
-  hipGraph_t graph_h = nullptr;
-  hipGraphExec_t exec = nullptr;
-  if ((e = hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
   int par[kMsGraphKernels];
   void* kargs[kMsGraphKernels][2];
+  hipKernelNodeParams kp[kMsGraphKernels];
   for (int i = 0; i < kMsGraphKernels; ++i) {
     par[i] = i & 1;
     kargs[i][0] = static_cast<void*>(&a);
     kargs[i][1] = static_cast<void*>(&par[i]);
-    (void)hipLaunchKernel(fn, dim3(ms->grid), dim3(kMsBlock), kargs[i], shmem, gs);
+    kp[i] = hipKernelNodeParams{};
+    kp[i].func = const_cast<void*>(fn);
+    kp[i].gridDim = dim3(ms->grid);
+    kp[i].blockDim = dim3(kMsBlock);
+    kp[i].sharedMemBytes = shmem;
+    kp[i].kernelParams = kargs[i];
+    kp[i].extra = nullptr;
   }
-  (void)hipMemcpyAsync(flags + 2, &g.ctl->ms_state[0][0], sizeof(int), hipMemcpyDeviceToHost, gs);
-  (void)hipMemcpyAsync(flags + 3, &g.ctl->error[0], sizeof(int), hipMemcpyDeviceToHost, gs);
-  e = hipStreamEndCapture(gs, &graph_h);
-  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph_h, nullptr, nullptr, 0);
+  if (ms->gexec && (ms->gfn != fn || ms->ggrid != ms->grid || ms->gshmem != shmem)) {
+    ms_graph_destroy(ms);
+  }
+  if (!ms->gexec) {
+    if ((e = hipGraphCreate(&ms->graph, 0)) != hipSuccess) return e;
+    hipGraphNode_t prev = nullptr;
+    for (int i = 0; i < kMsGraphKernels && e == hipSuccess; ++i) {
+      e = hipGraphAddKernelNode(&ms->gnode[i], ms->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp[i]);
+      prev = ms->gnode[i];
+    }
+    hipGraphNode_t cp[2] = {nullptr, nullptr};
+    if (e == hipSuccess)
+      e = hipGraphAddMemcpyNode1D(&cp[0], ms->graph, &prev, 1, flags + 2, &g.ctl->ms_state[0][0], sizeof(int),
+                                  hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+      e = hipGraphAddMemcpyNode1D(&cp[1], ms->graph, &cp[0], 1, flags + 3, &g.ctl->error[0], sizeof(int),
+                                  hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipGraphInstantiate(&ms->gexec, ms->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      ms_graph_destroy(ms);
+      return e;
+    }
+    ms->gfn = fn;
+    ms->ggrid = ms->grid;
+    ms->gshmem = shmem;
+    ++ms->gcaptures;
+  } else {
+    for (int i = 0; i < kMsGraphKernels; ++i)
+      if ((e = hipGraphExecKernelNodeSetParams(ms->gexec, ms->gnode[i], &kp[i])) != hipSuccess) return e;
+  }
+  if ((e = hipEventRecord(ms->gev[0], st)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(gs, ms->gev[0], 0)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ms_start, dim3(1), dim3(64), 0, gs, g.ctl);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   // every batch has at most 3 + 2 * 32768 + 1 phases (levels are int16)
   const long long max_replays = static_cast<long long>(nplan) * (2LL * 32768 + 4) / kMsGraphKernels + 2;
   for (long long r = 0; e == hipSuccess; ++r) {
@@ -1135,12 +1178,10 @@ hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, 
       e = hipErrorLaunchTimeOut;
       break;
     }
-    if ((e = hipGraphLaunch(exec, gs)) != hipSuccess) break;
+    if ((e = hipGraphLaunch(ms->gexec, gs)) != hipSuccess) break;
     if ((e = hipStreamSynchronize(gs)) != hipSuccess) break;
     if (flags[2] == MS_DONE || flags[3] != 0) break;
   }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph_h) (void)hipGraphDestroy(graph_h);
   if (e != hipSuccess) return e;
   if ((e = hipEventRecord(ms->gev[1], gs)) != hipSuccess) return e;
   return hipStreamWaitEvent(st, ms->gev[1], 0);
@@ -1160,6 +1201,7 @@ void ms_release(MsDev* ms) {
 
 void ms_free_all(MsDev* ms) {
   ms_release(ms);
+  ms_graph_destroy(ms);
   if (ms->gstream) (void)hipStreamDestroy(ms->gstream);
   for (int i = 0; i < 2; ++i)
     if (ms->gev[i]) (void)hipEventDestroy(ms->gev[i]);

@@ -246,6 +246,9 @@ def test_msbfs_graph_mode(blest, name):
     assert np.array_equal(s.cpu().numpy(), osum)
     assert np.array_equal(r.cpu().numpy(), oreach)
     assert np.array_equal(c.cpu().numpy(), occ)
+    # one captured graph served every call: each policy's, and closeness with
+    # its different outputs (these policies share the kernel and LDS size)
+    assert g.info()["ms_graph_captures"] == 1
     g.close()
 
 
