@@ -406,10 +406,11 @@ blest_status blest_build(const blest_csr* csr, const blest_opts* opts_in, blest_
   d.mark_bytes = mark_bytes;
   if (pn.npanels > 0) {
     TRY(dalloc_t(g, &d.pwords, pn.words.size()));
-    TRY(dalloc_t(g, &d.pbase, pn.base.size()));
+    TRY(dalloc_t(g, &d.pbase, pn.base.size() + blest::kPanelBasePad));
     TRY(dalloc_t(g, &d.pptr, pn.ptr.size()));
     TRY(hipMemcpy(d.pwords, pn.words.data(), 4 * pn.words.size(), hipMemcpyHostToDevice));
     TRY(hipMemcpy(d.pbase, pn.base.data(), 4 * pn.base.size(), hipMemcpyHostToDevice));
+    TRY(hipMemset(d.pbase + pn.base.size(), 0, 4 * blest::kPanelBasePad));
     TRY(hipMemcpy(d.pptr, pn.ptr.data(), 4 * pn.ptr.size(), hipMemcpyHostToDevice));
   }
   TRY(dalloc_t(g, &d.queue[2], static_cast<size_t>(std::max<int64_t>(b.nvss, 1))));

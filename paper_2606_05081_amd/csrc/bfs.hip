@@ -311,6 +311,7 @@ __device__ long long engine_bvss(const BfsArgs& a, const uint4* __restrict__ q, 
 // single-workgroup hash set shares it).
 constexpr int kPanelChunk = 256;      // slices per chunk (host layout)
 constexpr int kPanelUnroll = 8;       // chunks per wave per batch
+static_assert(kPanelUnroll <= kPanelBasePad, "batch bases are read past the last chunk");
 constexpr int kPanelMaxBytes = 1 << 15;  // LDS byte map of one panel (rb <= 15)
 static_assert(kSingleHash * 4 >= kPanelMaxBytes, "the panel byte map lives in the hash-set slots");
 constexpr long long kPanelDenom = 8;  // dense: queued slices >= panel slots / 8
@@ -324,7 +325,7 @@ __device__ __forceinline__ bool use_panel(const BfsArgs& a, const LevelView& v) 
 struct PanelPtrs {
   gptr<const uint4> words;    // 64 uint4 per chunk
   gptr<const uint2> front8;   // 8 frontier bytes per element
-  gptr<const uint32_t> base;  // first set of each chunk
+  cptr<const uint32_t> base;  // first set of each chunk (read-only: scalar loads)
 };
 
 // Loads chunk c (clamped to the panel's last chunk `cl`, so every load is in
@@ -353,6 +354,53 @@ __device__ __forceinline__ void panel_test4(const uint4& w, uint32_t b7, const u
   for (int q = 0; q < 4; ++q) {
     const uint32_t al = (((d[q] >> 2) & 1u) ? hi[q] : lo[q]) >> (8u * (d[q] & 3u));
     if (s[q] & al & 0xffu) reinterpret_cast<lptr<uint8_t>>(pm)[s[q] >> rshift] = 1;
+  }
+}
+
+// One batch of kPanelUnroll chunks in registers: each chunk's base set, this
+// lane's 4 slice words and its 8 bytes of the chunk's frontier window; bit u
+// of `valid` (wave-uniform) is set if chunk u lies in the panel.
+struct PanelBatch {
+  uint32_t b[kPanelUnroll];
+  uint4 w[kPanelUnroll];
+  uint2 f[kPanelUnroll];
+  uint32_t valid;
+};
+
+// Bases of the chunks min(c, cl) .. min(c, cl) + U - 1 by scalar loads (c and
+// cl wave-uniform; cl = the panel's last chunk). The base array is padded
+// with kPanelBasePad zeros, so these loads stay in bounds and a base read
+// past the last chunk is set 0, whose window is in bounds too.
+__device__ __forceinline__ void panel_bases(const PanelPtrs& pp, uint32_t c, uint32_t cl,
+                                            uint32_t (&x)[kPanelUnroll]) {
+  const cptr<const uint32_t> b = pp.base + min(c, cl);
+#pragma unroll
+  for (int u = 0; u < kPanelUnroll; ++u) x[u] = b[u];
+}
+
+// Issues the slice and window loads of the batch starting at chunk c, whose
+// bases panel_bases read into x. A chunk past cl loads chunk cl's words
+// (in bounds) and is left out of the test by `valid`.
+__device__ __forceinline__ void panel_issue(const PanelPtrs& pp, PanelBatch& B, uint32_t c, uint32_t cl,
+                                            uint32_t lane, const uint32_t (&x)[kPanelUnroll]) {
+  B.valid = c > cl ? 0u : (cl - c >= kPanelUnroll - 1 ? (1u << kPanelUnroll) - 1u : (2u << (cl - c)) - 1u);
+#pragma unroll
+  for (int u = 0; u < kPanelUnroll; ++u) {
+    B.b[u] = x[u];
+    panel_load(pp, c + u, cl, lane, x[u], B.w[u], B.f[u]);
+  }
+}
+
+// Tests the chunks of a batch as straight-line code: a chunk outside the
+// panel gets an all-zero frontier window, so it hits nothing. With no branch
+// in the test, every path to the next batch's loads has waited for exactly
+// this batch's loads and no later ones.
+__device__ __forceinline__ void panel_test_batch(const PanelBatch& B, uint32_t dmask, int rshift, lptr<uint32_t> pm) {
+#pragma unroll
+  for (int u = 0; u < kPanelUnroll; ++u) {
+    const bool in = (B.valid >> u) & 1u;
+    const uint2 f = make_uint2(in ? B.f[u].x : 0u, in ? B.f[u].y : 0u);
+    panel_test4(B.w[u], B.b[u] & 7u, f, dmask, rshift, pm);
   }
 }
 
@@ -421,7 +469,7 @@ __device__ __attribute__((noinline)) long long engine_panel(const BfsArgs& a, lp
   PanelPtrs pp;
   pp.words = to_global(reinterpret_cast<const uint4*>(a.pwords));
   pp.front8 = to_global(static_cast<const uint2*>(front_buf(a, sel)));
-  pp.base = to_global(static_cast<const uint32_t*>(a.pbase));
+  pp.base = to_const_uniform(static_cast<const uint32_t*>(a.pbase));
   const gptr<const uint32_t> pptr = to_global(static_cast<const uint32_t*>(a.pptr));
   const gptr<uint32_t> vis32 = to_global(static_cast<uint32_t*>(a.vis));
   const gptr<uint32_t> next32 = to_global(static_cast<uint32_t*>(front_buf(a, sel ^ 1)));
@@ -437,52 +485,52 @@ __device__ __attribute__((noinline)) long long engine_panel(const BfsArgs& a, lp
   for (int p = blockIdx.x; p < npanels; p += gridDim.x) {
     for (uint32_t j = threadIdx.x; j < 2 * W; j += BLOCK) pm16[j] = u32x4{0u, 0u, 0u, 0u};
     __syncthreads();
-    const uint32_t c0 = pptr[p], c1 = pptr[p + 1];
+    // the chunk range is wave-uniform: scalar registers and scalar branches
+    const uint32_t c0 = __builtin_amdgcn_readfirstlane(pptr[p]);
+    const uint32_t c1 = __builtin_amdgcn_readfirstlane(pptr[p + 1]);
     const uint32_t cl = c1 - 1;  // used only when the panel has a chunk (c < c1)
-    uint32_t c = c0 + wv * U;
+    uint32_t c = c0 + __builtin_amdgcn_readfirstlane(wv) * U;
     if (c < c1) {
-      // Software pipeline over batches of U chunks. The bases of a batch are
-      // one vector load (lane u holds chunk c+u's) issued before the previous
-      // batch's slice and window loads, so reading them never waits for the
-      // slices; while batch k is tested, batch k+1's slices and windows and
-      // batch k+2's bases are in flight.
-      uint32_t bv = pp.base[min(c + lane % U, cl)];
-      uint32_t b[U];
-      uint4 w[U];
-      uint2 f[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) b[u] = __builtin_amdgcn_readlane(bv, u);
-      bv = pp.base[min(c + STEP + lane % U, cl)];
-#pragma unroll
-      for (int u = 0; u < U; ++u) panel_load(pp, c + u, cl, lane, b[u], w[u], f[u]);
-      for (;;) {
-        const uint32_t cn = c + STEP;
-        uint32_t bn[U];
-        uint4 wn[U];
-        uint2 fn[U];
-        const bool more = cn < c1;
-        if (more) {
-#pragma unroll
-          for (int u = 0; u < U; ++u) bn[u] = __builtin_amdgcn_readlane(bv, u);
-          bv = pp.base[min(cn + STEP + lane % U, cl)];
-#pragma unroll
-          for (int u = 0; u < U; ++u) panel_load(pp, cn + u, cl, lane, bn[u], wn[u], fn[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (c + u >= c1) break;
-          panel_test4(w[u], b[u] & 7u, f[u], dmask, rshift, pm);
-          work += kPanelChunk;
-        }
-        if (!more) break;
-        c = cn;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          b[u] = bn[u];
-          w[u] = wn[u];
-          f[u] = fn[u];
-        }
+      // Software pipeline over batches of U chunks in two register sets used
+      // in turn: batch k+1 is issued into one set before batch k is tested
+      // from the other, so the test waits only for batch k's loads. (A copy
+      // from a "next" set into a "current" one would wait for the batch in
+      // flight.) The bases of a batch are one vector load, issued a batch
+      // ahead and before the slice and window loads it precedes.
+      // A counted loop with its exit at the bottom and loads issued
+      // unconditionally (past the end they read the clamped last chunk), so
+      // the wait before each test is the same on every path: the batch
+      // tested has landed while the one issued after it is still in flight.
+      // The wave's batches start at c, c + STEP, ...; nb of them hold chunks.
+      const uint32_t nb = (c1 - c + STEP - 1) / STEP;
+      PanelBatch A, B;
+      uint32_t bn[U];
+      work += static_cast<long long>(kPanelChunk) * ((nb - 1) * U + min(U, c1 - c - (nb - 1) * STEP));
+      // (the scheduling barriers keep each batch's loads together and in
+      // this order, so the wait counts below are the same on every path)
+      panel_bases(pp, c, cl, bn);
+      __builtin_amdgcn_sched_barrier(0);
+      panel_issue(pp, A, c, cl, lane, bn);
+      panel_bases(pp, c + STEP, cl, bn);
+      __builtin_amdgcn_sched_barrier(0);
+      panel_issue(pp, B, c + STEP, cl, lane, bn);
+      panel_bases(pp, c + 2 * STEP, cl, bn);
+      __builtin_amdgcn_sched_barrier(0);
+      uint32_t k = 0;
+      for (; k + 2 < nb; k += 2) {
+        panel_test_batch(A, dmask, rshift, pm);
+        __builtin_amdgcn_sched_barrier(0);
+        panel_issue(pp, A, c + (k + 2) * STEP, cl, lane, bn);
+        panel_bases(pp, c + (k + 3) * STEP, cl, bn);
+        __builtin_amdgcn_sched_barrier(0);
+        panel_test_batch(B, dmask, rshift, pm);
+        __builtin_amdgcn_sched_barrier(0);
+        panel_issue(pp, B, c + (k + 3) * STEP, cl, lane, bn);
+        panel_bases(pp, c + (k + 4) * STEP, cl, bn);
+        __builtin_amdgcn_sched_barrier(0);
       }
+      panel_test_batch(A, dmask, rshift, pm);
+      if (k + 1 < nb) panel_test_batch(B, dmask, rshift, pm);
     }
     __syncthreads();
     const size_t wb = static_cast<size_t>(p) * W;
@@ -737,12 +785,16 @@ __device__ __forceinline__ void run_engine(const BfsArgs& a, int engine, int sel
 // prefix sums, so a hub set with thousands of VSSs costs a few wave steps.
 enum FinMode : int { FIN_ATOMIC = 0, FIN_LOCAL = 1, FIN_COUNT = 2, FIN_EMIT = 3 };
 
+// Slice sets per thread in one window of the Stage 2 sweep (a window is
+// BLOCK * kFinSpt consecutive sets); their loads are issued together.
+constexpr int kFinSpt = 4;
+
 template <int SIGMA, int BLOCK, int MODE, class SetAt>
 __device__ void finalize_windows(const BfsArgs& a, int new_level, gptr<unsigned long long> acc, int sel_out,
                                  long long win0, long long nwin, long long wstep, SetAt set_at, long long (&st)[8],
                                  unsigned long long* local, bool want_push = true, bool want_queue = true) {
   using M = typename MaskOf<SIGMA>::T;
-  constexpr int SPT = 2;
+  constexpr int SPT = kFinSpt;
   constexpr bool UPDATE = MODE != FIN_EMIT;
   __shared__ int lds32[3 * (BLOCK / 64)];
   __shared__ unsigned long long bases[3];
@@ -825,7 +877,13 @@ __device__ void finalize_windows(const BfsArgs& a, int new_level, gptr<unsigned 
       }
     }
     if constexpr (MODE == FIN_COUNT) continue;
-    int cnt[3] = {nl[0] + nl[1], nh[0] + nh[1], nq[0] + nq[1]};
+    int cnt[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+      cnt[0] += nl[k];
+      cnt[1] += nh[k];
+      cnt[2] += nq[k];
+    }
     if (!__syncthreads_or(cnt[0] | cnt[1] | cnt[2])) continue;
     int ex[3], tot[3];
     block_exclusive_scan<BLOCK, 3>(cnt, ex, tot, lds32);
@@ -950,7 +1008,7 @@ __device__ void finalize_stats(gptr<unsigned long long> acc, const long long (&s
 template <int SIGMA, int BLOCK>
 __device__ void finalize(const BfsArgs& a, int new_level, int slot_out, int sel_out, long long cumv_in,
                          long long cume_in, unsigned nblocks) {
-  constexpr long long WIN = static_cast<long long>(BLOCK) * 2;
+  constexpr long long WIN = static_cast<long long>(BLOCK) * kFinSpt;
   const gptr<unsigned long long> acc = to_global(&a.ctl->acc[slot_out][0][0]);
   long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // frontier, queued slices, frontier edges, deg>=32, deg>=1024
   const long long nsets = a.nsets;
@@ -982,7 +1040,7 @@ __device__ void finalize(const BfsArgs& a, int new_level, int slot_out, int sel_
 // slot `slot_out`); either way the level statistics go to the partials.
 template <int SIGMA, int BLOCK, int MODE>
 __device__ void finalize_count(const BfsArgs& a, int new_level, int slot_out, int sel_out) {
-  constexpr long long WIN = static_cast<long long>(BLOCK) * 2;
+  constexpr long long WIN = static_cast<long long>(BLOCK) * kFinSpt;
   __shared__ long long lds64[kParts * (BLOCK / 64)];
   long long st[kParts] = {0, 0, 0, 0, 0, 0, 0, 0};
   const long long nsets = a.nsets;
@@ -1041,7 +1099,7 @@ __device__ void reduce_parts(const BfsArgs& a, long long (&tot)[kParts], long lo
 template <int SIGMA, int BLOCK>
 __device__ void finalize_emit(const BfsArgs& a, int sel_out, const long long (&before)[3], bool want_push,
                               bool want_queue, bool panel_part) {
-  constexpr long long WIN = static_cast<long long>(BLOCK) * 2;
+  constexpr long long WIN = static_cast<long long>(BLOCK) * kFinSpt;
   __shared__ unsigned long long cursor[3];
   if (threadIdx.x < 3) cursor[threadIdx.x] = static_cast<unsigned long long>(before[threadIdx.x]);
   __syncthreads();
@@ -1099,7 +1157,7 @@ __device__ __forceinline__ bool single_eligible(const BfsArgs& a, int engine, co
 template <int SIGMA, int BLOCK>
 __device__ void finalize_list(const BfsArgs& a, int new_level, int slot_out, int sel_out, long long cumv_in,
                               long long cume_in, lptr<int> hs) {
-  constexpr int WIN = BLOCK * 2;
+  constexpr int WIN = BLOCK * kFinSpt;
   __shared__ unsigned long long local[3];
   __shared__ long long lds64[5 * (BLOCK / 64)];
   const gptr<unsigned long long> acc = to_global(&a.ctl->acc[slot_out][0][0]);

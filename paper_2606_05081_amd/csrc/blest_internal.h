@@ -25,6 +25,11 @@
 
 namespace blest {
 
+// Entries past the last chunk base of the panel copy, so that a wave may read
+// the bases of a whole batch of consecutive chunks with scalar loads.
+constexpr int kPanelBasePad = 8;
+
+
 constexpr int kStatFields = 12;     // accumulated by Stage 2, one 256-byte line each
 constexpr int kStatSlots = 3;       // rotating per-level slots
 constexpr int kPad = 32;            // 32 x 8 bytes = 256 bytes
@@ -142,7 +147,7 @@ struct BfsArgs {
   int32_t single_block;  // run small levels on workgroup 0 alone
   // panel-blocked BVSS copy (sigma = 8, 32-bit slices); npanels = 0 if absent
   const uint32_t* pwords;  // nchunks * 64 slice words
-  const uint32_t* pbase;   // first set of each chunk
+  const uint32_t* pbase;   // first set of each chunk (+ kPanelBasePad entries of padding)
   const uint32_t* pptr;    // npanels + 1 chunk offsets
   int32_t npanels;
   int32_t panel_rb;        // log2 rows per panel

@@ -50,20 +50,37 @@ __device__ __forceinline__ int lane_id() { return static_cast<int>(threadIdx.x &
 // (The host pass of the single-source compile only parses device code; there
 // the qualifiers are dropped, since x86 has no generic address space that
 // contains them.)
+// cptr<T> points into the constant address space: memory no kernel writes
+// while it runs, whose wave-uniform loads become scalar loads (waited on with
+// the LDS/scalar counter instead of the vector-load counter).
 #if defined(__HIP_DEVICE_COMPILE__)
 template <class T>
 using gptr = __attribute__((address_space(1))) T*;
 template <class T>
 using lptr = __attribute__((address_space(3))) T*;
+template <class T>
+using cptr = __attribute__((address_space(4))) T*;
 #else
 template <class T>
 using gptr = T*;
 template <class T>
 using lptr = T*;
+template <class T>
+using cptr = T*;
 #endif
 template <class T>
 __device__ __forceinline__ gptr<T> to_global(T* p) {
   return (gptr<T>)p;
+}
+// A pointer the caller knows to be the same in every lane, made wave-uniform
+// for the compiler (a pointer read through a function argument is not), so
+// that loads through it with uniform indices can be scalar loads.
+template <class T>
+__device__ __forceinline__ cptr<T> to_const_uniform(T* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return (cptr<T>)reinterpret_cast<T*>((static_cast<unsigned long long>(hi) << 32) | lo);
 }
 typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
