@@ -41,6 +41,14 @@ namespace {
 
 constexpr int kWMax = 8;  // up to 512 sources per batch
 
+// LDS words per wave for the top-down engine: the frontier words of one slice
+// set (sigma * W), and for sigma = 8 also two 16-entry nibble tables per word
+// (32 * W).
+template <int SIGMA>
+constexpr int ms_lds_words() {
+  return (SIGMA == 8 ? SIGMA + 32 : SIGMA) * kWMax;
+}
+
 struct MsBatch {
   int32_t offset;  // first source index of the batch in the call's source list
   int32_t count;   // sources in the batch (<= 64 * W)
@@ -273,6 +281,102 @@ __device__ void ms_engine_bvss_k(const MsArgs& a, const uint4* __restrict__ q, l
   }
 }
 
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long x, int l) {
+  const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(x), l);
+  const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(x >> 32), l);
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+// The sigma = 8 form of the engine above, shaped for memory latency. Per VSS
+// the slices, the set's frontier words and its activity words are loaded
+// together. The frontier words are staged in LDS and expanded into two
+// 16-entry tables per word w: lo[i] = OR of the words of the vertices in bit
+// subset i of bits 0..3, hi[i] the same for bits 4..7, so a slice's
+// neighbour word for w is lo[mask & 15] | hi[mask >> 4] (two LDS reads, where
+// the bit loop took up to eight dependent ones). Then, word by word, the
+// visited words of all the lane's K slices are loaded at once before any is
+// used. LDS layout per wave: F at [b * W + w], tables at
+// [8 W + (h * 16 + i) * W + w].
+// (Not inlined: it gets its own register allocation instead of adding to the
+// persistent kernel's; its pointers are converted to the global address space.)
+template <class SliceT, int K, int ABL>
+__device__ __attribute__((noinline)) void ms_engine_bvss8(const MsArgs& a, const uint4* q_in, long long qlen, int W,
+                                                          long long gwave, long long nwaves,
+                                                          unsigned long long* lds_in) {
+  constexpr int SIGMA = 8;
+  const gptr<const SliceT> sl = to_global(static_cast<const SliceT*>(a.slices));
+  const gptr<const uint4> q = to_global(q_in);
+  const gptr<const unsigned long long> F = to_global(static_cast<const unsigned long long*>(a.F));
+  const gptr<const unsigned long long> V = to_global(static_cast<const unsigned long long*>(a.V));
+  const gptr<const unsigned long long> act = to_global(static_cast<const unsigned long long*>(a.act));
+  const gptr<unsigned long long> N = to_global(a.N);
+  const gptr<uint8_t> dirty = to_global(a.dirty);
+  const lptr<unsigned long long> lds = to_lds(lds_in);
+  const long long rho = a.nsets;
+  const int lane = lane_id();
+  const lptr<unsigned long long> tab = lds + SIGMA * W;
+  for (long long i = gwave; i < qlen; i += nwaves) {
+    const uint4 d = q[i];
+    const uint32_t start = d.x, cnt = d.y;
+    const long long s = d.w;
+    SliceT sv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const uint32_t j = static_cast<uint32_t>(lane) + 64u * k;
+      sv[k] = (j < cnt) ? sl[start + j] : SliceT(0);
+    }
+    unsigned long long fw = 0ULL, aw = 0ULL;
+    if (lane < SIGMA * W) fw = F[ms_vi<ABL>(a, s * SIGMA + lane / W, rho, SIGMA) * W + lane % W];
+    if (lane < W) aw = act[s * W + lane];
+    if (lane < SIGMA * W) lds[lane] = fw;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int e = lane; e < 32 * W; e += 64) {
+      const int w = e % W, t = e / W;
+      const int h = t >> 4, sub = t & 15;
+      unsigned long long x = 0ULL;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if ((sub >> b) & 1) x |= lds[(4 * h + b) * W + w];
+      tab[e] = x;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    long long vi[K];
+    uint32_t m8[K];
+    bool any[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      m8[k] = static_cast<uint32_t>(sv[k] & SliceT(0xff));
+      vi[k] = ms_vi<ABL>(a, static_cast<long long>(sv[k] >> SliceFmt<SliceT>::kRowShift), rho, SIGMA);
+      any[k] = false;
+    }
+    for (int w = 0; w < W; ++w) {
+      if (!readlane64(aw, w)) continue;
+      unsigned long long mw[K], v[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        mw[k] = m8[k] ? (tab[(m8[k] & 15u) * W + w] | tab[(16u + (m8[k] >> 4)) * W + w]) : 0ULL;
+#pragma unroll
+      for (int k = 0; k < K; ++k) v[k] = mw[k] ? V[vi[k] * W + w] : ~0ULL;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const unsigned long long m = mw[k] & ~v[k];
+        if (m) {
+          __hip_atomic_fetch_or(&N[vi[k] * W + w], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          any[k] = true;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (any[k]) dirty[(sv[k] >> SliceFmt<SliceT>::kRowShift) / SIGMA] = 1;
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // The same neighbour check as an int8 matrix product on the matrix cores (an
 // experiment kept behind opts.ms_mfma; sigma = 8 only). For 16 slices of a VSS
 // and 16 traversals c, C = A B with A[i][b] = bit b of slice i's mask and
@@ -360,6 +464,23 @@ __device__ void ms_engine_bvss(const MsArgs& a, const uint4* q, long long qlen, 
                                long long nwaves, unsigned long long* lds_f) {
   if constexpr (MF && SIGMA == 8) {
     ms_engine_mfma<SliceT, ABL>(a, q, qlen, W, gwave, nwaves, lds_f);
+    return;
+  }
+  if constexpr (SIGMA == 8) {
+    switch (a.tau) {
+      case 64:
+        ms_engine_bvss8<SliceT, 1, ABL>(a, q, qlen, W, gwave, nwaves, lds_f);
+        break;
+      case 128:
+        ms_engine_bvss8<SliceT, 2, ABL>(a, q, qlen, W, gwave, nwaves, lds_f);
+        break;
+      case 192:
+        ms_engine_bvss8<SliceT, 3, ABL>(a, q, qlen, W, gwave, nwaves, lds_f);
+        break;
+      default:
+        ms_engine_bvss8<SliceT, 4, ABL>(a, q, qlen, W, gwave, nwaves, lds_f);
+        break;
+    }
     return;
   }
   switch (a.tau) {
@@ -618,7 +739,7 @@ __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
   constexpr bool MF = MODE == 1;
   constexpr int ABL = MODE >= 10 ? MODE - 10 : 0;
   extern __shared__ float s_mlp[];
-  __shared__ unsigned long long lds_f[(BLOCK / 64) * SIGMA * kWMax];
+  __shared__ unsigned long long lds_f[(BLOCK / 64) * ms_lds_words<SIGMA>()];
   __shared__ int lds_cnt[64 * kWMax];
   const bool learned = a.policy == BLEST_POLICY_LEARNED && a.mlp != nullptr && a.mlp->valid;
   if (learned) mlp_to_lds(a.mlp, s_mlp);
@@ -627,7 +748,7 @@ __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
   const int wave = wave_in_block();
   const long long gwave = static_cast<long long>(blockIdx.x) * (BLOCK / 64) + wave;
   const long long nwaves = static_cast<long long>(gridDim.x) * (BLOCK / 64);
-  unsigned long long* my_f = lds_f + wave * SIGMA * kWMax;
+  unsigned long long* my_f = lds_f + wave * ms_lds_words<SIGMA>();
   const long long rho = a.nsets;
   const long long nhat = a.nsets * SIGMA;
   const bool count_sources = a.sums != nullptr || a.reach != nullptr || a.cc != nullptr;
@@ -762,7 +883,7 @@ template <int SIGMA, class SliceT, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_ms_phase(MsArgs a, int parity) {
   constexpr int ABL = -1;
   extern __shared__ float s_mlp[];
-  __shared__ unsigned long long lds_f[(BLOCK / 64) * SIGMA * kWMax];
+  __shared__ unsigned long long lds_f[(BLOCK / 64) * ms_lds_words<SIGMA>()];
   __shared__ int lds_cnt[64 * kWMax];
   const int phase = a.ctl->ms_state[parity][0];
   const int bi = a.ctl->ms_state[parity][1];
@@ -775,7 +896,7 @@ __global__ void __launch_bounds__(BLOCK) k_ms_phase(MsArgs a, int parity) {
     const int wave = wave_in_block();
     const long long gwave = static_cast<long long>(blockIdx.x) * (BLOCK / 64) + wave;
     const long long nwaves = static_cast<long long>(gridDim.x) * (BLOCK / 64);
-    unsigned long long* my_f = lds_f + wave * SIGMA * kWMax;
+    unsigned long long* my_f = lds_f + wave * ms_lds_words<SIGMA>();
     const long long rho = a.nsets;
     const long long nhat = a.nsets * SIGMA;
     const bool count_sources = a.sums != nullptr || a.reach != nullptr || a.cc != nullptr;
