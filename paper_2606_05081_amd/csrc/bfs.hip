@@ -810,37 +810,108 @@ __device__ void finalize_windows(const BfsArgs& a, int new_level, gptr<unsigned 
   gptr<int32_t> __restrict__ levels = to_global(a.levels);
   const gptr<const int32_t> __restrict__ orig_id = to_global(a.orig_id);
   const int lane = lane_id();
+  const bool need_rp = UPDATE || want_push;
+  const bool need_sp = UPDATE || want_queue;
   for (long long win = win0; win < nwin; win += wstep) {
+    // The SPT sets of a thread are finalised in phases, each issuing the
+    // loads of all SPT sets before any is used (marks; visited words; row and
+    // slice pointers; input ids), so a window costs four dependent memory
+    // round trips rather than four per set.
     M nw[SPT];
     long long sset[SPT];
     int nl[SPT], nh[SPT], nq[SPT];
+    M got[SPT];
 #pragma unroll
     for (int k = 0; k < SPT; ++k) {
       const long long s = set_at(win, k);
       sset[k] = s;
       nw[k] = 0;
       nl[k] = nh[k] = nq[k] = 0;
-      if (s < 0) continue;
-      M x = 0;
-      if constexpr (UPDATE) {
-        const M bits = load_marks<SIGMA>(mark + s * SIGMA);
-        if (bits) {
-          clear_marks<SIGMA>(mark + s * SIGMA);
-          const M old = vis[s];
-          x = static_cast<M>(bits & ~old);
-          if (x) vis[s] = static_cast<M>(old | x);
-        }
+      got[k] = 0;
+      if (s >= 0) {
+        if constexpr (UPDATE)
+          got[k] = load_marks<SIGMA>(mark + s * SIGMA);
+        else
+          got[k] = front[s];
+      }
+    }
+    if constexpr (UPDATE) {
+      M old[SPT];
+#pragma unroll
+      for (int k = 0; k < SPT; ++k) old[k] = got[k] ? vis[sset[k]] : M(0);
+#pragma unroll
+      for (int k = 0; k < SPT; ++k) {
+        const long long s = sset[k];
+        if (s < 0) continue;
+        const M x = static_cast<M>(got[k] & ~old[k]);
+        if (got[k]) clear_marks<SIGMA>(mark + s * SIGMA);
+        if (x) vis[s] = static_cast<M>(old[k] | x);
         if (MODE == FIN_COUNT)
           front[s] = x;
         else if (x)
           front[s] = x;
-      } else {
-        x = front[s];
+        nw[k] = x;
       }
-      if (!x) continue;
-      nw[k] = x;
-      const bool need_rp = UPDATE || want_push;
-      if (need_rp) {
+    } else {
+#pragma unroll
+      for (int k = 0; k < SPT; ++k) nw[k] = got[k];
+    }
+    uint32_t p0[SPT], p1[SPT];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+      p0[k] = p1[k] = 0;
+      if (nw[k] && need_sp) {
+        p0[k] = sp[sset[k]];
+        p1[k] = sp[sset[k] + 1];
+      }
+    }
+    if constexpr (SIGMA == 8) {
+      // eight vertices per set: every set's row pointers and input ids fit
+      // in registers at once
+      int r[SPT][SIGMA + 1];
+#pragma unroll
+      for (int k = 0; k < SPT; ++k)
+        if (nw[k] && need_rp) load_set_rp<SIGMA>(rp, sset[k], r[k]);
+      if constexpr (UPDATE) {
+        int32_t id[SPT][SIGMA];
+#pragma unroll
+        for (int k = 0; k < SPT; ++k)
+#pragma unroll
+          for (int b = 0; b < SIGMA; ++b) {
+            const long long u = sset[k] * SIGMA + b;
+            id[k][b] = ((nw[k] >> b) & 1u) ? (orig_id ? orig_id[u] : static_cast<int32_t>(u)) : 0;
+          }
+#pragma unroll
+        for (int k = 0; k < SPT; ++k)
+#pragma unroll
+          for (int b = 0; b < SIGMA; ++b)
+            if ((nw[k] >> b) & 1u) levels[id[k][b]] = new_level;
+      }
+#pragma unroll
+      for (int k = 0; k < SPT; ++k) {
+        if (!nw[k] || !need_rp) continue;
+#pragma unroll
+        for (int b = 0; b < SIGMA; ++b) {
+          if (!((nw[k] >> b) & 1u)) continue;
+          const int d = r[k][b + 1] - r[k][b];
+          if constexpr (UPDATE) {
+            st[0] += 1;
+            st[2] += d;
+            st[3] += d >= 32;
+            st[4] += d >= 1024;
+          }
+          if (d > kLightMax)
+            nh[k] += (d + kHeavyChunk - 1) / kHeavyChunk;
+          else
+            nl[k] += 1;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < SPT; ++k) {
+        const M x = nw[k];
+        if (!x || !need_rp) continue;
+        const long long s = sset[k];
         int r[SIGMA + 1];
         load_set_rp<SIGMA>(rp, s, r);
 #pragma unroll
@@ -861,8 +932,11 @@ __device__ void finalize_windows(const BfsArgs& a, int new_level, gptr<unsigned 
             nl[k] += 1;
         }
       }
-      if (UPDATE || want_queue) {
-        const uint32_t ns = sp[s + 1] - sp[s];
+    }
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) {
+      if (nw[k] && need_sp) {
+        const uint32_t ns = p1[k] - p0[k];
         nq[k] = static_cast<int>((ns + tau - 1) / tau);
         if constexpr (UPDATE) st[1] += ns;
       }
