@@ -53,31 +53,30 @@ def traversal_edges(rp, levels):
     return int(deg[levels >= 0].sum() // 2)
 
 
-def algorithmic_bytes(stats, n, nsets, sigma, slice_bytes, deg, levels):
-    """Bytes a traversal must move, from its per-level log: init 4n + 2n/8;
-    per step the engine's reads (BVSS over the queue: slice words + 16 B per
-    queued VSS; BVSS over the panel copy: 4 B per slice slot + 4 B per
-    256-slot chunk + the n/8 visited bytes read at the flush; push: 4 B per
-    edge + 12 B per frontier vertex; bottom-up: 4 B per scanned edge + 8 B per
-    unvisited vertex of nonzero degree) and the finalisation (n_hat mark bytes
-    + 12 B per new vertex + 16 B per enqueued VSS + n/4 visited/frontier
-    words)."""
-    total = 4 * n + 2 * n // 8
-    nhat = nsets * sigma
+def algorithmic_bytes(stats, n, sigma, slice_bytes, deg, levels, relabelled):
+    """Bytes a traversal must move, from its per-level log, by these per-unit
+    counts: a top-down step (Alg. 3 Stage 1, queue or panel form) moves the
+    slice word plus the sigma/8 frontier bytes of its set per slice of a
+    queued VSS, and 9 B per queued VSS (its descriptor and frontier word); a
+    bottom-up step 8 B per unvisited vertex of nonzero degree and 4 B per
+    scanned edge; a push step 8 B per frontier vertex and 4 B per edge; each
+    Stage 2 3n/8 B (marks, visited and frontier words) plus 4 B per new vertex
+    and 4 B per enqueued VSS; and a traversal 4n B of initialisation, 4n of
+    levels, and 4n of input ids when the graph was relabelled. Slots of the
+    panel copy outside the queued VSSs are read but not counted."""
+    total = 8 * n + (4 * n if relabelled else 0)
     lev = np.where(levels < 0, np.iinfo(np.int32).max, levels)
     for i, r in enumerate(stats[:-1]):
         eng = r["engine"]
-        if eng == 0 and r.get("bvss_panel"):
-            total += 4 * r["work"] + 4 * (r["work"] // 256) + n // 8
-        elif eng == 0:
-            total += slice_bytes * r["work"] + 16 * r["queue"]
+        if eng == 0:
+            total += (slice_bytes + sigma // 8) * r["queue_slices"] + 9 * r["queue"]
         elif eng == 1:
-            total += 4 * r["work"] + 12 * r["frontier"]
+            total += 4 * r["work"] + 8 * r["frontier"]
         else:
             unv_deg = int(((lev > r["level"]) & (deg > 0)).sum())
             total += 4 * r["work"] + 8 * unv_deg
         nxt = stats[i + 1]
-        total += nhat + 12 * nxt["frontier"] + 16 * nxt["queue"] + n // 4
+        total += 3 * n // 8 + 4 * nxt["frontier"] + 4 * nxt["queue"]
     return int(total)
 
 
@@ -358,16 +357,18 @@ def c3_leg(kind, scale, gseed, sseed, model, eta_tuned, torch, blest, inputs, ns
 
 def ms_algorithmic_bytes(recs, n, nsets, sigma, slice_bytes, k):
     """Lower bound of the bytes a multi-source call must move, from its level
-    records: per level, the queued slices (slice_bytes each), 16 B per queued
-    VSS descriptor and the sigma * kappa / 8 frontier bytes each VSS stages;
-    per new (vertex, traversal-word) the visited, frontier and next words
-    (3 x 8 B, counted once per new pair / 64 as a lower bound); and the int16
-    level of every (source, vertex) pair."""
+    records: per level, (slice word + sigma/8) B per slice of a queued VSS and
+    the sigma * kappa / 8 frontier bytes each queued VSS stages; kappa/8 B per
+    hit row (the next-word flush) and 3 kappa/8 B per dirty vertex (next,
+    visited and frontier words), bounded below by the new (vertex, traversal)
+    pairs, since a vertex has at most kappa of them: new_pairs / 8 and
+    3 new_pairs / 8; and the int16 levels: 2 B per (source, vertex) filled,
+    and 2 B per visited pair written."""
     total = 2 * k * n
     for r in recs:
         kappa = r["width"]
-        total += slice_bytes * r["queue_slices"] + 16 * r["queue"] + sigma * kappa // 8 * r["queue"]
-        total += 24 * ((r["new_pairs"] + 63) // 64)
+        total += (slice_bytes + sigma // 8) * r["queue_slices"] + sigma * kappa // 8 * r["queue"]
+        total += r["new_pairs"] // 2 + 2 * r["new_pairs"]
     return int(total)
 
 
@@ -472,8 +473,8 @@ def main():
         g.sync()
         lev = out.cpu().numpy()
         st = g.level_stats()
-        nb.append(algorithmic_bytes(st, info["n"], info["n_slice_sets"], info["sigma"],
-                                    info["slice_bytes"], deg, lev))
+        nb.append(algorithmic_bytes(st, info["n"], info["sigma"], info["slice_bytes"], deg, lev,
+                                    info["reordered"] != 0))
         for r in st[:-1]:
             if r["engine"] == 0 and r.get("bvss_panel"):
                 pan_b.append(4 * r["work"] + 4 * (r["work"] // 256) + info["n"] // 8)
@@ -492,8 +493,8 @@ def main():
         g.bfs(int(s), out)
         g.sync()
         lev = out.cpu().numpy()
-        nb2.append(algorithmic_bytes(g.level_stats(), info["n"], info["n_slice_sets"], info["sigma"],
-                                     info["slice_bytes"], deg, lev))
+        nb2.append(algorithmic_bytes(g.level_stats(), info["n"], info["sigma"], info["slice_bytes"], deg, lev,
+                                     info["reordered"] != 0))
     sw_ach = float(np.mean(nb2)) / (float(np.mean(heur_t[:8])) * 1e-3) / 1e9
     g.set_log_work(False)
 

@@ -1,10 +1,13 @@
-"""Host-side logic of the learned switch and autotuner (no GPU)."""
+"""Host-side logic of the learned switch, the autotuner and the benchmark's byte
+counts (no GPU)."""
 import json
+import os
 
 import numpy as np
 import pytest
 
 from paper_2606_05081_amd import autotune, switch
+from tests.conftest import ROOT
 
 
 def test_labels_prefer_fastest_and_break_ties_to_eq3():
@@ -109,3 +112,31 @@ def test_update_divergence_host_equals_oracle():
             assert got == pytest.approx(want, rel=1e-12, abs=1e-12), (sigma, tau)
     with pytest.raises(blest.BlestError):
         blest.blest_update_divergence(rp, col, 12, 128)
+
+
+def test_bench_algorithmic_bytes_counts_by_hand():
+    """The per-launch byte count bench.py reports: a two-step traversal on a
+    16-vertex graph, summed by hand from the per-unit counts in its docstring."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    n, sigma = 16, 8
+    deg = np.array([3, 0, 2, 2] + [1] * 12, np.int64)
+    levels = np.array([0, -1, 1, 1] + [2] * 12, np.int32)
+    stats = [
+        # level 0: top-down over 1 VSS of 5 slices
+        {"level": 0, "engine": 0, "frontier": 1, "queue": 1, "queue_slices": 5, "work": 5},
+        # level 1: bottom-up scanning 7 edges
+        {"level": 1, "engine": 2, "frontier": 2, "queue": 3, "queue_slices": 9, "work": 7},
+        {"level": 2, "engine": -1, "frontier": 12, "queue": 2, "queue_slices": 4, "work": 0},
+    ]
+    got = bench.algorithmic_bytes(stats, n, sigma, 4, deg, levels, relabelled=True)
+    init_out_ids = 4 * n + 4 * n + 4 * n
+    step0 = 5 * 5 + 9 * 1                      # (4 + 1) B per slice + 9 B per VSS
+    fin0 = 3 * n // 8 + 4 * 2 + 4 * 3          # Stage 2 into level 1: 2 new vertices, 3 VSSs
+    unv_deg_after_1 = 12                        # vertices with level > 1 and degree > 0
+    step1 = 4 * 7 + 8 * unv_deg_after_1
+    fin1 = 3 * n // 8 + 4 * 12 + 4 * 2
+    assert got == init_out_ids + step0 + fin0 + step1 + fin1
+    assert bench.algorithmic_bytes(stats, n, sigma, 4, deg, levels, relabelled=False) == got - 4 * n
