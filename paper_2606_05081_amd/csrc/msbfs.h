@@ -20,6 +20,12 @@ struct MsDev {
   unsigned long long* V = nullptr;   // visited words
   unsigned long long* N = nullptr;   // next marks (atomic OR targets)
   unsigned long long* act = nullptr; // per slice set: sources active in it
+  // int16 level output: a batch's levels are first written by internal id
+  // (lstage[i * 64 W + c], the row of vertex i) and copied to the caller's
+  // source-major rows once the batch is done; perm: input id -> internal id
+  int16_t* lstage = nullptr;
+  int64_t lstage_elems = 0;
+  int32_t* perm = nullptr;
   uint8_t* dirty = nullptr;          // per slice set: marked in Stage 1
   uint4* queue[2] = {nullptr, nullptr};
   int32_t* srcs = nullptr;           // internal ids of all sources of a call

@@ -76,6 +76,8 @@ struct MsArgs {
   const MsBatch* batches;
   int32_t nbatches;
   int16_t* levels16;  // k * n or NULL
+  int16_t* lstage;    // the batch's levels by internal id (n * 64 W), or NULL: Stage 2 writes levels16 directly
+  const int32_t* perm;  // input id -> internal id, or NULL when not relabelled
   int64_t* sums;      // k or NULL
   int64_t* reach;     // k or NULL
   double* cc;         // k or NULL
@@ -573,6 +575,44 @@ struct MsExpandRec {
   unsigned long long out;
   uint32_t n, s0, ns, s;
 };
+// Copies a finished batch's staged levels to the caller's rows:
+// levels16[(offset + c) * n + v] = level of input vertex v in traversal c, -1
+// if the traversal did not reach it. Thread t handles input ids v = t, t +
+// nthreads, ...: for each traversal the wave's 64 stores are consecutive, and
+// each lane reads its vertex's staging row 16 bytes at a time. Visited bits
+// come from V (getVI order), so unreached pairs need no staged value.
+template <int SIGMA, int ABL>
+__device__ __attribute__((noinline)) void ms_copy_levels(const MsArgs& a, const MsBatch& bt, long long gtid,
+                                                         long long nthreads) {
+  const int W = bt.W;
+  const long long K = 64LL * W;
+  const long long n = a.n;
+  const long long rho = a.nsets;
+  const int count = bt.count;
+  int16_t* out = a.levels16 + static_cast<long long>(bt.offset) * n;
+  for (long long v = gtid; v < n; v += nthreads) {
+    const long long i = a.perm ? a.perm[v] : v;
+    const long long vi = ms_vi<ABL>(a, i, rho, SIGMA);
+    const uint4* row = reinterpret_cast<const uint4*>(a.lstage + i * K);
+    for (int w = 0; w < W && 64 * w < count; ++w) {
+      const unsigned long long vis = a.V[vi * W + w];
+      for (int j = 0; j < 8 && 64 * w + 8 * j < count; ++j) {
+        const uint32_t bits = static_cast<uint32_t>(vis >> (8 * j)) & 0xffu;
+        uint4 q = make_uint4(0u, 0u, 0u, 0u);
+        if (bits) q = row[8 * w + j];
+        const uint32_t h[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int c = 64 * w + 8 * j + e;
+          if (c >= count) break;
+          const int16_t lv = static_cast<int16_t>((h[e / 2] >> (16 * (e % 2))) & 0xffffu);
+          out[static_cast<long long>(c) * n + v] = ((bits >> e) & 1u) ? lv : static_cast<int16_t>(-1);
+        }
+      }
+    }
+  }
+}
+
 constexpr int kMsExpandMin = 8;
 constexpr int kMsMaxExpand = 128;
 
@@ -639,9 +679,24 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
           A_any |= Aw;
           if (Aw & ~lds_live[w])
             __hip_atomic_fetch_or(&lds_live[w], Aw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          // int16 levels: for each traversal c with new vertices in this set,
-          // write the set's vertices (8 contiguous int16 when not reordered).
-          if (a.levels16 && Aw && !overflow) {
+          // int16 levels. Staged: each new (vertex, traversal) pair goes to
+          // the vertex's staging row; the set's sigma rows are contiguous, so
+          // these stores stay within a few lines. Direct (no staging buffer):
+          // for each traversal c with new vertices in this set, the set's
+          // vertices in c's output row (scattered when relabelled).
+          if (a.lstage && Aw && !overflow) {
+            const long long K = 64LL * W;
+#pragma unroll
+            for (int b = 0; b < SIGMA; ++b) {
+              unsigned long long t = dw[b];
+              int16_t* row = a.lstage + (s * SIGMA + b) * K + 64 * w;
+              while (t) {
+                const int c = __builtin_ctzll(t);
+                t &= t - 1;
+                row[c] = static_cast<int16_t>(new_level);
+              }
+            }
+          } else if (a.levels16 && Aw && !overflow) {
             unsigned long long t = Aw;
             while (t) {
               const int c = __builtin_ctzll(t);
@@ -788,8 +843,8 @@ __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
       a.F[i] = 0ULL;
       a.V[i] = 0ULL;
     }
-    if (a.levels16) fill_minus_one(a.levels16 + static_cast<long long>(bt.offset) * a.n,
-                                   static_cast<long long>(bt.count) * a.n, gtid, nthreads);
+    if (a.levels16 && !a.lstage) fill_minus_one(a.levels16 + static_cast<long long>(bt.offset) * a.n,
+                                                static_cast<long long>(bt.count) * a.n, gtid, nthreads);
     if (count_sources) {
       long long* part = a.part + static_cast<long long>(blockIdx.x) * (2 * 64 * kWMax);
       for (int c = threadIdx.x; c < 2 * 64 * kWMax; c += BLOCK) part[c] = 0;
@@ -863,6 +918,7 @@ __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
       if (!grid_barrier(a.ctl, bc)) return;
       total_levels = max(total_levels, level + 1);
     }
+    if (a.lstage && a.ctl->error[0] == 0) ms_copy_levels<SIGMA, ABL>(a, bt, gtid, nthreads);
     if (count_sources) {
       // reduce the block partials of this batch
       for (long long c = gtid; c < bt.count; c += nthreads) {
@@ -933,8 +989,8 @@ __global__ void __launch_bounds__(BLOCK) k_ms_phase(MsArgs a, int parity) {
           a.F[i] = 0ULL;
           a.V[i] = 0ULL;
         }
-        if (a.levels16) fill_minus_one(a.levels16 + static_cast<long long>(bt.offset) * a.n,
-                                       static_cast<long long>(bt.count) * a.n, gtid, nthreads);
+        if (a.levels16 && !a.lstage) fill_minus_one(a.levels16 + static_cast<long long>(bt.offset) * a.n,
+                                                    static_cast<long long>(bt.count) * a.n, gtid, nthreads);
         if (count_sources) {
           long long* part = a.part + static_cast<long long>(blockIdx.x) * (2 * 64 * kWMax);
           for (int q = threadIdx.x; q < 2 * 64 * kWMax; q += BLOCK) part[q] = 0;
@@ -1013,6 +1069,7 @@ __global__ void __launch_bounds__(BLOCK) k_ms_phase(MsArgs a, int parity) {
         break;
       }
       default:  // MS_END
+        if (a.lstage && a.ctl->error[0] == 0) ms_copy_levels<SIGMA, ABL>(a, bt, gtid, nthreads);
         if (count_sources) {
           for (long long q = gtid; q < bt.count; q += nthreads) {
             long long su = 0, re = 0;
@@ -1197,6 +1254,8 @@ MsArgs ms_args(const DevGraph& g, const MsDev* ms, const int32_t* srcs_dev, cons
   a.batches = batches_dev;
   a.nbatches = nplan;
   a.levels16 = levels16;
+  a.lstage = levels16 ? ms->lstage : nullptr;
+  a.perm = ms->perm;
   a.sums = sums;
   a.reach = reach;
   a.cc = cc;
@@ -1219,6 +1278,35 @@ MsArgs ms_args(const DevGraph& g, const MsDev* ms, const int32_t* srcs_dev, cons
 
 }  // namespace
 
+__global__ void k_ms_perm(const int32_t* __restrict__ orig_id, int64_t n, int32_t* __restrict__ perm) {
+  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    perm[orig_id[i]] = static_cast<int32_t>(i);
+}
+
+// Staging rows for the int16 level output of batches up to 64 * wmax wide,
+// and (for a relabelled graph) the input -> internal id map they are read
+// back through.
+hipError_t ensure_levels(const DevGraph& g, MsDev* ms, int wmax, hipStream_t st) {
+  const int64_t need = g.n * 64 * static_cast<int64_t>(wmax);
+  hipError_t e;
+  if (ms->lstage_elems < need) {
+    if (ms->lstage) (void)hipFree(ms->lstage);
+    ms->lstage = nullptr;
+    ms->lstage_elems = 0;
+    if ((e = hipMalloc(&ms->lstage, sizeof(int16_t) * static_cast<size_t>(need))) != hipSuccess) return e;
+    ms->lstage_elems = need;
+  }
+  if (g.orig_id && !ms->perm) {
+    if ((e = hipMalloc(&ms->perm, sizeof(int32_t) * static_cast<size_t>(std::max<int64_t>(g.n, 1)))) != hipSuccess)
+      return e;
+    hipLaunchKernelGGL(k_ms_perm, dim3(static_cast<unsigned>(std::min<int64_t>((g.n + 255) / 256, 4096))),
+                       dim3(256), 0, st, g.orig_id, g.n, ms->perm);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, const int32_t* widths, int nwidths,
                   int policy, float eta, uint64_t seed, int16_t* levels16, int64_t* sums, int64_t* reach, double* cc,
                   hipStream_t st, int graph, int64_t* far, int probe) {
@@ -1236,6 +1324,7 @@ hipError_t ms_run(const DevGraph& g, MsDev* ms, const int32_t* srcs, int32_t k, 
   for (int i = 0; i < nplan; ++i) wmax = std::max(wmax, plan[i].W);
   hipError_t e = ensure(g, ms, wmax, k, nplan);
   if (e != hipSuccess) return e;
+  if (levels16 && (e = ensure_levels(g, ms, wmax, st)) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(ms->srcs, srcs, sizeof(int32_t) * k, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
   if ((e = hipMemcpyAsync(ms->batches, plan.data(), sizeof(MsBatch) * nplan, hipMemcpyHostToDevice, st)) !=
       hipSuccess)
@@ -1341,6 +1430,11 @@ void ms_release(MsDev* ms) {
   ms->queue[0] = ms->queue[1] = nullptr;
   ms->wmax = 0;
   ms->nhat = 0;
+  if (ms->lstage) (void)hipFree(ms->lstage);
+  if (ms->perm) (void)hipFree(ms->perm);
+  ms->lstage = nullptr;
+  ms->lstage_elems = 0;
+  ms->perm = nullptr;
 }
 
 void ms_free_all(MsDev* ms) {
@@ -1442,6 +1536,9 @@ hipError_t ms_run_noalloc(const DevGraph& g, MsDev* ms, const int32_t* srcs, con
   if ((e = hipMemcpyAsync(dplan, plan, sizeof(MsBatch) * nplan, hipMemcpyHostToDevice, st)) != hipSuccess) return e;
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
   MsArgs a = ms_args(g, ms, dsrcs, dplan, nplan, policy, eta, seed, levels16, nullptr, nullptr, nullptr, nullptr, 0);
+  // no staging buffer here (the entry point allocates nothing): Stage 2
+  // writes the caller's rows directly
+  a.lstage = nullptr;
   const unsigned shmem = policy == BLEST_POLICY_LEARNED ? kLdsMlpFloats * sizeof(float) : 0u;
   void* args[] = {static_cast<void*>(&a)};
   return hipLaunchCooperativeKernel(ms_kernel(g), dim3(ms->grid), dim3(ms->block), args, shmem, st);
