@@ -296,8 +296,12 @@ __device__ __forceinline__ unsigned long long readlane64(unsigned long long x, i
 // subset i of bits 0..3, hi[i] the same for bits 4..7, so a slice's
 // neighbour word for w is lo[mask & 15] | hi[mask >> 4] (two LDS reads, where
 // the bit loop took up to eight dependent ones). Then, two words at a time
-// (one 16-byte load per vertex), the visited words of all the lane's K
-// slices are loaded at once before any is used. LDS layout per wave: F at [b * W + w], tables at
+// (one 16-byte load per vertex), the visited and next words of all the lane's
+// K slices are loaded at once before any is used, and an atomic OR is issued
+// only for bits in neither: the next words only grow during Stage 1 (Stage 2
+// cleared them before the barrier), so a bit seen set needs no OR, and a
+// stale read only costs an OR that changes nothing. On this GPU the
+// device-scope ORs, performed at the memory side, are what bounds the step. LDS layout per wave: F at [b * W + w], tables at
 // [8 W + (h * 16 + i) * W + w].
 // (Not inlined: it gets its own register allocation instead of adding to the
 // persistent kernel's; its pointers are converted to the global address space.)
@@ -360,11 +364,15 @@ __device__ __attribute__((noinline)) void ms_engine_bvss8(const MsArgs& a, const
         unsigned long long mw[K], v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) mw[k] = m8[k] ? (tab[m8[k] & 15u] | tab[16u + (m8[k] >> 4)]) : 0ULL;
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = mw[k] ? V[vi[k]] : ~0ULL;
+        unsigned long long nx[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const unsigned long long m = mw[k] & ~v[k];
+          v[k] = mw[k] ? V[vi[k]] : ~0ULL;
+          nx[k] = mw[k] ? N[vi[k]] : 0ULL;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const unsigned long long m = mw[k] & ~v[k] & ~nx[k];
           if (m) {
             __hip_atomic_fetch_or(&N[vi[k]], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             any[k] = true;
@@ -377,18 +385,21 @@ __device__ __attribute__((noinline)) void ms_engine_bvss8(const MsArgs& a, const
       for (int w = 0; w < W; w += 2) {
         if (!(readlane64(aw, w) | readlane64(aw, w + 1))) continue;
         unsigned long long m0[K], m1[K];
-        u64x2 v[K];
+        u64x2 v[K], nx[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           m0[k] = m8[k] ? (tab[(m8[k] & 15u) * W + w] | tab[(16u + (m8[k] >> 4)) * W + w]) : 0ULL;
           m1[k] = m8[k] ? (tab[(m8[k] & 15u) * W + w + 1] | tab[(16u + (m8[k] >> 4)) * W + w + 1]) : 0ULL;
         }
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-          v[k] = (m0[k] | m1[k]) ? *(gptr<const u64x2>)(V + vi[k] * W + w) : u64x2{~0ULL, ~0ULL};
+        for (int k = 0; k < K; ++k) {
+          const bool need = (m0[k] | m1[k]) != 0ULL;
+          v[k] = need ? *(gptr<const u64x2>)(V + vi[k] * W + w) : u64x2{~0ULL, ~0ULL};
+          nx[k] = need ? *(gptr<const u64x2>)(N + vi[k] * W + w) : u64x2{0ULL, 0ULL};
+        }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const unsigned long long x0 = m0[k] & ~v[k].x, x1 = m1[k] & ~v[k].y;
+          const unsigned long long x0 = m0[k] & ~v[k].x & ~nx[k].x, x1 = m1[k] & ~v[k].y & ~nx[k].y;
           if (x0) __hip_atomic_fetch_or(&N[vi[k] * W + w], x0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (x1) __hip_atomic_fetch_or(&N[vi[k] * W + w + 1], x1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           any[k] = any[k] || (x0 | x1) != 0ULL;
