@@ -18,7 +18,7 @@ struct MsDev {
   int64_t nsets = 0;
   unsigned long long* F = nullptr;   // frontier words, getVI-ordered, W per vertex
   unsigned long long* V = nullptr;   // visited words
-  unsigned long long* N = nullptr;   // next marks (atomic OR targets)
+  unsigned long long* N = nullptr;   // next words: visited bits plus this level's marks (atomic OR targets)
   unsigned long long* act = nullptr; // per slice set: sources active in it
   // int16 level output: a batch's levels are first written by internal id
   // (lstage[i * 64 W + c], the row of vertex i) and copied to the caller's

@@ -296,12 +296,13 @@ __device__ __forceinline__ unsigned long long readlane64(unsigned long long x, i
 // subset i of bits 0..3, hi[i] the same for bits 4..7, so a slice's
 // neighbour word for w is lo[mask & 15] | hi[mask >> 4] (two LDS reads, where
 // the bit loop took up to eight dependent ones). Then, two words at a time
-// (one 16-byte load per vertex), the visited and next words of all the lane's
-// K slices are loaded at once before any is used, and an atomic OR is issued
-// only for bits in neither: the next words only grow during Stage 1 (Stage 2
-// cleared them before the barrier), so a bit seen set needs no OR, and a
-// stale read only costs an OR that changes nothing. On this GPU the
-// device-scope ORs, performed at the memory side, are what bounds the step. LDS layout per wave: F at [b * W + w], tables at
+// (one 16-byte load per vertex), the next words of all the lane's K slices
+// are loaded at once before any is used, and an atomic OR is issued only for
+// bits not yet in them. As in Alg. 5's V_next, a next word holds the visited
+// bits plus this level's marks, so this one load filters both; it only grows
+// during Stage 1, so a bit seen set needs no OR, and a stale read only costs
+// an OR that changes nothing. On this GPU the device-scope ORs, performed at
+// the memory side, are what bounds the step. LDS layout per wave: F at [b * W + w], tables at
 // [8 W + (h * 16 + i) * W + w].
 // (Not inlined: it gets its own register allocation instead of adding to the
 // persistent kernel's; its pointers are converted to the global address space.)
@@ -313,7 +314,6 @@ __device__ __attribute__((noinline)) void ms_engine_bvss8(const MsArgs& a, const
   const gptr<const SliceT> sl = to_global(static_cast<const SliceT*>(a.slices));
   const gptr<const uint4> q = to_global(q_in);
   const gptr<const unsigned long long> F = to_global(static_cast<const unsigned long long*>(a.F));
-  const gptr<const unsigned long long> V = to_global(static_cast<const unsigned long long*>(a.V));
   const gptr<const unsigned long long> act = to_global(static_cast<const unsigned long long*>(a.act));
   const gptr<unsigned long long> N = to_global(a.N);
   const gptr<uint8_t> dirty = to_global(a.dirty);
@@ -364,15 +364,11 @@ __device__ __attribute__((noinline)) void ms_engine_bvss8(const MsArgs& a, const
         unsigned long long mw[K], v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) mw[k] = m8[k] ? (tab[m8[k] & 15u] | tab[16u + (m8[k] >> 4)]) : 0ULL;
-        unsigned long long nx[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = mw[k] ? N[vi[k]] : ~0ULL;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          v[k] = mw[k] ? V[vi[k]] : ~0ULL;
-          nx[k] = mw[k] ? N[vi[k]] : 0ULL;
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const unsigned long long m = mw[k] & ~v[k] & ~nx[k];
+          const unsigned long long m = mw[k] & ~v[k];
           if (m) {
             __hip_atomic_fetch_or(&N[vi[k]], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             any[k] = true;
@@ -381,25 +377,22 @@ __device__ __attribute__((noinline)) void ms_engine_bvss8(const MsArgs& a, const
       }
     } else {
       // W is even: words w and w + 1 of a vertex are one aligned 16-byte
-      // load (V is 16-byte aligned and vi * W + w is even)
+      // load (N is 16-byte aligned and vi * W + w is even)
       for (int w = 0; w < W; w += 2) {
         if (!(readlane64(aw, w) | readlane64(aw, w + 1))) continue;
         unsigned long long m0[K], m1[K];
-        u64x2 v[K], nx[K];
+        u64x2 v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           m0[k] = m8[k] ? (tab[(m8[k] & 15u) * W + w] | tab[(16u + (m8[k] >> 4)) * W + w]) : 0ULL;
           m1[k] = m8[k] ? (tab[(m8[k] & 15u) * W + w + 1] | tab[(16u + (m8[k] >> 4)) * W + w + 1]) : 0ULL;
         }
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const bool need = (m0[k] | m1[k]) != 0ULL;
-          v[k] = need ? *(gptr<const u64x2>)(V + vi[k] * W + w) : u64x2{~0ULL, ~0ULL};
-          nx[k] = need ? *(gptr<const u64x2>)(N + vi[k] * W + w) : u64x2{0ULL, 0ULL};
-        }
+        for (int k = 0; k < K; ++k)
+          v[k] = (m0[k] | m1[k]) ? *(gptr<const u64x2>)(N + vi[k] * W + w) : u64x2{~0ULL, ~0ULL};
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const unsigned long long x0 = m0[k] & ~v[k].x & ~nx[k].x, x1 = m1[k] & ~v[k].y & ~nx[k].y;
+          const unsigned long long x0 = m0[k] & ~v[k].x, x1 = m1[k] & ~v[k].y;
           if (x0) __hip_atomic_fetch_or(&N[vi[k] * W + w], x0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (x1) __hip_atomic_fetch_or(&N[vi[k] * W + w + 1], x1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           any[k] = any[k] || (x0 | x1) != 0ULL;
@@ -546,11 +539,12 @@ __device__ void ms_engine_pull(const MsArgs& a, int W, int count, const unsigned
     const int p0 = a.rp_in[u], p1 = a.rp_in[u + 1];
     if (p0 == p1) continue;
     const long long vi = ms_vi<ABL>(a, u, rho, SIGMA);
-    unsigned long long unv[kWMax], acc[kWMax];
+    unsigned long long vis[kWMax], unv[kWMax], acc[kWMax];
     bool open = false;
 #pragma unroll
     for (int w = 0; w < kWMax; ++w) {
-      unv[w] = (w < W) ? (~a.V[vi * W + w] & bm[w]) : 0ULL;
+      vis[w] = (w < W) ? a.V[vi * W + w] : ~0ULL;
+      unv[w] = ~vis[w] & bm[w];
       acc[w] = 0ULL;
       open |= unv[w] != 0ULL;
     }
@@ -572,7 +566,7 @@ __device__ void ms_engine_pull(const MsArgs& a, int W, int count, const unsigned
     for (int w = 0; w < kWMax; ++w) {
       const unsigned long long x = acc[w] & unv[w];
       if (w < W && x) {
-        a.N[vi * W + w] = x;
+        a.N[vi * W + w] = vis[w] | x;  // N = visited words plus this level's marks
         any = true;
       }
     }
@@ -672,13 +666,14 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
             dw[b] = 0ULL;
             if (mine) {
               const long long idx = ms_vi<ABL>(a, s * SIGMA + b, rho, SIGMA) * W + w;
+              // N holds the visited words plus this level's marks (Alg. 5's
+              // V_next); the new bits are its difference from V
               const unsigned long long nx = a.N[idx];
               unsigned long long dd = 0ULL;
               if (nx) {
-                a.N[idx] = 0ULL;
                 const unsigned long long old = a.V[idx];
                 dd = nx & ~old;
-                if (dd) a.V[idx] = old | dd;
+                if (dd) a.V[idx] = nx;
               }
               a.F[idx] = dd;
               dw[b] = dd;
@@ -853,6 +848,7 @@ __global__ void __launch_bounds__(BLOCK) k_ms_persistent(MsArgs a) {
     for (long long i = gtid; i < nhat * W; i += nthreads) {
       a.F[i] = 0ULL;
       a.V[i] = 0ULL;
+      a.N[i] = 0ULL;
     }
     if (a.levels16 && !a.lstage) fill_minus_one(a.levels16 + static_cast<long long>(bt.offset) * a.n,
                                                 static_cast<long long>(bt.count) * a.n, gtid, nthreads);
@@ -999,6 +995,7 @@ __global__ void __launch_bounds__(BLOCK) k_ms_phase(MsArgs a, int parity) {
         for (long long i = gtid; i < nhat * W; i += nthreads) {
           a.F[i] = 0ULL;
           a.V[i] = 0ULL;
+          a.N[i] = 0ULL;
         }
         if (a.levels16 && !a.lstage) fill_minus_one(a.levels16 + static_cast<long long>(bt.offset) * a.n,
                                                     static_cast<long long>(bt.count) * a.n, gtid, nthreads);
