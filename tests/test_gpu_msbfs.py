@@ -73,6 +73,26 @@ def test_msbfs_structured(blest, name):
         g.close()
 
 
+def test_msbfs_staging_grows_with_the_batch_width(blest):
+    """The int16 levels go through a staging row per vertex that is sized for
+    the widest batch seen so far: calls with growing and shrinking widths on a
+    relabelled graph, with engines mixed per level, closeness in between (no
+    levels), all equal the oracle."""
+    rp, col = inputs.rmat_graph(13, 63)
+    srcs = inputs.sources(rp, 700, seed=64)
+    ref = oracle.msbfs16(rp, col, srcs)
+    osum, oreach, _ = oracle.closeness(rp, col, srcs[:300])
+    g = blest.Graph(rp, col)
+    assert g.info()["reordered"] != 0
+    for widths, pol in [([64], "BVSS"), ([512], "RANDOM"), ([128, 256], "BOTTOM_UP"), ([64, 512], "HEURISTIC")]:
+        g.set_policy(getattr(blest.Policy, pol), 10.0, 5)
+        got = g.msbfs_batched(srcs, widths).cpu().numpy()
+        assert np.array_equal(got, ref), (widths, pol)
+        s, r, _ = g.closeness(srcs[:300])
+        assert np.array_equal(s.cpu().numpy(), osum) and np.array_equal(r.cpu().numpy(), oreach), (widths, pol)
+    g.close()
+
+
 def test_msbfs_overflow_and_errors(blest):
     rp, col = H.path(33000)
     g = blest.Graph(rp, col)
