@@ -549,13 +549,22 @@ __device__ void ms_engine_pull(const MsArgs& a, int W, int count, const unsigned
       open |= unv[w] != 0ULL;
     }
     if (!open) continue;
-    for (int p = p0; p < p1; ++p) {
-      const long long iv = ms_vi<ABL>(a, a.col_in[p], rho, SIGMA);
+    // Four in-neighbours at a time: their column indices and frontier words
+    // are loaded before any is tested (the test may end the scan, so one at a
+    // time every load waited for the previous one); up to three loads past
+    // the covering neighbour are wasted.
+    for (int p = p0; p < p1; p += 4) {
+      long long iv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) iv[j] = p + j < p1 ? ms_vi<ABL>(a, a.col_in[p + j], rho, SIGMA) : -1;
       bool covered = true;
 #pragma unroll
       for (int w = 0; w < kWMax; ++w) {
         if (w < W && unv[w]) {
-          acc[w] |= a.F[iv * W + w];
+          unsigned long long f[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) f[j] = iv[j] >= 0 ? a.F[iv[j] * W + w] : 0ULL;
+          acc[w] |= f[0] | f[1] | f[2] | f[3];
           covered &= (acc[w] & unv[w]) == unv[w];
         }
       }
