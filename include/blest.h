@@ -181,8 +181,11 @@ blest_status blest_bfs_probe(blest_graph* g, int32_t src, int32_t* levels_dev, v
 /* Multi-source BFS (Alg. 5): levels_dev[c*n + v] = d(srcs_host[c], v) as int16,
  * -1 if unreachable, source-major, input vertex ids. levels_dev: int16[k*n].
  * Sources may repeat; k = 0 is a no-op. Batches of opts.msbfs_width sources.
+ * The graph keeps, from the first call on, a staging buffer of
+ * n * (widest batch) int16 (plus an int32[n] id map for a relabelled graph)
+ * through which each batch's levels reach levels_dev; blest_free releases it.
  * Errors: OUT_OF_RANGE, OVERFLOW (a distance > 32767; levels then unspecified),
- * INVALID_ARG, TIMEOUT, HIP. */
+ * INVALID_ARG, TIMEOUT, OOM, HIP. */
 blest_status blest_msbfs(blest_graph* g, const int32_t* srcs_host, int32_t k, int16_t* levels_dev, void* stream);
 
 /* blest_msbfs for callers that cannot allocate device memory (code under HIP
