@@ -670,21 +670,26 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
         for (int w = 0; w < W; ++w) {
           unsigned long long dw[SIGMA];
           unsigned long long Aw = 0ULL;
+          // N holds the visited words plus this level's marks (Alg. 5's
+          // V_next); the new bits are its difference from V. All the set's
+          // N and V words for word w are loaded before any store (the stores
+          // below would otherwise order each vertex's loads after the
+          // previous vertex's stores).
+          long long idx[SIGMA];
+          unsigned long long nx[SIGMA], old[SIGMA];
+#pragma unroll
+          for (int b = 0; b < SIGMA; ++b) {
+            idx[b] = ms_vi<ABL>(a, s * SIGMA + b, rho, SIGMA) * W + w;
+            nx[b] = mine ? a.N[idx[b]] : 0ULL;
+            old[b] = mine ? a.V[idx[b]] : 0ULL;
+          }
 #pragma unroll
           for (int b = 0; b < SIGMA; ++b) {
             dw[b] = 0ULL;
             if (mine) {
-              const long long idx = ms_vi<ABL>(a, s * SIGMA + b, rho, SIGMA) * W + w;
-              // N holds the visited words plus this level's marks (Alg. 5's
-              // V_next); the new bits are its difference from V
-              const unsigned long long nx = a.N[idx];
-              unsigned long long dd = 0ULL;
-              if (nx) {
-                const unsigned long long old = a.V[idx];
-                dd = nx & ~old;
-                if (dd) a.V[idx] = nx;
-              }
-              a.F[idx] = dd;
+              const unsigned long long dd = nx[b] & ~old[b];
+              if (dd) a.V[idx[b]] = nx[b];
+              a.F[idx[b]] = dd;
               dw[b] = dd;
               Aw |= dd;
               far_cnt[b] += __popcll(dd);
