@@ -700,20 +700,24 @@ __device__ void ms_finalize(const MsArgs& a, const MsBatch& bt, int new_level, i
           if (Aw & ~lds_live[w])
             __hip_atomic_fetch_or(&lds_live[w], Aw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           // int16 levels. Staged: each new (vertex, traversal) pair goes to
-          // the vertex's staging row; the set's sigma rows are contiguous, so
-          // these stores stay within a few lines. Direct (no staging buffer):
-          // for each traversal c with new vertices in this set, the set's
-          // vertices in c's output row (scattered when relabelled).
-          if (a.lstage && Aw && !overflow) {
+          // the vertex's staging row. The wave writes them together: for each
+          // of its lanes' sets with new bits (lane l holds set s - lane + l),
+          // lane c stores traversal 64 w + c of each of the set's vertices,
+          // so one store covers 128 contiguous bytes of a row. Direct (no
+          // staging buffer): for each traversal c with new vertices in this
+          // set, the set's vertices in c's output row (scattered when
+          // relabelled).
+          if (a.lstage && !overflow) {
             const long long K = 64LL * W;
+            unsigned long long todo = __ballot(Aw != 0ULL);
+            while (todo) {
+              const int l = __builtin_ctzll(todo);
+              todo &= todo - 1;
+              int16_t* rows = a.lstage + (s - lane + l) * SIGMA * K + 64 * w + lane;
 #pragma unroll
-            for (int b = 0; b < SIGMA; ++b) {
-              unsigned long long t = dw[b];
-              int16_t* row = a.lstage + (s * SIGMA + b) * K + 64 * w;
-              while (t) {
-                const int c = __builtin_ctzll(t);
-                t &= t - 1;
-                row[c] = static_cast<int16_t>(new_level);
+              for (int b = 0; b < SIGMA; ++b) {
+                const unsigned long long d = readlane64(dw[b], l);
+                if ((d >> lane) & 1ULL) rows[b * K] = static_cast<int16_t>(new_level);
               }
             }
           } else if (a.levels16 && Aw && !overflow) {
