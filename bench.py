@@ -384,8 +384,8 @@ def main():
                     help="only a short run of one workload plus a calibration copy, for rocprofv3")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is not built "
-                                   "(see DESIGN.md, 'How the path would shard')", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the path is built for one GPU, "
+                                   "multi-GPU sharding (by source batches or by rows) is not", "n_gpus": args.gpus}))
         sys.exit(2)
 
     if args.profile_leg:
