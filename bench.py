@@ -139,7 +139,7 @@ def host_description():
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
         avail = nproc
-    # the GPU machine grants one GPU's share of its host (16 threads), whatever nproc shows
+    # at most 16 threads (one GPU's share of a shared host), fewer if OMP_NUM_THREADS or the affinity mask says so
     threads = max(1, min(avail, int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16))
     smt = None
     try:
