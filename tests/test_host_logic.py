@@ -140,3 +140,24 @@ def test_bench_algorithmic_bytes_counts_by_hand():
     fin1 = 3 * n // 8 + 4 * 12 + 4 * 2
     assert got == init_out_ids + step0 + fin0 + step1 + fin1
     assert bench.algorithmic_bytes(stats, n, sigma, 4, deg, levels, relabelled=False) == got - 4 * n
+
+
+def test_bench_multi_source_bytes_counts_by_hand():
+    """The multi-source lower bound bench.py reports, summed by hand from the
+    per-unit counts in its docstring for two level records of different widths."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    n, sigma, k = 16, 8, 100
+    recs = [
+        {"width": 64, "queue": 2, "queue_slices": 10, "new_pairs": 40},
+        {"width": 512, "queue": 1, "queue_slices": 3, "new_pairs": 16},
+    ]
+    got = bench.ms_algorithmic_bytes(recs, n, 2, sigma, 4, k)
+    fill = 2 * k * n                              # every (source, vertex) level written once
+    lvl_a = (4 + 1) * 10 + 8 * 8 * 2              # slice word + mask byte per slice; 8 words x 8 B staged per VSS
+    lvl_a += 40 // 8 + 3 * 40 // 8 + 2 * 40       # next-word flush, Stage 2 words, int16 level per new pair
+    lvl_b = (4 + 1) * 3 + 8 * 64 * 1              # 512 traversals: 64 B of frontier words per vertex
+    lvl_b += 16 // 8 + 3 * 16 // 8 + 2 * 16
+    assert got == fill + lvl_a + lvl_b
